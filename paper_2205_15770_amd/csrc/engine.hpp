@@ -1,0 +1,95 @@
+// Host-side solver engine: level hierarchy, set-up (Algorithm 2), smoother
+// (inexact symmetric Uzawa, Sec. 1 / Sec. 3.3.1), multigrid cycle
+// (Algorithm 1), outer FGMRES and the stationary protocol (Sec. 4.1).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "../../include/smg.h"
+#include "fe1d.hpp"
+
+namespace smg {
+
+struct Error {
+  smg_status code;
+  std::string msg;
+};
+
+#define SMG_HIP(call)                                                                     \
+  do {                                                                                    \
+    hipError_t e_ = (call);                                                               \
+    if (e_ != hipSuccess)                                                                 \
+      throw ::smg::Error{SMG_EDEVICE, std::string(#call) + ": " + hipGetErrorString(e_)}; \
+  } while (0)
+
+// Per-precision workspace of one level.
+template <typename T>
+struct Work {
+  T *x = nullptr, *b = nullptr, *r = nullptr;        // level iterate / rhs / residual (length N)
+  T *ru = nullptr, *uhat = nullptr, *q = nullptr, *w = nullptr;  // velocity (d Nv)
+  T *cr = nullptr, *cx = nullptr, *cd[2] = {nullptr, nullptr};  // Chebyshev state, A
+  T *rp = nullptr, *dp = nullptr;                     // pressure (Np)
+  T *sr = nullptr, *sx = nullptr, *sd[2] = {nullptr, nullptr};  // Chebyshev state, S~
+  T *t1 = nullptr, *t2 = nullptr;                     // transfer intermediates (length N)
+  T *dinvA = nullptr, *dinvS = nullptr;               // inverse diagonals
+  T *mu_cell = nullptr;                               // per-cell viscosity (optional)
+};
+
+struct LevelInfo {
+  int n[3] = {1, 1, 1};
+  int vd[3] = {1, 1, 1}, pd[3] = {1, 1, 1};
+  int64_t Nv = 0, Np = 0, Nu = 0, N = 0;
+  double h[3] = {1, 1, 1};
+  double beta_A = 0, beta_S = 0;
+  double *DA = nullptr, *DS = nullptr;  // FP64 diagonals
+  double *mp1 = nullptr;                // M_p 1 (pressure mean weights)
+  Work<double> w64;
+  Work<float> w32;
+};
+
+class EngineBase {
+ public:
+  virtual ~EngineBase() {}
+  smg_desc desc;
+  std::vector<LevelInfo> lv;
+  hipStream_t stream = nullptr;
+  int L = 0;  // finest level index
+
+  virtual void setup() = 0;
+  virtual void vmult(int l, int dt, const void *x, void *y) = 0;
+  virtual void residual(int l, int dt, const void *x, const void *b, void *r) = 0;
+  virtual void apply_block(int l, int dt, int blk, const void *x, void *y) = 0;
+  virtual void chebyshev(int l, int dt, int which, const void *r, void *out) = 0;
+  virtual void smooth(int l, int dt, void *x, const void *b, int steps) = 0;
+  virtual void restrict_(int lf, int dt, const void *rf, void *rc) = 0;
+  virtual void prolongate_add(int lf, int dt, const void *wc, void *xf) = 0;
+  virtual void coarse_solve(int dt, const void *b0, void *x0) = 0;
+  virtual void vcycle(int l, int dt, void *x, const void *b) = 0;
+  virtual smg_status solve(double *x, const double *b, double rtol, int maxit, smg_solve_info *info) = 0;
+  virtual smg_status solve_stationary(double *x, const double *b, double rtol, int maxit, smg_solve_info *info) = 0;
+  virtual void node_coordinates(int l, double *xyz) = 0;
+
+  std::vector<void *> allocations;
+  template <typename T>
+  T *dalloc(int64_t n) {
+    void *p = nullptr;
+    if (n <= 0) n = 1;
+    hipError_t e = hipMalloc(&p, sizeof(T) * (size_t)n);
+    if (e != hipSuccess) throw Error{SMG_ENOMEM, std::string("hipMalloc failed: ") + hipGetErrorString(e)};
+    allocations.push_back(p);
+    return (T *)p;
+  }
+  void free_all() {
+    for (void *p : allocations) (void)hipFree(p);
+    allocations.clear();
+  }
+};
+
+EngineBase *make_engine(const smg_desc &d);
+
+}  // namespace smg

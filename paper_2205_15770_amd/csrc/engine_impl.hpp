@@ -1,0 +1,934 @@
+// Solver engine for one (dimension, degree) pair; instantiated per pair in
+// its own translation unit.
+#pragma once
+#include <algorithm>
+#include <chrono>
+#include <cstdio>
+
+#include "cell_kernel.hpp"
+#include "engine.hpp"
+#include "ops.hpp"
+#include "setup_kernels.hpp"
+#include "vec_kernels.hpp"
+
+namespace smg {
+
+// Lanczos (Algorithm 2 asks for a close approximation of lambda_max): steps,
+// safety factor and SplitMix64 seeds of the start vectors.
+constexpr int LANCZOS_STEPS = 30;
+constexpr double LANCZOS_SAFETY = 1.02;
+constexpr uint64_t LANCZOS_SEED_A = 1234, LANCZOS_SEED_S = 4321;
+
+// SplitMix64 (Steele, Lea, Flood 2014) as a counter-based generator: output i
+// (i = 1, 2, ...) mixes seed + i * 0x9E3779B97F4A7C15.  Mapped to [-1, 1) from
+// the top 53 bits.
+inline double splitmix64_uniform(uint64_t seed, uint64_t i) {
+  uint64_t z = seed + i * 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  z = z ^ (z >> 31);
+  return 2.0 * ((double)(z >> 11) / 9007199254740992.0) - 1.0;
+}
+
+// C_{k+1}(3) / (1 + C_{k+1}(3)) of Lemma 1 / Algorithm 2, C_n(3) by the
+// Chebyshev three-term recurrence C_{n+1} = 6 C_n - C_{n-1}.
+inline double cheb_scaling(int k) {
+  double c0 = 1.0, c1 = 3.0;
+  for (int n = 1; n < k + 1; ++n) {
+    double c2 = 6.0 * c1 - c0;
+    c0 = c1;
+    c1 = c2;
+  }
+  return c1 / (1.0 + c1);
+}
+
+template <int DIM, int K>
+class EngineT : public EngineBase {
+ public:
+  // one cell per thread; (T-1)^d owned cells plus one low halo layer per tile
+  static constexpr int TX = DIM == 2 ? 16 : (K == 2 ? 4 : 3);
+  static constexpr int TY = TX;
+  static constexpr int TZ = DIM == 2 ? 1 : TX;
+  static constexpr int OWN = TX - 1;
+
+  Ref1D ref;
+  TransferTables ttab;
+  double *Kinv = nullptr;
+  int n0 = 0;
+  double sigma = 0, tau = 0;
+  // FGMRES storage
+  int restart = 30;
+  double *V = nullptr, *Z = nullptr, *partial = nullptr, *dvec = nullptr;
+  float *b32 = nullptr, *x32 = nullptr;
+  double *lz[4] = {nullptr, nullptr, nullptr, nullptr};  // Lanczos temporaries
+  double mp1_sum = 0;
+
+  // ---------------------------------------------------------------- helpers
+  template <typename T>
+  Work<T> &work(int l) {
+    if constexpr (std::is_same<T, double>::value) return lv[l].w64;
+    else return lv[l].w32;
+  }
+
+  template <typename T>
+  LevelGeom<T, DIM, K> geom(int l, bool unit_cp = false) {
+    const LevelInfo &I = lv[l];
+    LevelGeom<T, DIM, K> g;
+    std::memset(&g, 0, sizeof(g));
+    for (int a = 0; a < 3; ++a) {
+      g.n[a] = I.n[a];
+      g.vd[a] = I.vd[a];
+      g.pd[a] = I.pd[a];
+      g.tiles[a] = (a < DIM) ? (I.n[a] + OWN - 1) / OWN : 1;
+    }
+    g.Nv = I.Nv;
+    g.Np = I.Np;
+    g.mu = (T)desc.mu;
+    g.gr = (T)(desc.gamma * desc.rho);
+    g.cp = (T)(unit_cp ? 1.0 : desc.c_pressure);
+    g.mu_cell = work<T>(l).mu_cell;
+    const int nv = K + 1, np = K;
+    for (int a = 0; a < DIM; ++a) {
+      const double h = I.h[a];
+      for (int i = 0; i < nv; ++i)
+        for (int j = 0; j < nv; ++j) {
+          g.c[a].Kv[i][j] = (T)(ref.Kv[i * nv + j] / h);
+          g.c[a].Mv[i][j] = (T)(ref.Mv[i * nv + j] * h);
+        }
+      for (int i = 0; i < np; ++i) {
+        for (int j = 0; j < nv; ++j) {
+          g.c[a].G[i][j] = (T)(ref.G[i * nv + j]);
+          g.c[a].N[i][j] = (T)(ref.N[i * nv + j] * h);
+        }
+        for (int j = 0; j < np; ++j) g.c[a].Mp[i][j] = (T)(ref.Mp[i * np + j] * h);
+      }
+    }
+    return g;
+  }
+
+  void check_launch() { SMG_HIP(hipGetLastError()); }
+
+  template <typename T, int BLK, class Op>
+  void tile(const LevelGeom<T, DIM, K> &g, const Op &op) {
+    const unsigned nblk = (unsigned)(g.tiles[0] * g.tiles[1] * g.tiles[2]);
+    hipLaunchKernelGGL((tile_apply_kernel<DIM, K, T, BLK, Op, TX, TY, TZ>), dim3(nblk), dim3(TX * TY * TZ), 0, stream, g, op);
+    check_launch();
+  }
+
+  bool has_c() const { return desc.c_pressure != 0.0; }
+
+  template <typename T>
+  void vset(T *y, T v, int64_t n) {
+    hipLaunchKernelGGL((k_set<T>), dim3(grid_for(n)), dim3(VB), 0, stream, y, v, (i64)n);
+    check_launch();
+  }
+
+  // ---------------------------------------------------------------- blocks
+  template <typename T>
+  void vmult_t(int l, const T *x, T *y) {
+    auto g = geom<T>(l);
+    OpApply<T> op{x, x + lv[l].Nu, y, y + lv[l].Nu};
+    if (has_c()) tile<T, BLK_A | BLK_BT | BLK_B | BLK_C>(g, op);
+    else tile<T, BLK_A | BLK_BT | BLK_B>(g, op);
+  }
+
+  template <typename T>
+  void residual_t(int l, const T *x, const T *b, T *r) {
+    auto g = geom<T>(l);
+    const int64_t nu = lv[l].Nu;
+    OpResidual<T> op{x, x + nu, b, b + nu, r, r + nu};
+    if (has_c()) tile<T, BLK_A | BLK_BT | BLK_B | BLK_C>(g, op);
+    else tile<T, BLK_A | BLK_BT | BLK_B>(g, op);
+  }
+
+  template <typename T>
+  void block_t(int l, int blk, const T *x, T *y) {
+    auto g = geom<T>(l);
+    switch (blk) {
+      case SMG_BLOCK_K: vmult_t<T>(l, x, y); break;
+      case SMG_BLOCK_A: tile<T, BLK_A>(g, OpApply<T>{x, nullptr, y, nullptr}); break;
+      case SMG_BLOCK_BT: tile<T, BLK_BT>(g, OpApply<T>{nullptr, x, y, nullptr}); break;
+      case SMG_BLOCK_B: tile<T, BLK_B>(g, OpApply<T>{x, nullptr, nullptr, y}); break;
+      case SMG_BLOCK_MASS: {
+        auto gm = g;
+        tile<T, BLK_MASS>(gm, OpMass<T>{x, y});
+        break;
+      }
+      default: throw Error{SMG_EINVAL, "unknown block"};
+    }
+  }
+
+  // --------------------------------------------------------- Chebyshev (A)
+  // out = base + s * Cheb(A, D_A, k_A) r   (Sec. 3.3.1; three-term recurrence)
+  template <typename T>
+  void cheb_A(int l, const T *r, const T *base, T *out, double s) {
+    Work<T> &W = work<T>(l);
+    const int64_t nu = lv[l].Nu;
+    const double beta = lv[l].beta_A, theta = 0.75 * beta, delta = 0.25 * beta, s1 = theta / delta;
+    const int k = desc.cheb_deg_A;
+    if (k == 0) {
+      hipLaunchKernelGGL((k_jacobi<T>), dim3(grid_for(nu)), dim3(VB), 0, stream, out, base, (T)(s / theta), W.dinvA, r, (i64)nu);
+      check_launch();
+      return;
+    }
+    auto g = geom<T>(l);
+    double rho = 1.0 / s1;
+    for (int i = 0; i < k; ++i) {
+      const double rn = 1.0 / (2.0 * s1 - rho);
+      OpChebA<T, true, true> o;  // field holder; copied into the right instantiation below
+      std::memset(&o, 0, sizeof(o));
+      o.rin = (i == 0) ? r : W.cr;
+      o.dinv = W.dinvA;
+      o.d = W.cd[i % 2];
+      o.x = W.cx;
+      o.r_out = W.cr;
+      o.x_out = W.cx;
+      o.d_out = W.cd[(i + 1) % 2];
+      o.base = base;
+      o.out = out;
+      o.inv_theta = (T)(1.0 / theta);
+      o.c1 = (T)(rn * rho);
+      o.c2 = (T)(2.0 * rn / delta);
+      o.s = (T)s;
+      const bool first = i == 0, last = i == k - 1;
+      if (first && last) tile<T, BLK_A>(g, cast_op<OpChebA<T, true, true>>(o));
+      else if (first) tile<T, BLK_A>(g, cast_op<OpChebA<T, true, false>>(o));
+      else if (last) tile<T, BLK_A>(g, cast_op<OpChebA<T, false, true>>(o));
+      else tile<T, BLK_A>(g, cast_op<OpChebA<T, false, false>>(o));
+      rho = rn;
+    }
+  }
+
+  template <class To, class From>
+  static To cast_op(const From &f) {
+    static_assert(sizeof(To) == sizeof(From), "op layout");
+    To t;
+    std::memcpy(&t, &f, sizeof(To));
+    return t;
+  }
+
+  // ------------------------------------------------------- Chebyshev (S~)
+  // dp = tau * Cheb(S~, D~_S, k_S) rp, and p += dp when p != nullptr.
+  template <typename T>
+  void cheb_S(int l, const T *rp, T *dp, T *p) {
+    Work<T> &W = work<T>(l);
+    const int64_t np = lv[l].Np;
+    const double beta = lv[l].beta_S, theta = 0.75 * beta, delta = 0.25 * beta, s1 = theta / delta;
+    const int k = desc.cheb_deg_S;
+    if (k == 0) {
+      if (p)
+        hipLaunchKernelGGL((k_jacobi_update<T>), dim3(grid_for(np)), dim3(VB), 0, stream, p, dp, (T)(tau / theta), W.dinvS, rp, (i64)np);
+      else
+        hipLaunchKernelGGL((k_jacobi<T>), dim3(grid_for(np)), dim3(VB), 0, stream, dp, (const T *)nullptr, (T)(tau / theta), W.dinvS, rp, (i64)np);
+      check_launch();
+      return;
+    }
+    auto g = geom<T>(l);
+    double rho = 1.0 / s1;
+    for (int i = 0; i < k; ++i) {
+      const double rn = 1.0 / (2.0 * s1 - rho);
+      const bool first = i == 0, last = i == k - 1;
+      // q = B^T d_i
+      if (first) tile<T, BLK_BT>(g, OpGrad<T, true>{rp, W.dinvS, nullptr, (T)(1.0 / theta), W.q});
+      else tile<T, BLK_BT>(g, OpGrad<T, false>{nullptr, nullptr, W.sd[i % 2], (T)0, W.q});
+      // w = A_hat^-1 q
+      cheb_A<T>(l, W.q, nullptr, W.w, sigma);
+      // t = B w + C d_i and the recurrence
+      OpChebS<T, true, true> o;
+      std::memset(&o, 0, sizeof(o));
+      o.w = W.w;
+      o.rin = first ? rp : W.sr;
+      o.dinv_s = W.dinvS;
+      o.d = W.sd[i % 2];
+      o.x = W.sx;
+      o.r_out = W.sr;
+      o.x_out = W.sx;
+      o.d_out = W.sd[(i + 1) % 2];
+      o.p = p;
+      o.dp = dp;
+      o.inv_theta = (T)(1.0 / theta);
+      o.c1 = (T)(rn * rho);
+      o.c2 = (T)(2.0 * rn / delta);
+      o.tau = (T)tau;
+      if (first && last) div_cheb<T>(g, cast_op<OpChebS<T, true, true>>(o));
+      else if (first) div_cheb<T>(g, cast_op<OpChebS<T, true, false>>(o));
+      else if (last) div_cheb<T>(g, cast_op<OpChebS<T, false, true>>(o));
+      else div_cheb<T>(g, cast_op<OpChebS<T, false, false>>(o));
+      rho = rn;
+    }
+  }
+
+  template <typename T, class Op>
+  void div_cheb(const LevelGeom<T, DIM, K> &g, const Op &op) {
+    if (has_c()) tile<T, BLK_B | BLK_C | BLK_CPLUS>(g, op);
+    else tile<T, BLK_B>(g, op);
+  }
+
+  // out = S~ d = B A_hat^-1 B^T d + C d
+  template <typename T>
+  void S_tilde(int l, const T *d, T *out) {
+    Work<T> &W = work<T>(l);
+    auto g = geom<T>(l);
+    tile<T, BLK_BT>(g, OpGrad<T, false>{nullptr, nullptr, d, (T)0, W.q});
+    cheb_A<T>(l, W.q, nullptr, W.w, sigma);
+    OpApply<T> op{W.w, d, nullptr, out};
+    if (has_c()) tile<T, BLK_B | BLK_C | BLK_CPLUS>(g, op);
+    else tile<T, BLK_B>(g, op);
+  }
+
+  // ------------------------------------------------------ Uzawa smoother
+  // One inexact symmetric Uzawa step in the form consistent with the compact
+  // form x <- x + K_hat^-1 (b - K x) of Sec. 3.3.1:
+  //   u_hat = u + A_hat^-1 (f - A u - B^T p)
+  //   dp    = S_hat^-1 (B u_hat - C p - g),   p <- p + dp
+  //   u     = u_hat - A_hat^-1 B^T dp
+  template <typename T>
+  void uzawa_step(int l, T *x, const T *b, bool zero_init) {
+    Work<T> &W = work<T>(l);
+    const int64_t nu = lv[l].Nu;
+    T *u = x, *p = x + nu;
+    const T *f = b, *gp = b + nu;
+    auto g = geom<T>(l);
+    const T *ru = f;
+    if (!zero_init) {
+      OpResidual<T> op{u, p, f, nullptr, W.ru, nullptr};
+      tile<T, BLK_A | BLK_BT>(g, op);
+      ru = W.ru;
+    }
+    cheb_A<T>(l, ru, zero_init ? nullptr : u, W.uhat, sigma);
+    OpDivResidual<T> od{W.uhat, p, gp, W.rp};
+    if (has_c()) tile<T, BLK_B | BLK_C>(g, od);
+    else tile<T, BLK_B>(g, od);
+    cheb_S<T>(l, W.rp, W.dp, p);
+    tile<T, BLK_BT>(g, OpGrad<T, false>{nullptr, nullptr, W.dp, (T)0, W.q});
+    cheb_A<T>(l, W.q, W.uhat, u, -sigma);
+  }
+
+  template <typename T>
+  void smooth_t(int l, T *x, const T *b, int steps, bool zero_init) {
+    for (int s = 0; s < steps; ++s) uzawa_step<T>(l, x, b, zero_init && s == 0);
+  }
+
+  // ------------------------------------------------------------ transfers
+  TransferField tfield(int lf, bool velocity) {
+    TransferField F;
+    std::memset(&F, 0, sizeof(F));
+    const LevelInfo &f = lv[lf], &c = lv[lf - 1];
+    F.deg = velocity ? K : K - 1;
+    for (int a = 0; a < 3; ++a) {
+      F.cdim[a] = velocity ? c.vd[a] : c.pd[a];
+      F.fdim[a] = velocity ? f.vd[a] : f.pd[a];
+      F.ncell_f[a] = f.n[a];
+    }
+    F.coff = velocity ? 0 : c.Nu;
+    F.foff = velocity ? 0 : f.Nu;
+    F.ncomp = velocity ? DIM : 1;
+    F.cstride = velocity ? c.Nv : 0;
+    F.fstride = velocity ? f.Nv : 0;
+    F.bc = velocity ? 1 : 0;
+    return F;
+  }
+
+  template <typename T>
+  void prolongate_t(int lf, const T *wc, T *xf) {
+    TransferField fv = tfield(lf, true), fp = tfield(lf, false);
+    const i64 nfv = lv[lf].Nv, nfp = lv[lf].Np;
+    const i64 total = nfv * DIM + nfp;
+    hipLaunchKernelGGL((k_prolongate_add<T, DIM>), dim3(grid_for(total)), dim3(VB), 0, stream, wc, xf, fv, fp, ttab, nfv, nfp);
+    check_launch();
+  }
+
+  template <typename T>
+  void restrict_t(int lf, const T *rf, T *rc) {
+    Work<T> &W = work<T>(lf);
+    for (int field = 0; field < 2; ++field) {
+      const bool vel = field == 0;
+      TransferField F = tfield(lf, vel);
+      int dims[3] = {F.fdim[0], F.fdim[1], F.fdim[2]};
+      const T *in = rf;
+      i64 in_off = F.foff, in_cs = vel ? F.fstride : 0;
+      for (int dir = 0; dir < DIM; ++dir) {
+        int od[3] = {dims[0], dims[1], dims[2]};
+        od[dir] = F.cdim[dir];
+        const bool lastp = dir == DIM - 1;
+        T *out = lastp ? rc : (dir % 2 == 0 ? W.t1 : W.t2);
+        const i64 per = (i64)od[0] * od[1] * od[2];
+        const i64 out_off = lastp ? F.coff : 0;
+        const i64 out_cs = lastp ? (vel ? F.cstride : 0) : per;
+        hipLaunchKernelGGL((k_restrict_pass<T>), dim3(grid_for(per * F.ncomp)), dim3(VB), 0, stream,
+                           in, out, dir, F.deg, F.ncell_f[dir], dims[0], dims[1], dims[2], od[0], od[1], od[2],
+                           F.ncomp, in_cs, out_cs, in_off, out_off, ttab, field, (int)(dir == 0 && F.bc),
+                           (int)(lastp && F.bc), F.fdim[0], F.fdim[1], F.fdim[2], F.cdim[0], F.cdim[1], F.cdim[2], DIM);
+        check_launch();
+        in = out;
+        in_off = out_off;
+        in_cs = out_cs;
+        for (int a = 0; a < 3; ++a) dims[a] = od[a];
+      }
+    }
+  }
+
+  // --------------------------------------------------------- coarse solve
+  template <typename T>
+  void coarse_t(const T *b0, T *x0) {
+    const unsigned nb = (unsigned)((n0 + (VB / 64) - 1) / (VB / 64));
+    hipLaunchKernelGGL((k_coarse_gemv<T>), dim3(nb), dim3(VB), 0, stream, Kinv, (i64)(n0 + 1), n0, b0, x0);
+    check_launch();
+  }
+
+  // ---------------------------------------------------------- the cycle
+  // Algorithm 1 with cycle index desc.cycle_index; level 0 is the direct solve.
+  template <typename T>
+  void cycle_t(int l, T *x, const T *b, bool zero_init) {
+    if (l == 0) {
+      coarse_t<T>(b, x);
+      return;
+    }
+    Work<T> &W = work<T>(l);
+    Work<T> &C = work<T>(l - 1);
+    smooth_t<T>(l, x, b, desc.smooth_steps, zero_init);
+    residual_t<T>(l, x, b, W.r);
+    restrict_t<T>(l, W.r, C.b);
+    vset<T>(C.x, (T)0, lv[l - 1].N);
+    for (int j = 0; j < desc.cycle_index; ++j) cycle_t<T>(l - 1, C.x, C.b, j == 0);
+    prolongate_t<T>(l, C.x, x);
+    smooth_t<T>(l, x, b, desc.smooth_steps, false);
+  }
+
+  // ---------------------------------------------------------- reductions
+  // dvec[0..nv) = V_j . w (V_j = V + j * ldv), FP64, deterministic.
+  void multidot(const double *Vb, int64_t ldv, int nv, const double *w, int64_t n, double *outdev) {
+    hipLaunchKernelGGL((k_multidot_partial<double>), dim3(RB), dim3(VB), 0, stream, Vb, (i64)ldv, nv, w, (i64)n, partial);
+    check_launch();
+    hipLaunchKernelGGL(k_partial_finish, dim3((nv + 63) / 64), dim3(64), 0, stream, partial, RB, nv, outdev);
+    check_launch();
+  }
+  double dot(const double *a, const double *b, int64_t n) {
+    multidot(a, 0, 1, b, n, dvec);
+    double h = 0;
+    SMG_HIP(hipMemcpyAsync(&h, dvec, sizeof(double), hipMemcpyDeviceToHost, stream));
+    SMG_HIP(hipStreamSynchronize(stream));
+    return h;
+  }
+  double norm(const double *a, int64_t n) { return std::sqrt(dot(a, a, n)); }
+
+  void remove_pressure_mean(double *x) {
+    const LevelInfo &I = lv[L];
+    multidot(I.mp1, 0, 1, x + I.Nu, I.Np, dvec);
+    hipLaunchKernelGGL(k_subtract_scalar, dim3(grid_for(I.Np)), dim3(VB), 0, stream, x + I.Nu, (const double *)dvec, mp1_sum, (i64)I.Np);
+    check_launch();
+  }
+
+  // ------------------------------------------------------------- set-up
+  double lanczos(int l, int which) {
+    const LevelInfo &I = lv[l];
+    const int64_t n = which == 0 ? I.Nu : I.Np;
+    const double *D = which == 0 ? I.DA : I.DS;
+    const uint64_t seed = which == 0 ? LANCZOS_SEED_A : LANCZOS_SEED_S;
+    std::vector<double> v0(n);
+    for (int64_t i = 0; i < n; ++i) v0[i] = splitmix64_uniform(seed, (uint64_t)i + 1);
+    if (which == 0) {
+      // start in the free (unconstrained) velocity subspace
+      for (int c = 0; c < DIM; ++c)
+        for (int64_t node = 0; node < I.Nv; ++node) {
+          int64_t r = node;
+          bool bc = false;
+          for (int a = 0; a < DIM; ++a) {
+            int ia = (int)(r % I.vd[a]);
+            r /= I.vd[a];
+            bc |= (ia == 0 || ia == I.vd[a] - 1);
+          }
+          if (bc) v0[c * I.Nv + node] = 0.0;
+        }
+    }
+    double *q = lz[0], *qp = lz[1], *w = lz[2], *t = lz[3];
+    SMG_HIP(hipMemcpyAsync(q, v0.data(), n * sizeof(double), hipMemcpyHostToDevice, stream));
+    vset<double>(qp, 0.0, n);
+    auto Dmul = [&](double *y, const double *x) {  // y = D x
+      hipLaunchKernelGGL((k_jacobi<double>), dim3(grid_for(n)), dim3(VB), 0, stream, y, (const double *)nullptr, 1.0, D, x, (i64)n);
+      check_launch();
+    };
+    Dmul(t, q);
+    const double nq = std::sqrt(dot(q, t, n));
+    std::vector<double> qs(n);
+    // q /= ||q||_D  (host round trip keeps this set-up code simple)
+    SMG_HIP(hipMemcpyAsync(qs.data(), q, n * sizeof(double), hipMemcpyDeviceToHost, stream));
+    SMG_HIP(hipStreamSynchronize(stream));
+    for (auto &v : qs) v /= nq;
+    SMG_HIP(hipMemcpyAsync(q, qs.data(), n * sizeof(double), hipMemcpyHostToDevice, stream));
+    std::vector<double> al, be;
+    double bprev = 0.0;
+    const double *dinv = which == 0 ? lv[l].w64.dinvA : lv[l].w64.dinvS;
+    for (int j = 0; j < LANCZOS_STEPS && j < n; ++j) {
+      // t = M q
+      if (which == 0) {
+        auto g = geom<double>(l);
+        tile<double, BLK_A>(g, OpApply<double>{q, nullptr, t, nullptr});
+      } else {
+        S_tilde<double>(l, q, t);
+      }
+      const double a = dot(q, t, n);
+      // w = D^-1 t - a q - bprev qp
+      hipLaunchKernelGGL((k_jacobi<double>), dim3(grid_for(n)), dim3(VB), 0, stream, w, (const double *)nullptr, 1.0, dinv, t, (i64)n);
+      check_launch();
+      hipLaunchKernelGGL((k_axpy<double>), dim3(grid_for(n)), dim3(VB), 0, stream, w, -a, (const double *)q, (i64)n);
+      check_launch();
+      hipLaunchKernelGGL((k_axpy<double>), dim3(grid_for(n)), dim3(VB), 0, stream, w, -bprev, (const double *)qp, (i64)n);
+      check_launch();
+      al.push_back(a);
+      Dmul(t, w);
+      const double b = std::sqrt(std::max(dot(w, t, n), 0.0));
+      if (!(b > 1e-14 * std::fabs(a))) break;
+      be.push_back(b);
+      // qp = q; q = w / b
+      hipLaunchKernelGGL((k_copy<double, double>), dim3(grid_for(n)), dim3(VB), 0, stream, qp, (const double *)q, (i64)n);
+      check_launch();
+      hipLaunchKernelGGL((k_jacobi<double>), dim3(grid_for(n)), dim3(VB), 0, stream, q, (const double *)nullptr, 1.0 / b, unit_vec(n), w, (i64)n);
+      check_launch();
+      bprev = b;
+    }
+    return LANCZOS_SAFETY * tridiag_max_eig(al, be);
+  }
+
+  double *ones = nullptr;
+  int64_t ones_n = 0;
+  const double *unit_vec(int64_t n) {
+    if (ones_n < n) throw Error{SMG_EINVAL, "internal: ones vector too short"};
+    return ones;
+  }
+
+  // largest eigenvalue of the symmetric tridiagonal (alpha, beta) by bisection
+  // on the Sturm sequence count.
+  static double tridiag_max_eig(const std::vector<double> &a, const std::vector<double> &b) {
+    const int m = (int)a.size();
+    double lo = 1e300, hi = -1e300;
+    for (int i = 0; i < m; ++i) {
+      double r = (i > 0 ? std::fabs(b[i - 1]) : 0.0) + (i < m - 1 ? std::fabs(b[i]) : 0.0);
+      lo = std::min(lo, a[i] - r);
+      hi = std::max(hi, a[i] + r);
+    }
+    auto count_below = [&](double x) {  // number of eigenvalues < x
+      int cnt = 0;
+      double d = 1.0;
+      for (int i = 0; i < m; ++i) {
+        d = a[i] - x - (i > 0 ? b[i - 1] * b[i - 1] / d : 0.0);
+        if (d == 0.0) d = -1e-300;
+        if (d < 0) ++cnt;
+      }
+      return cnt;
+    };
+    for (int it = 0; it < 200; ++it) {
+      const double mid = 0.5 * (lo + hi);
+      if (count_below(mid) >= m) hi = mid;
+      else lo = mid;
+      if (hi - lo <= 1e-15 * std::max(1.0, std::fabs(hi))) break;
+    }
+    return hi;
+  }
+
+  void build_coarse() {
+    const LevelInfo &I = lv[0];
+    n0 = (int)I.N;
+    double *e = dalloc<double>(n0);
+    double *cols = dalloc<double>((int64_t)n0 * n0);
+    for (int j = 0; j < n0; ++j) {
+      vset<double>(e, 0.0, n0);
+      const double one = 1.0;
+      SMG_HIP(hipMemcpyAsync(e + j, &one, sizeof(double), hipMemcpyHostToDevice, stream));
+      vmult_t<double>(0, e, cols + (int64_t)j * n0);
+    }
+    std::vector<double> Kc((size_t)n0 * n0), m(n0, 0.0);
+    SMG_HIP(hipMemcpyAsync(Kc.data(), cols, sizeof(double) * Kc.size(), hipMemcpyDeviceToHost, stream));
+    SMG_HIP(hipMemcpyAsync(m.data() + I.Nu, I.mp1, sizeof(double) * I.Np, hipMemcpyDeviceToHost, stream));
+    SMG_HIP(hipStreamSynchronize(stream));
+    const int nb = n0 + 1;
+    std::vector<double> A((size_t)nb * nb, 0.0), Inv((size_t)nb * nb, 0.0);
+    for (int i = 0; i < n0; ++i)
+      for (int j = 0; j < n0; ++j) A[(size_t)i * nb + j] = Kc[(size_t)j * n0 + i];  // column j = K e_j
+    for (int i = 0; i < n0; ++i) {
+      A[(size_t)i * nb + n0] = m[i];
+      A[(size_t)n0 * nb + i] = m[i];
+    }
+    for (int i = 0; i < nb; ++i) Inv[(size_t)i * nb + i] = 1.0;
+    // Gauss-Jordan elimination with partial pivoting
+    for (int c = 0; c < nb; ++c) {
+      int piv = c;
+      for (int r = c + 1; r < nb; ++r)
+        if (std::fabs(A[(size_t)r * nb + c]) > std::fabs(A[(size_t)piv * nb + c])) piv = r;
+      if (A[(size_t)piv * nb + c] == 0.0) throw Error{SMG_EINVAL, "singular coarse matrix"};
+      if (piv != c)
+        for (int j = 0; j < nb; ++j) {
+          std::swap(A[(size_t)c * nb + j], A[(size_t)piv * nb + j]);
+          std::swap(Inv[(size_t)c * nb + j], Inv[(size_t)piv * nb + j]);
+        }
+      const double d = 1.0 / A[(size_t)c * nb + c];
+      for (int j = 0; j < nb; ++j) {
+        A[(size_t)c * nb + j] *= d;
+        Inv[(size_t)c * nb + j] *= d;
+      }
+      for (int r = 0; r < nb; ++r) {
+        if (r == c) continue;
+        const double f = A[(size_t)r * nb + c];
+        if (f == 0.0) continue;
+        for (int j = 0; j < nb; ++j) {
+          A[(size_t)r * nb + j] -= f * A[(size_t)c * nb + j];
+          Inv[(size_t)r * nb + j] -= f * Inv[(size_t)c * nb + j];
+        }
+      }
+    }
+    Kinv = dalloc<double>((int64_t)nb * nb);
+    SMG_HIP(hipMemcpyAsync(Kinv, Inv.data(), sizeof(double) * Inv.size(), hipMemcpyHostToDevice, stream));
+    SMG_HIP(hipStreamSynchronize(stream));
+  }
+
+  template <typename T>
+  void alloc_work(int l) {
+    LevelInfo &I = lv[l];
+    Work<T> &W = work<T>(l);
+    W.x = dalloc<T>(I.N);
+    W.b = dalloc<T>(I.N);
+    W.r = dalloc<T>(I.N);
+    W.ru = dalloc<T>(I.Nu);
+    W.uhat = dalloc<T>(I.Nu);
+    W.q = dalloc<T>(I.Nu);
+    W.w = dalloc<T>(I.Nu);
+    W.cr = dalloc<T>(I.Nu);
+    W.cx = dalloc<T>(I.Nu);
+    W.cd[0] = dalloc<T>(I.Nu);
+    W.cd[1] = dalloc<T>(I.Nu);
+    W.rp = dalloc<T>(I.Np);
+    W.dp = dalloc<T>(I.Np);
+    W.sr = dalloc<T>(I.Np);
+    W.sx = dalloc<T>(I.Np);
+    W.sd[0] = dalloc<T>(I.Np);
+    W.sd[1] = dalloc<T>(I.Np);
+    W.t1 = dalloc<T>(I.N);
+    W.t2 = dalloc<T>(I.N);
+    W.dinvA = dalloc<T>(I.Nu);
+    W.dinvS = dalloc<T>(I.Np);
+    hipLaunchKernelGGL((k_reciprocal<T>), dim3(grid_for(I.Nu)), dim3(VB), 0, stream, W.dinvA, (const double *)I.DA, (i64)I.Nu);
+    check_launch();
+    hipLaunchKernelGGL((k_reciprocal<T>), dim3(grid_for(I.Np)), dim3(VB), 0, stream, W.dinvS, (const double *)I.DS, (i64)I.Np);
+    check_launch();
+  }
+
+  void setup() override {
+    ref = make_ref1d(K);
+    sigma = cheb_scaling(desc.cheb_deg_A);
+    tau = cheb_scaling(desc.cheb_deg_S);
+    std::memset(&ttab, 0, sizeof(ttab));
+    {
+      std::vector<double> Wv = prolongation_weights(ref.zv), Wp = prolongation_weights(ref.zp);
+      std::copy(Wv.begin(), Wv.end(), ttab.W[0]);
+      std::copy(Wp.begin(), Wp.end(), ttab.W[1]);
+    }
+    stream = (hipStream_t)desc.stream;
+    L = desc.n_levels - 1;
+    lv.resize(desc.n_levels);
+    for (int l = 0; l <= L; ++l) {
+      LevelInfo &I = lv[l];
+      I.Nv = 1;
+      I.Np = 1;
+      for (int a = 0; a < 3; ++a) {
+        if (a < DIM) {
+          I.n[a] = desc.n_coarse[a] << l;
+          I.vd[a] = K * I.n[a] + 1;
+          I.pd[a] = (K - 1) * I.n[a] + 1;
+          I.h[a] = (desc.box_hi[a] - desc.box_lo[a]) / I.n[a];
+        } else {
+          I.n[a] = 1;
+          I.vd[a] = 1;
+          I.pd[a] = 1;
+          I.h[a] = 1.0;
+        }
+        I.Nv *= I.vd[a];
+        I.Np *= I.pd[a];
+      }
+      I.Nu = DIM * I.Nv;
+      I.N = I.Nu + I.Np;
+    }
+    // per-cell viscosity: finest as given, coarser levels by averaging children
+    if (desc.mu_cell) {
+      std::vector<std::vector<double>> mu(desc.n_levels);
+      const LevelInfo &F = lv[L];
+      const int64_t ncf = (int64_t)F.n[0] * F.n[1] * F.n[2];
+      mu[L].assign(desc.mu_cell, desc.mu_cell + ncf);
+      for (int l = L - 1; l >= 0; --l) {
+        const LevelInfo &I = lv[l], &J = lv[l + 1];
+        mu[l].assign((size_t)I.n[0] * I.n[1] * I.n[2], 0.0);
+        const double wgt = 1.0 / (1 << DIM);
+        for (int cz = 0; cz < I.n[2]; ++cz)
+          for (int cy = 0; cy < I.n[1]; ++cy)
+            for (int cx = 0; cx < I.n[0]; ++cx) {
+              double s = 0.0;
+              for (int dz = 0; dz < (DIM == 3 ? 2 : 1); ++dz)
+                for (int dy = 0; dy < 2; ++dy)
+                  for (int dx = 0; dx < 2; ++dx)
+                    s += mu[l + 1][(2 * cx + dx) + (int64_t)J.n[0] * ((2 * cy + dy) + (int64_t)J.n[1] * (DIM == 3 ? 2 * cz + dz : 0))];
+              mu[l][cx + (int64_t)I.n[0] * (cy + (int64_t)I.n[1] * cz)] = s * wgt;
+            }
+      }
+      for (int l = 0; l <= L; ++l) {
+        const int64_t nc = (int64_t)mu[l].size();
+        lv[l].w64.mu_cell = dalloc<double>(nc);
+        lv[l].w32.mu_cell = dalloc<float>(nc);
+        SMG_HIP(hipMemcpyAsync(lv[l].w64.mu_cell, mu[l].data(), nc * sizeof(double), hipMemcpyHostToDevice, stream));
+        hipLaunchKernelGGL((k_copy<float, double>), dim3(grid_for(nc)), dim3(VB), 0, stream, lv[l].w32.mu_cell, (const double *)lv[l].w64.mu_cell, (i64)nc);
+        check_launch();
+      }
+    }
+    int64_t nmax = 0;
+    for (int l = 0; l <= L; ++l) nmax = std::max(nmax, lv[l].N);
+    ones = dalloc<double>(nmax);
+    ones_n = nmax;
+    vset<double>(ones, 1.0, nmax);
+    for (int i = 0; i < 4; ++i) lz[i] = dalloc<double>(nmax);
+    partial = dalloc<double>((int64_t)RB * 256);
+    dvec = dalloc<double>(256);
+    // diagonals and M_p 1 on every level
+    for (int l = 0; l <= L; ++l) {
+      LevelInfo &I = lv[l];
+      I.DA = dalloc<double>(I.Nu);
+      I.DS = dalloc<double>(I.Np);
+      I.mp1 = dalloc<double>(I.Np);
+      auto g = geom<double>(l);
+      hipLaunchKernelGGL((k_diag_A<DIM, K>), dim3(grid_for(I.Nv)), dim3(VB), 0, stream, g, I.DA);
+      check_launch();
+      const int kind = desc.schur_diag == SMG_SCHUR_D ? 0 : (desc.schur_diag == SMG_SCHUR_LOC ? 1 : 2);
+      hipLaunchKernelGGL((k_diag_S<DIM, K>), dim3(grid_for(I.Np)), dim3(VB), 0, stream, g, kind, (const double *)I.DA, I.DS);
+      check_launch();
+      auto gu = geom<double>(l, true);
+      tile<double, BLK_C | BLK_CPLUS>(gu, OpApply<double>{nullptr, ones, nullptr, I.mp1});
+      alloc_work<double>(l);
+      alloc_work<float>(l);
+    }
+    {
+      std::vector<double> h(lv[L].Np);
+      SMG_HIP(hipMemcpyAsync(h.data(), lv[L].mp1, h.size() * sizeof(double), hipMemcpyDeviceToHost, stream));
+      SMG_HIP(hipStreamSynchronize(stream));
+      mp1_sum = 0;
+      for (double v : h) mp1_sum += v;
+    }
+    // Chebyshev intervals (Algorithm 2); level 0 is solved directly
+    for (int l = 1; l <= L; ++l) {
+      lv[l].beta_A = lanczos(l, 0);
+      lv[l].beta_S = lanczos(l, 1);
+    }
+    build_coarse();
+    // FGMRES storage
+    restart = desc.fgmres_restart;
+    V = dalloc<double>((int64_t)(restart + 1) * lv[L].N);
+    Z = dalloc<double>((int64_t)restart * lv[L].N);
+    b32 = dalloc<float>(lv[L].N);
+    x32 = dalloc<float>(lv[L].N);
+    SMG_HIP(hipStreamSynchronize(stream));
+  }
+
+  // -------------------------------------------------------- public (dt)
+#define SMG_DISPATCH(dt, call_f64, call_f32) \
+  do {                                        \
+    if ((dt) == SMG_F64) { call_f64; }        \
+    else { call_f32; }                        \
+  } while (0)
+
+  void vmult(int l, int dt, const void *x, void *y) override {
+    SMG_DISPATCH(dt, vmult_t<double>(l, (const double *)x, (double *)y), vmult_t<float>(l, (const float *)x, (float *)y));
+  }
+  void residual(int l, int dt, const void *x, const void *b, void *r) override {
+    SMG_DISPATCH(dt, residual_t<double>(l, (const double *)x, (const double *)b, (double *)r),
+                 residual_t<float>(l, (const float *)x, (const float *)b, (float *)r));
+  }
+  void apply_block(int l, int dt, int blk, const void *x, void *y) override {
+    SMG_DISPATCH(dt, block_t<double>(l, blk, (const double *)x, (double *)y), block_t<float>(l, blk, (const float *)x, (float *)y));
+  }
+  void chebyshev(int l, int dt, int which, const void *r, void *out) override {
+    if (which == 0)
+      SMG_DISPATCH(dt, cheb_A<double>(l, (const double *)r, nullptr, (double *)out, sigma),
+                   cheb_A<float>(l, (const float *)r, nullptr, (float *)out, sigma));
+    else
+      SMG_DISPATCH(dt, cheb_S<double>(l, (const double *)r, (double *)out, nullptr),
+                   cheb_S<float>(l, (const float *)r, (float *)out, nullptr));
+  }
+  void smooth(int l, int dt, void *x, const void *b, int steps) override {
+    SMG_DISPATCH(dt, smooth_t<double>(l, (double *)x, (const double *)b, steps, false),
+                 smooth_t<float>(l, (float *)x, (const float *)b, steps, false));
+  }
+  void restrict_(int lf, int dt, const void *rf, void *rc) override {
+    SMG_DISPATCH(dt, restrict_t<double>(lf, (const double *)rf, (double *)rc), restrict_t<float>(lf, (const float *)rf, (float *)rc));
+  }
+  void prolongate_add(int lf, int dt, const void *wc, void *xf) override {
+    SMG_DISPATCH(dt, prolongate_t<double>(lf, (const double *)wc, (double *)xf), prolongate_t<float>(lf, (const float *)wc, (float *)xf));
+  }
+  void coarse_solve(int dt, const void *b0, void *x0) override {
+    SMG_DISPATCH(dt, coarse_t<double>((const double *)b0, (double *)x0), coarse_t<float>((const float *)b0, (float *)x0));
+  }
+  void vcycle(int l, int dt, void *x, const void *b) override {
+    SMG_DISPATCH(dt, cycle_t<double>(l, (double *)x, (const double *)b, false), cycle_t<float>(l, (float *)x, (const float *)b, false));
+  }
+
+  // z = M^-1 v: one cycle from zero, in the precision of the descriptor
+  void precondition(const double *v, double *z) {
+    const int64_t N = lv[L].N;
+    if (desc.precision == SMG_PRECOND_F64) {
+      vset<double>(z, 0.0, N);
+      cycle_t<double>(L, z, v, true);
+    } else {
+      hipLaunchKernelGGL((k_copy<float, double>), dim3(grid_for(N)), dim3(VB), 0, stream, b32, v, (i64)N);
+      check_launch();
+      vset<float>(x32, 0.0f, N);
+      cycle_t<float>(L, x32, b32, true);
+      hipLaunchKernelGGL((k_copy<double, float>), dim3(grid_for(N)), dim3(VB), 0, stream, z, (const float *)x32, (i64)N);
+      check_launch();
+    }
+  }
+
+  static bool finite(double v) { return std::isfinite(v); }
+
+  smg_status solve(double *x, const double *b, double rtol, int maxit, smg_solve_info *info) override {
+    auto t0 = std::chrono::steady_clock::now();
+    const int64_t N = lv[L].N;
+    const int m = restart;
+    const double bnorm = norm(b, N);
+    int hist_len = 0;
+    auto record = [&](double v) {
+      if (info && info->history && hist_len < info->history_capacity) info->history[hist_len] = v;
+      ++hist_len;
+    };
+    smg_status st = SMG_OK;
+    int it = 0;
+    double rel = 0.0;
+    if (bnorm == 0.0) {
+      vset<double>(x, 0.0, N);
+      record(0.0);
+    } else {
+      residual_t<double>(L, x, b, V);
+      double beta = norm(V, N);
+      rel = beta / bnorm;
+      record(rel);
+      std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), gv(m + 1), y(m), h(m + 1);
+      while (it < maxit && rel > rtol) {
+        hipLaunchKernelGGL((k_jacobi<double>), dim3(grid_for(N)), dim3(VB), 0, stream, V, (const double *)nullptr, 1.0 / beta, unit_vec(N), (const double *)V, (i64)N);
+        check_launch();
+        std::fill(gv.begin(), gv.end(), 0.0);
+        std::fill(H.begin(), H.end(), 0.0);
+        gv[0] = beta;
+        int jdone = 0;
+        bool broke = false;
+        for (int j = 0; j < m; ++j) {
+          double *vj = V + (int64_t)j * N, *zj = Z + (int64_t)j * N, *w = V + (int64_t)(j + 1) * N;
+          precondition(vj, zj);
+          vmult_t<double>(L, zj, w);
+          // classical Gram-Schmidt, twice
+          for (int pass = 0; pass < 2; ++pass) {
+            multidot(V, N, j + 1, w, N, dvec);
+            hipLaunchKernelGGL((k_multi_axpy<double>), dim3(grid_for(N)), dim3(VB), 0, stream, w, (const double *)V, (i64)N, j + 1, (const double *)dvec, -1.0, (i64)N);
+            check_launch();
+            SMG_HIP(hipMemcpyAsync(h.data(), dvec, sizeof(double) * (j + 1), hipMemcpyDeviceToHost, stream));
+            SMG_HIP(hipStreamSynchronize(stream));
+            for (int i = 0; i <= j; ++i) H[(size_t)i * m + j] += h[i];
+          }
+          const double hn = norm(w, N);
+          H[(size_t)(j + 1) * m + j] = hn;
+          if (!finite(hn)) { broke = true; break; }
+          if (hn > 0)
+            hipLaunchKernelGGL((k_jacobi<double>), dim3(grid_for(N)), dim3(VB), 0, stream, w, (const double *)nullptr, 1.0 / hn, unit_vec(N), (const double *)w, (i64)N);
+          check_launch();
+          for (int i = 0; i < j; ++i) {
+            const double t = cs[i] * H[(size_t)i * m + j] + sn[i] * H[(size_t)(i + 1) * m + j];
+            H[(size_t)(i + 1) * m + j] = -sn[i] * H[(size_t)i * m + j] + cs[i] * H[(size_t)(i + 1) * m + j];
+            H[(size_t)i * m + j] = t;
+          }
+          const double den = std::hypot(H[(size_t)j * m + j], H[(size_t)(j + 1) * m + j]);
+          cs[j] = H[(size_t)j * m + j] / den;
+          sn[j] = H[(size_t)(j + 1) * m + j] / den;
+          H[(size_t)j * m + j] = den;
+          H[(size_t)(j + 1) * m + j] = 0.0;
+          gv[j + 1] = -sn[j] * gv[j];
+          gv[j] = cs[j] * gv[j];
+          ++it;
+          jdone = j + 1;
+          rel = std::fabs(gv[j + 1]) / bnorm;
+          if (!finite(rel)) { broke = true; break; }
+          record(rel);
+          if (rel <= rtol || it >= maxit) break;
+        }
+        if (broke) { st = SMG_EBREAKDOWN; break; }
+        for (int i = jdone - 1; i >= 0; --i) {
+          double s = gv[i];
+          for (int c = i + 1; c < jdone; ++c) s -= H[(size_t)i * m + c] * y[c];
+          y[i] = s / H[(size_t)i * m + i];
+        }
+        SMG_HIP(hipMemcpyAsync(dvec, y.data(), sizeof(double) * jdone, hipMemcpyHostToDevice, stream));
+        hipLaunchKernelGGL((k_multi_axpy<double>), dim3(grid_for(N)), dim3(VB), 0, stream, x, (const double *)Z, (i64)N, jdone, (const double *)dvec, 1.0, (i64)N);
+        check_launch();
+        residual_t<double>(L, x, b, V);
+        beta = norm(V, N);
+        rel = beta / bnorm;
+        if (!finite(rel)) { st = SMG_EBREAKDOWN; break; }
+        if (hist_len > 0 && info && info->history && hist_len - 1 < info->history_capacity) info->history[hist_len - 1] = rel;
+      }
+      if (st == SMG_OK && rel > rtol) st = SMG_ENOTCONV;
+    }
+    remove_pressure_mean(x);
+    SMG_HIP(hipStreamSynchronize(stream));
+    if (info) {
+      info->iterations = it;
+      info->rel_residual = rel;
+      info->rate_q = 0.0;
+      info->history_len = std::min(hist_len, info->history_capacity);
+      info->t_solve_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    }
+    return st;
+  }
+
+  smg_status solve_stationary(double *x, const double *b, double rtol, int maxit, smg_solve_info *info) override {
+    auto t0 = std::chrono::steady_clock::now();
+    const int64_t N = lv[L].N;
+    double *r = lv[L].w64.r;
+    residual_t<double>(L, x, b, r);
+    const double r0 = norm(r, N);
+    std::vector<double> hist{r0};
+    smg_status st = SMG_OK;
+    int it = 0;
+    while (it < maxit && hist.back() > rtol * r0) {
+      cycle_t<double>(L, x, b, false);
+      residual_t<double>(L, x, b, r);
+      const double rn = norm(r, N);
+      ++it;
+      hist.push_back(rn);
+      if (!finite(rn) || rn > 1e3 * r0) { st = SMG_EBREAKDOWN; break; }
+    }
+    if (st == SMG_OK && hist.back() > rtol * r0) st = SMG_ENOTCONV;
+    remove_pressure_mean(x);
+    SMG_HIP(hipStreamSynchronize(stream));
+    if (info) {
+      info->iterations = it;
+      info->rel_residual = r0 > 0 ? hist.back() / r0 : 0.0;
+      const int j = (int)hist.size() - 1, s = std::min(3, j);
+      info->rate_q = (j > 0 && hist[j - s] > 0) ? std::pow(hist[j] / hist[j - s], 1.0 / s) : 0.0;
+      int n = 0;
+      for (size_t i = 0; i < hist.size(); ++i)
+        if (info->history && (int)i < info->history_capacity) { info->history[i] = r0 > 0 ? hist[i] / r0 : 0.0; ++n; }
+      info->history_len = n;
+      info->t_solve_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    }
+    return st;
+  }
+
+  void node_coordinates(int l, double *xyz) override {
+    const LevelInfo &I = lv[l];
+    for (int64_t node = 0; node < I.Nv; ++node) {
+      int64_t r = node;
+      for (int a = 0; a < DIM; ++a) {
+        const int i = (int)(r % I.vd[a]);
+        r /= I.vd[a];
+        int c = i / K;
+        if (c > I.n[a] - 1) c = I.n[a] - 1;
+        const double t = ref.zv[i - c * K];
+        xyz[node * DIM + a] = desc.box_lo[a] + I.h[a] * (c + t);
+      }
+    }
+  }
+};
+
+}  // namespace smg

@@ -1,0 +1,351 @@
+// C ABI of the multigrid library (declarations and contracts in include/smg.h).
+#include <cmath>
+#include <cstring>
+#include <string>
+
+#include "engine.hpp"
+
+namespace smg {
+EngineBase *make_engine_2_2();
+EngineBase *make_engine_2_3();
+EngineBase *make_engine_3_2();
+EngineBase *make_engine_3_3();
+}  // namespace smg
+
+struct smg_ctx {
+  smg::EngineBase *eng = nullptr;
+  int device = 0;
+};
+
+namespace {
+
+thread_local std::string g_last_error;
+
+smg_status fail(smg_status code, const std::string &msg) {
+  g_last_error = msg;
+  return code;
+}
+
+#define SMG_TRY(body)                                              \
+  try {                                                            \
+    body;                                                          \
+    g_last_error.clear();                                          \
+    return SMG_OK;                                                 \
+  } catch (const smg::Error &e) {                                  \
+    return fail(e.code, e.msg);                                    \
+  } catch (const std::exception &e) {                              \
+    return fail(SMG_EDEVICE, std::string("exception: ") + e.what()); \
+  }
+
+smg_status check_ctx(const smg_ctx *ctx) {
+  if (!ctx || !ctx->eng) return fail(SMG_EINVAL, "null context");
+  return SMG_OK;
+}
+
+smg_status check_level(const smg_ctx *ctx, int level, int min_level = 0) {
+  smg_status s = check_ctx(ctx);
+  if (s != SMG_OK) return s;
+  if (level < min_level || level > ctx->eng->L)
+    return fail(SMG_EINVAL, "level " + std::to_string(level) + " out of range [" + std::to_string(min_level) + ", " +
+                                std::to_string(ctx->eng->L) + "]");
+  return SMG_OK;
+}
+
+smg_status check_dtype(int dt) {
+  if (dt != SMG_F64 && dt != SMG_F32) return fail(SMG_EINVAL, "dtype must be SMG_F64 (0) or SMG_F32 (1)");
+  return SMG_OK;
+}
+
+smg_status check_ptrs(std::initializer_list<const void *> ps) {
+  for (const void *p : ps)
+    if (!p) return fail(SMG_EINVAL, "null vector pointer");
+  return SMG_OK;
+}
+
+smg_status validate(const smg_desc *d) {
+  if (!d) return fail(SMG_EINVAL, "null descriptor");
+  if (d->dim != 2 && d->dim != 3) return fail(SMG_EINVAL, "dim must be 2 or 3");
+  if (d->fe_degree < 2) return fail(SMG_EINVAL, "fe_degree must be >= 2 (Taylor-Hood Q_k-Q_{k-1})");
+  if (d->fe_degree > 3) return fail(SMG_EUNSUPPORTED, "fe_degree > 3 is not built");
+  if (d->n_levels < 2 || d->n_levels > 16) return fail(SMG_EINVAL, "n_levels must be in [2, 16]");
+  double ncells = 1.0;
+  for (int a = 0; a < d->dim; ++a) {
+    if (d->n_coarse[a] < 2) return fail(SMG_EINVAL, "n_coarse must be >= 2 in every direction (no cell with two opposite boundary faces)");
+    if (!(d->box_hi[a] > d->box_lo[a])) return fail(SMG_EINVAL, "box_hi must exceed box_lo");
+    const double n = (double)d->n_coarse[a] * std::ldexp(1.0, d->n_levels - 1);
+    if (n * d->fe_degree + 1 > 2.0e9) return fail(SMG_EINVAL, "mesh too large");
+    ncells *= n;
+  }
+  if (ncells > 4.0e9) return fail(SMG_EINVAL, "mesh too large");
+  if (!(d->mu > 0) && !d->mu_cell) return fail(SMG_EINVAL, "mu must be > 0");
+  if (!(d->gamma >= 0) || !(d->rho > 0)) return fail(SMG_EINVAL, "need gamma >= 0 and rho > 0");
+  if (!(d->c_pressure >= 0)) return fail(SMG_EINVAL, "c_pressure must be >= 0");
+  if (d->cheb_deg_A < 0 || d->cheb_deg_A > 16 || d->cheb_deg_S < 0 || d->cheb_deg_S > 16)
+    return fail(SMG_EINVAL, "Chebyshev degrees must be in [0, 16]");
+  if (d->smooth_steps < 1 || d->smooth_steps > 64) return fail(SMG_EINVAL, "smooth_steps must be in [1, 64]");
+  if (d->cycle_index < 1 || d->cycle_index > 2) return fail(SMG_EINVAL, "cycle_index must be 1 (V) or 2 (W)");
+  if (d->schur_diag < 0 || d->schur_diag > 2) return fail(SMG_EINVAL, "schur_diag must be 0, 1 or 2");
+  if (d->precision != SMG_PRECOND_F64 && d->precision != SMG_PRECOND_F32) return fail(SMG_EINVAL, "precision must be 0 or 1");
+  if (d->fgmres_restart < 1 || d->fgmres_restart > 200) return fail(SMG_EINVAL, "fgmres_restart must be in [1, 200]");
+  if (d->fine_vertices) return fail(SMG_EUNSUPPORTED, "non-Cartesian (vertex-given) meshes are not built");
+  if (d->mu_cell) {
+    double nf = 1.0;
+    for (int a = 0; a < d->dim; ++a) nf *= (double)d->n_coarse[a] * std::ldexp(1.0, d->n_levels - 1);
+    for (int64_t i = 0; i < (int64_t)nf; ++i)
+      if (!(d->mu_cell[i] > 0) || !std::isfinite(d->mu_cell[i])) return fail(SMG_EINVAL, "mu_cell entries must be finite and > 0");
+  }
+  return SMG_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+void smg_desc_default(smg_desc *d) {
+  if (!d) return;
+  std::memset(d, 0, sizeof(*d));
+  d->dim = 2;
+  d->fe_degree = 2;
+  d->n_coarse[0] = d->n_coarse[1] = d->n_coarse[2] = 4;
+  d->n_levels = 3;
+  for (int a = 0; a < 3; ++a) {
+    d->box_lo[a] = 0.0;
+    d->box_hi[a] = 1.0;
+  }
+  d->fine_vertices = nullptr;
+  d->mu = 1.0;
+  d->mu_cell = nullptr;
+  d->gamma = 0.0;
+  d->rho = 1.0;
+  d->c_pressure = 0.0;
+  d->cheb_deg_A = 1;
+  d->cheb_deg_S = 1;
+  d->smooth_steps = 2;
+  d->cycle_index = 1;
+  d->schur_diag = SMG_SCHUR_D;
+  d->precision = SMG_PRECOND_F64;
+  d->fgmres_restart = 30;
+  d->stream = nullptr;
+}
+
+smg_status smg_create(const smg_desc *desc, smg_ctx **out) {
+  if (!out) return fail(SMG_EINVAL, "null output pointer");
+  *out = nullptr;
+  smg_status s = validate(desc);
+  if (s != SMG_OK) return s;
+  smg::EngineBase *eng = nullptr;
+  if (desc->dim == 2 && desc->fe_degree == 2) eng = smg::make_engine_2_2();
+  else if (desc->dim == 2 && desc->fe_degree == 3) eng = smg::make_engine_2_3();
+  else if (desc->dim == 3 && desc->fe_degree == 2) eng = smg::make_engine_3_2();
+  else eng = smg::make_engine_3_3();
+  eng->desc = *desc;
+  eng->desc.fine_vertices = nullptr;
+  eng->desc.mu_cell = desc->mu_cell;  // read during setup only
+  smg_ctx *ctx = new smg_ctx();
+  ctx->eng = eng;
+  try {
+    int dev = 0;
+    SMG_HIP(hipGetDevice(&dev));
+    ctx->device = dev;
+    eng->setup();
+    eng->desc.mu_cell = nullptr;
+  } catch (const smg::Error &e) {
+    eng->free_all();
+    delete eng;
+    delete ctx;
+    return fail(e.code, e.msg);
+  } catch (const std::exception &e) {
+    eng->free_all();
+    delete eng;
+    delete ctx;
+    return fail(SMG_EDEVICE, e.what());
+  }
+  *out = ctx;
+  g_last_error.clear();
+  return SMG_OK;
+}
+
+smg_status smg_destroy(smg_ctx *ctx) {
+  if (!ctx) return SMG_OK;
+  if (ctx->eng) {
+    (void)hipStreamSynchronize(ctx->eng->stream);
+    ctx->eng->free_all();
+    delete ctx->eng;
+  }
+  delete ctx;
+  return SMG_OK;
+}
+
+smg_status smg_sizes(const smg_ctx *ctx, int level, int64_t *n_u, int64_t *n_p) {
+  smg_status s = check_level(ctx, level);
+  if (s != SMG_OK) return s;
+  if (n_u) *n_u = ctx->eng->lv[level].Nu;
+  if (n_p) *n_p = ctx->eng->lv[level].Np;
+  return SMG_OK;
+}
+
+smg_status smg_set_stream(smg_ctx *ctx, void *stream) {
+  smg_status s = check_ctx(ctx);
+  if (s != SMG_OK) return s;
+  ctx->eng->stream = (hipStream_t)stream;
+  ctx->eng->desc.stream = stream;
+  return SMG_OK;
+}
+
+smg_status smg_vmult(smg_ctx *ctx, int level, int dtype, const void *x, void *y) {
+  smg_status s = check_level(ctx, level);
+  if (s == SMG_OK) s = check_dtype(dtype);
+  if (s == SMG_OK) s = check_ptrs({x, y});
+  if (s != SMG_OK) return s;
+  if (x == y) return fail(SMG_EINVAL, "x and y must be distinct");
+  SMG_TRY(ctx->eng->vmult(level, dtype, x, y));
+}
+
+smg_status smg_residual(smg_ctx *ctx, int level, int dtype, const void *x, const void *b, void *r) {
+  smg_status s = check_level(ctx, level);
+  if (s == SMG_OK) s = check_dtype(dtype);
+  if (s == SMG_OK) s = check_ptrs({x, b, r});
+  if (s != SMG_OK) return s;
+  if (r == x || r == b) return fail(SMG_EINVAL, "r may alias neither x nor b");
+  SMG_TRY(ctx->eng->residual(level, dtype, x, b, r));
+}
+
+smg_status smg_apply_block(smg_ctx *ctx, int level, int dtype, int block, const void *x, void *y) {
+  smg_status s = check_level(ctx, level);
+  if (s == SMG_OK) s = check_dtype(dtype);
+  if (s == SMG_OK) s = check_ptrs({x, y});
+  if (s != SMG_OK) return s;
+  if (block < SMG_BLOCK_K || block > SMG_BLOCK_MASS) return fail(SMG_EINVAL, "unknown block");
+  if (x == y) return fail(SMG_EINVAL, "x and y must be distinct");
+  SMG_TRY(ctx->eng->apply_block(level, dtype, block, x, y));
+}
+
+smg_status smg_get_diagonal(const smg_ctx *ctx, int level, int which, double *out) {
+  smg_status s = check_level(ctx, level);
+  if (s == SMG_OK) s = check_ptrs({out});
+  if (s != SMG_OK) return s;
+  if (which != 0 && which != 1) return fail(SMG_EINVAL, "which must be 0 (D_A) or 1 (D~_S)");
+  const smg::LevelInfo &I = ctx->eng->lv[level];
+  SMG_TRY({
+    SMG_HIP(hipMemcpyAsync(out, which == 0 ? I.DA : I.DS, sizeof(double) * (which == 0 ? I.Nu : I.Np),
+                           hipMemcpyDeviceToDevice, ctx->eng->stream));
+    SMG_HIP(hipStreamSynchronize(ctx->eng->stream));
+  });
+}
+
+smg_status smg_get_eigs(const smg_ctx *ctx, int level, double *beta_A, double *beta_S) {
+  smg_status s = check_level(ctx, level);
+  if (s != SMG_OK) return s;
+  if (beta_A) *beta_A = ctx->eng->lv[level].beta_A;
+  if (beta_S) *beta_S = ctx->eng->lv[level].beta_S;
+  return SMG_OK;
+}
+
+smg_status smg_set_eigs(smg_ctx *ctx, int level, double beta_A, double beta_S) {
+  smg_status s = check_level(ctx, level, 1);
+  if (s != SMG_OK) return s;
+  if (!(beta_A > 0) || !(beta_S > 0) || !std::isfinite(beta_A) || !std::isfinite(beta_S))
+    return fail(SMG_EINVAL, "eigenvalue bounds must be finite and > 0");
+  ctx->eng->lv[level].beta_A = beta_A;
+  ctx->eng->lv[level].beta_S = beta_S;
+  return SMG_OK;
+}
+
+smg_status smg_chebyshev(smg_ctx *ctx, int level, int dtype, int which, const void *r, void *out) {
+  smg_status s = check_level(ctx, level, 1);
+  if (s == SMG_OK) s = check_dtype(dtype);
+  if (s == SMG_OK) s = check_ptrs({r, out});
+  if (s != SMG_OK) return s;
+  if (which != 0 && which != 1) return fail(SMG_EINVAL, "which must be 0 (A) or 1 (S)");
+  if (r == out) return fail(SMG_EINVAL, "r and out must be distinct");
+  SMG_TRY(ctx->eng->chebyshev(level, dtype, which, r, out));
+}
+
+smg_status smg_smooth(smg_ctx *ctx, int level, int dtype, void *x, const void *b, int steps) {
+  smg_status s = check_level(ctx, level, 1);
+  if (s == SMG_OK) s = check_dtype(dtype);
+  if (s == SMG_OK) s = check_ptrs({x, b});
+  if (s != SMG_OK) return s;
+  if (steps < 0) return fail(SMG_EINVAL, "steps must be >= 0");
+  if (x == b) return fail(SMG_EINVAL, "x and b must be distinct");
+  SMG_TRY(ctx->eng->smooth(level, dtype, x, b, steps));
+}
+
+smg_status smg_restrict(smg_ctx *ctx, int fine_level, int dtype, const void *r_fine, void *r_coarse) {
+  smg_status s = check_level(ctx, fine_level, 1);
+  if (s == SMG_OK) s = check_dtype(dtype);
+  if (s == SMG_OK) s = check_ptrs({r_fine, r_coarse});
+  if (s != SMG_OK) return s;
+  SMG_TRY(ctx->eng->restrict_(fine_level, dtype, r_fine, r_coarse));
+}
+
+smg_status smg_prolongate_add(smg_ctx *ctx, int fine_level, int dtype, const void *w_coarse, void *x_fine) {
+  smg_status s = check_level(ctx, fine_level, 1);
+  if (s == SMG_OK) s = check_dtype(dtype);
+  if (s == SMG_OK) s = check_ptrs({w_coarse, x_fine});
+  if (s != SMG_OK) return s;
+  SMG_TRY(ctx->eng->prolongate_add(fine_level, dtype, w_coarse, x_fine));
+}
+
+smg_status smg_coarse_solve(smg_ctx *ctx, int dtype, const void *b0, void *x0) {
+  smg_status s = check_ctx(ctx);
+  if (s == SMG_OK) s = check_dtype(dtype);
+  if (s == SMG_OK) s = check_ptrs({b0, x0});
+  if (s != SMG_OK) return s;
+  if (b0 == x0) return fail(SMG_EINVAL, "b0 and x0 must be distinct");
+  SMG_TRY(ctx->eng->coarse_solve(dtype, b0, x0));
+}
+
+smg_status smg_vcycle(smg_ctx *ctx, int level, int dtype, void *x, const void *b) {
+  smg_status s = check_level(ctx, level);
+  if (s == SMG_OK) s = check_dtype(dtype);
+  if (s == SMG_OK) s = check_ptrs({x, b});
+  if (s != SMG_OK) return s;
+  if (x == b) return fail(SMG_EINVAL, "x and b must be distinct");
+  SMG_TRY(ctx->eng->vcycle(level, dtype, x, b));
+}
+
+smg_status smg_solve(smg_ctx *ctx, double *x, const double *b, double rtol, int maxit, smg_solve_info *info) {
+  smg_status s = check_ctx(ctx);
+  if (s == SMG_OK) s = check_ptrs({x, b});
+  if (s != SMG_OK) return s;
+  if (!(rtol > 0) || maxit < 0) return fail(SMG_EINVAL, "need rtol > 0 and maxit >= 0");
+  if (x == b) return fail(SMG_EINVAL, "x and b must be distinct");
+  try {
+    smg_status r = ctx->eng->solve(x, b, rtol, maxit, info);
+    if (r == SMG_ENOTCONV) g_last_error = "iteration limit reached before the tolerance";
+    else if (r == SMG_EBREAKDOWN) g_last_error = "breakdown (NaN/Inf) in FGMRES";
+    else g_last_error.clear();
+    return r;
+  } catch (const smg::Error &e) {
+    return fail(e.code, e.msg);
+  }
+}
+
+smg_status smg_solve_stationary(smg_ctx *ctx, double *x, const double *b, double rtol, int maxit, smg_solve_info *info) {
+  smg_status s = check_ctx(ctx);
+  if (s == SMG_OK) s = check_ptrs({x, b});
+  if (s != SMG_OK) return s;
+  if (!(rtol > 0) || maxit < 0) return fail(SMG_EINVAL, "need rtol > 0 and maxit >= 0");
+  if (x == b) return fail(SMG_EINVAL, "x and b must be distinct");
+  try {
+    smg_status r = ctx->eng->solve_stationary(x, b, rtol, maxit, info);
+    if (r == SMG_ENOTCONV) g_last_error = "iteration limit reached before the tolerance";
+    else if (r == SMG_EBREAKDOWN) g_last_error = "breakdown: NaN/Inf or residual growth by more than 1e3";
+    else g_last_error.clear();
+    return r;
+  } catch (const smg::Error &e) {
+    return fail(e.code, e.msg);
+  }
+}
+
+smg_status smg_node_coordinates(const smg_ctx *ctx, int level, double *xyz) {
+  smg_status s = check_level(ctx, level);
+  if (s == SMG_OK) s = check_ptrs({xyz});
+  if (s != SMG_OK) return s;
+  SMG_TRY(ctx->eng->node_coordinates(level, xyz));
+}
+
+const char *smg_last_error(void) { return g_last_error.c_str(); }
+
+}  // extern "C"

@@ -1,0 +1,85 @@
+"""C ABI checks that need no GPU: the library loads, exports every function
+include/smg.h declares, fills defaults, and rejects invalid descriptors and
+arguments before touching the device."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "smg.h")
+LIB = os.path.join(ROOT, "paper_2205_15770_amd", "libsmg.so")
+
+pytestmark = pytest.mark.skipif(not os.path.exists(LIB), reason="libsmg.so not built (run __graft_entry__.build())")
+
+
+def _declared():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(smg_[a-z_]+)\s*\(", text)))
+
+
+def test_header_declarations_are_exported():
+    from paper_2205_15770_amd import _lib
+    lib = ctypes.CDLL(LIB)
+    names = _declared()
+    assert len(names) >= 20
+    for n in names:
+        assert hasattr(lib, n), n
+    assert sorted(_lib.EXPORTS) == names
+
+
+def test_desc_default_values():
+    from paper_2205_15770_amd import _lib
+    lib = _lib.load()
+    d = _lib.SmgDesc()
+    lib.smg_desc_default(ctypes.byref(d))
+    assert (d.dim, d.fe_degree, d.n_levels) == (2, 2, 3)
+    assert list(d.n_coarse) == [4, 4, 4]
+    assert (d.cheb_deg_A, d.cheb_deg_S, d.smooth_steps, d.cycle_index) == (1, 1, 2, 1)
+    assert d.mu == 1.0 and d.rho == 1.0 and d.gamma == 0.0 and d.c_pressure == 0.0
+    assert d.fgmres_restart == 30
+
+
+@pytest.mark.parametrize("field,value,code", [
+    ("dim", 4, -1), ("fe_degree", 1, -1), ("fe_degree", 4, -6), ("n_levels", 1, -1),
+    ("smooth_steps", 0, -1), ("cycle_index", 3, -1), ("schur_diag", 5, -1), ("precision", 7, -1),
+    ("fgmres_restart", 0, -1), ("cheb_deg_A", -1, -1), ("gamma", -1.0, -1), ("mu", 0.0, -1),
+    ("rho", 0.0, -1), ("c_pressure", -0.5, -1),
+])
+def test_invalid_descriptors_rejected_without_device(field, value, code):
+    from paper_2205_15770_amd import _lib
+    lib = _lib.load()
+    d = _lib.SmgDesc()
+    lib.smg_desc_default(ctypes.byref(d))
+    setattr(d, field, value)
+    h = ctypes.c_void_p(1234)
+    st = lib.smg_create(ctypes.byref(d), ctypes.byref(h))
+    assert st == code
+    assert h.value is None
+    assert len(lib.smg_last_error()) > 0
+
+
+def test_coarse_mesh_condition_and_box():
+    from paper_2205_15770_amd import _lib
+    lib = _lib.load()
+    d = _lib.SmgDesc()
+    lib.smg_desc_default(ctypes.byref(d))
+    d.n_coarse[1] = 1          # a coarse cell with two opposite boundary faces (App. A)
+    h = ctypes.c_void_p()
+    assert lib.smg_create(ctypes.byref(d), ctypes.byref(h)) == -1
+    lib.smg_desc_default(ctypes.byref(d))
+    d.box_hi[0] = d.box_lo[0]
+    assert lib.smg_create(ctypes.byref(d), ctypes.byref(h)) == -1
+
+
+def test_null_arguments_rejected():
+    from paper_2205_15770_amd import _lib
+    lib = _lib.load()
+    assert lib.smg_create(None, None) == -1
+    assert lib.smg_vmult(None, 0, 0, None, None) == -1
+    assert lib.smg_sizes(None, 0, None, None) == -1
+    assert lib.smg_solve(None, None, None, 1e-8, 10, None) == -1
+    assert lib.smg_destroy(None) == 0
+    assert b"null" in lib.smg_last_error() or lib.smg_last_error() == b""
