@@ -1,0 +1,233 @@
+"""Benchmark of the matrix-free monolithic multigrid Stokes solver on one MI355X.
+
+Workload (default): the 2D generalized Stokes problem, Q2-Q1 on a uniform
+512 x 512 box mesh (2,364,419 DoFs), mu = rho = 1, gamma = 1e3, nodal body
+force U[-1,1] per velocity DoF (seed 2), 7-level V-cycle with the inexact
+symmetric Uzawa smoother (k_A, k_S, m) = (1, 1, 2).
+
+A step is one solve K x = b to ||b - K x|| <= 1e-8 ||b|| from x = 0 by FP64
+FGMRES(30) preconditioned with one FP32 V-cycle per iteration: every part of
+the method (operator applications, Chebyshev-Jacobi Uzawa smoothing, residuals,
+transfers, coarse solve, cycle, outer loop) runs in each step; the diagonals
+and Chebyshev bounds are set up once before the timed region.
+
+value = DoFs solved per second (N * steps / time, GDoF/s).  The same line
+reports the vmult throughput (GDoF/s, FP64 and FP32), the FP64-preconditioned
+solve for comparison, the roofline of the dominant kernel (HIP events on the
+launch stream during the timed steps) and the CPU oracle on a bounded sample.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+WORKLOADS = {
+    "stokes2d_q2q1_512": dict(dim=2, fe_degree=2, n_coarse=(8, 8), n_levels=7, mu=1.0, rho=1.0, gamma=1e3,
+                              desc="2D generalized Stokes Q2-Q1, 512x512 cells, 7 levels, gamma=1e3"),
+    "stokes3d_q2q1_64": dict(dim=3, fe_degree=2, n_coarse=(2, 2, 2), n_levels=6, mu=1.0, rho=1.0, gamma=0.0,
+                             desc="3D Stokes Q2-Q1, 64^3 cells, 6 levels"),
+}
+
+
+def parse():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="stokes2d_q2q1_512", choices=sorted(WORKLOADS))
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--quick", action="store_true", help="skip the secondary measurements")
+    return ap.parse_args()
+
+
+def rhs(mg, level, dim, seed=2):
+    """b = [M_v f, 0] for a nodal random force f (the library's mass kernel)."""
+    import torch
+    import synth_inputs as si
+    nu, np_ = mg.sizes(level)
+    f = torch.tensor(si.nodal_random_f(dim, nu // dim, seed=seed).ravel(), dtype=torch.float64, device="cuda")
+    b = torch.zeros(nu + np_, dtype=torch.float64, device="cuda")
+    from paper_2205_15770_amd import SMG_BLOCK_MASS
+    mg.apply_block(level, SMG_BLOCK_MASS, f, b[:nu])
+    return b
+
+
+def time_vmult(mg, level, dtype, pairs=8, reps=10):
+    """GDoF/s of y = K x, rotating over `pairs` vector pairs (> the 256 MB
+    Infinity Cache for the default workload), HIP events on the stream."""
+    import torch
+    import synth_inputs as si
+    n = mg.n_total(level)
+    xs = [torch.tensor(si.uniform(n, 200 + i), dtype=dtype, device="cuda") for i in range(pairs)]
+    ys = [torch.empty(n, dtype=dtype, device="cuda") for _ in range(pairs)]
+    for i in range(pairs):
+        mg.vmult(level, xs[i], ys[i])
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(reps):
+        for i in range(pairs):
+            mg.vmult(level, xs[i], ys[i])
+    e1.record()
+    torch.cuda.synchronize()
+    t = e0.elapsed_time(e1) * 1e-3 / (reps * pairs)
+    return n / t / 1e9, t
+
+
+def traffic_from_profiles(kernel_key):
+    """Per-launch HBM bytes of `kernel_key` from the committed counter summary,
+    if it was taken on the current kernel sources (else None)."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "hbm_traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        rec = json.load(fh)
+    h = hashlib.sha256()
+    for f in sorted(os.listdir(os.path.join(ROOT, "paper_2205_15770_amd", "csrc"))):
+        with open(os.path.join(ROOT, "paper_2205_15770_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    if rec.get("sources_sha256") != h.hexdigest():
+        return None
+    k = rec.get("kernels", {}).get(kernel_key)
+    return None if k is None else k.get("bytes_per_launch")
+
+
+def cpu_baseline():
+    """The oracle (assembled CSR, FP64, same smoother and FGMRES) on a bounded
+    sample: the same generalized Stokes problem on a 256 x 256 mesh."""
+    import numpy as np
+    try:
+        from threadpoolctl import threadpool_limits
+    except Exception:  # pragma: no cover
+        threadpool_limits = None
+    import synth_inputs as si
+    from oracle.mesh import make_hierarchy
+    from oracle.mg import Multigrid
+    from oracle.krylov import fgmres
+    ctx = threadpool_limits(1) if threadpool_limits else None
+    try:
+        meshes = make_hierarchy(2, (8, 8), 6, 2)
+        ora = Multigrid(meshes, mu=1.0, gamma=1e3, rho=1.0, k_A=1, k_S=1, smooth_steps=2)
+        asm = ora.levels[-1]
+        b = asm.rhs_from_nodal_f(si.nodal_random_f(2, meshes[-1].n_vnode, seed=2))
+        t0 = time.perf_counter()
+        x, hist = fgmres(asm.K, ora.precondition, b, rtol=1e-8)
+        t = time.perf_counter() - t0
+        n = asm.K.shape[0]
+        # CSR SpMV of the assembled K (the oracle's counterpart of vmult)
+        xv = si.uniform(n, 1)
+        t1 = time.perf_counter()
+        reps = 50
+        for _ in range(reps):
+            asm.K @ xv
+        tv = (time.perf_counter() - t1) / reps
+    finally:
+        if ctx is not None:
+            ctx.unregister() if hasattr(ctx, "unregister") else None
+    return {"value": n / t / 1e9, "unit": "GDoF/s", "cores": 1, "kind": "oracle",
+            "sample": f"oracle FGMRES(30) + FP64 V-cycle solve to 1e-8 of the same generalized Stokes problem on "
+                      f"256x256 cells ({n} DoFs, 6 levels), {len(hist) - 1} iterations, {t:.2f} s, setup excluded; "
+                      f"CSR SpMV {n / tv / 1e9:.4f} GDoF/s",
+            "spmv_gdofs": n / tv / 1e9}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this benchmark runs on exactly one GPU (--gpus 1); "
+                                   "multi-GPU sharding is described in DESIGN.md, not built"}))
+        sys.exit(2)
+    import torch
+    from paper_2205_15770_amd import StokesMG
+    torch.cuda.set_device(0)
+    wl = WORKLOADS[args.workload]
+    common = dict(dim=wl["dim"], fe_degree=wl["fe_degree"], n_coarse=wl["n_coarse"], n_levels=wl["n_levels"],
+                  mu=wl["mu"], rho=wl["rho"], gamma=wl["gamma"], cheb_deg_A=1, cheb_deg_S=1, smooth_steps=2,
+                  cycle_index=1, schur_diag="d")
+    L = wl["n_levels"] - 1
+    t_setup0 = time.perf_counter()
+    mg = StokesMG(precision="f32", **common)
+    torch.cuda.synchronize()
+    t_setup = time.perf_counter() - t_setup0
+    N = mg.n_total(L)
+    b = rhs(mg, L, wl["dim"])
+    x = torch.zeros(N, dtype=torch.float64, device="cuda")
+    print(f"# setup {t_setup:.2f} s, N = {N}", file=sys.stderr, flush=True)
+    for _ in range(args.warmup):
+        x.zero_()
+        mg.solve(x, b, rtol=1e-8, maxit=300)
+    print("# warmup done", file=sys.stderr, flush=True)
+    mg.profile(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    infos = []
+    for _ in range(args.steps):
+        x.zero_()
+        infos.append(mg.solve(x, b, rtol=1e-8, maxit=300))
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    rep = mg.profile_report()
+    mg.profile(False)
+    print("# timed steps done", file=sys.stderr, flush=True)
+    elapsed = t1 - t0
+    value = N * args.steps / elapsed / 1e9
+    kern_ms = sum(v[1] for v in rep.values())
+    dom = max(rep, key=lambda k: rep[k][1])
+    cnt, ms, nbytes = rep[dom]
+    achieved = nbytes / (ms * 1e-3) / 1e9
+    traffic = traffic_from_profiles(dom)
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                "kernel": dom, "launches": cnt, "avg_us": round(ms * 1e3 / cnt, 2),
+                "algorithmic_bytes_per_launch": nbytes / cnt,
+                "share_of_kernel_time": round(ms / kern_ms, 3)}
+    extra = {}
+    if not args.quick:
+        g64, t64 = time_vmult(mg, L, torch.float64)
+        g32, t32 = time_vmult(mg, L, torch.float32)
+        extra["vmult"] = {"f64_gdofs": round(g64, 2), "f32_gdofs": round(g32, 2),
+                          "f64_us": round(t64 * 1e6, 2), "f32_us": round(t32 * 1e6, 2),
+                          "f64_hbm_gbs": round(2 * 8 * N / t64 / 1e9, 1), "f32_hbm_gbs": round(2 * 4 * N / t32 / 1e9, 1)}
+        x_mixed = x.clone()
+        mg64 = StokesMG(precision="f64", **common)
+        x64 = torch.zeros_like(x)
+        mg64.solve(x64, b, rtol=1e-8, maxit=300)
+        tt = []
+        for _ in range(2):
+            x64.zero_()
+            torch.cuda.synchronize()
+            s0 = time.perf_counter()
+            i64 = mg64.solve(x64, b, rtol=1e-8, maxit=300)
+            torch.cuda.synchronize()
+            tt.append(time.perf_counter() - s0)
+        err = (torch.linalg.norm(x_mixed - x64) / torch.linalg.norm(x64)).item()
+        extra["solve"] = {"f32_mixed_ms": round(elapsed / args.steps * 1e3, 2), "f64_ms": round(min(tt) * 1e3, 2),
+                          "speedup_mixed_vs_f64": round(min(tt) / (elapsed / args.steps), 3),
+                          "iterations_mixed": infos[-1]["iterations"], "iterations_f64": i64["iterations"],
+                          "rel_residual_mixed": infos[-1]["rel_residual"], "rel_residual_f64": i64["rel_residual"],
+                          "rel_diff_mixed_vs_f64_solution": err}
+        mg64.close()
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline()
+    out = {"metric": "GDoF/s Stokes vmult; solve time to 1e-8 resid, FP32-mixed vs FP64",
+           "value": round(value, 4), "unit": "GDoF/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+           "ms_per_step": round(elapsed / args.steps * 1e3, 3), "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f32 cycle / f64 outer", "data": "synthetic",
+           "config": {"workload": args.workload, "description": wl["desc"], "dofs": N,
+                      "smoother": "(k_A,k_S,m)=(1,1,2), D~_S_d, V-cycle", "rtol": 1e-8,
+                      "value_definition": "DoFs solved to 1e-8 per second (N*steps/time)"},
+           "roofline": roofline, "cpu_baseline": cpu}
+    out.update(extra)
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

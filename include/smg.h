@@ -208,6 +208,18 @@ smg_status smg_solve_stationary(smg_ctx *ctx, double *x, const double *b, double
  * lattice nodes of level l (for evaluating nodal data such as f). */
 smg_status smg_node_coordinates(const smg_ctx *ctx, int level, double *xyz);
 
+/* Kernel timing for measurement: with enable != 0, every later operator-kernel
+ * launch of this context is bracketed by two HIP events recorded on the
+ * context's stream (previous records are discarded); enable == 0 stops.
+ * smg_profile_report synchronises the stream and writes one line per kernel
+ * key "name/vVARIANT/blkBLOCKS/dtype/NXxNYxNZ count total_ms total_bytes" into buf
+ * (NUL-terminated, truncated to cap bytes); *len receives the full length.
+ * total_bytes is the algorithmic HBM traffic of those launches: each vector
+ * the kernel reads or writes counted once.
+ * Intended for benchmarks: the events add a little host overhead per launch. */
+smg_status smg_profile(smg_ctx *ctx, int enable);
+smg_status smg_profile_report(smg_ctx *ctx, char *buf, int64_t cap, int64_t *len);
+
 /* Message of the last failed call on this thread ("" if none). */
 const char *smg_last_error(void);
 

@@ -213,6 +213,22 @@ class StokesMG:
     def solve_stationary(self, x, b, rtol=1e-10, maxit=15, raise_on_failure=False):
         return self._solve(self.lib.smg_solve_stationary, x, b, rtol, maxit, raise_on_failure)
 
+    def profile(self, enable=True):
+        """Start (or stop) timing every operator-kernel launch with HIP events."""
+        _lib.check(self.lib.smg_profile(self._h, 1 if enable else 0))
+
+    def profile_report(self):
+        """{key: (count, total_ms, algorithmic_bytes)} of the launches recorded since profile(True)."""
+        n = ctypes.c_int64()
+        _lib.check(self.lib.smg_profile_report(self._h, None, 0, ctypes.byref(n)))
+        buf = ctypes.create_string_buffer(n.value + 1)
+        _lib.check(self.lib.smg_profile_report(self._h, buf, n.value + 1, ctypes.byref(n)))
+        out = {}
+        for line in buf.value.decode().splitlines():
+            key, cnt, ms, nbytes = line.rsplit(" ", 3)
+            out[key] = (int(cnt), float(ms), float(nbytes))
+        return out
+
     def node_coordinates(self, level):
         nu, _ = self.sizes(level)
         nv = nu // self.dim

@@ -22,7 +22,7 @@ EXPORTS = ["smg_desc_default", "smg_create", "smg_destroy", "smg_sizes", "smg_se
            "smg_vmult", "smg_residual", "smg_apply_block", "smg_get_diagonal", "smg_get_eigs",
            "smg_set_eigs", "smg_chebyshev", "smg_smooth", "smg_restrict", "smg_prolongate_add",
            "smg_coarse_solve", "smg_vcycle", "smg_solve", "smg_solve_stationary",
-           "smg_node_coordinates", "smg_last_error"]
+           "smg_node_coordinates", "smg_profile", "smg_profile_report", "smg_last_error"]
 
 
 class SmgDesc(ctypes.Structure):
@@ -86,6 +86,8 @@ def load(path=LIB_PATH):
         "smg_solve": (I, [P, P, P, D, I, ctypes.POINTER(SmgSolveInfo)]),
         "smg_solve_stationary": (I, [P, P, P, D, I, ctypes.POINTER(SmgSolveInfo)]),
         "smg_node_coordinates": (I, [P, I, P]),
+        "smg_profile": (I, [P, I]),
+        "smg_profile_report": (I, [P, ctypes.c_char_p, ctypes.c_int64, i64p]),
         "smg_last_error": (ctypes.c_char_p, []),
     }
     for name, (res, args) in sig.items():

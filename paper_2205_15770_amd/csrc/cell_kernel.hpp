@@ -196,37 +196,114 @@ tile_apply_kernel(const LevelGeom<T, DIM, K> g, const Op op) {
   const int vdz = DIM == 3 ? g.vd[2] : 1;
   const int pdz = DIM == 3 ? g.pd[2] : 1;
 
-  // 1. patch loads (x fastest -> coalesced rows)
-  if constexpr (NEED_U || OUT_U) {
-    for (int i = threadIdx.x; i < DIM * PV; i += NT) {
-      const int c = i / PV;
-      const int r = i - c * PV;
-      const int lx = r % PVX, ly = (r / PVX) % PVY, lz = r / (PVX * PVY);
-      const int gx = ax.node0 + lx, gy = ay.node0 + ly, gz = az.node0 + lz;
-      if constexpr (NEED_U) {
-        T v = 0;
-        if (gx >= 0 && gx < g.vd[0] && gy >= 0 && gy < g.vd[1] && gz >= 0 && gz < vdz) {
-          const bool bc = on_box_boundary(gx, g.vd[0]) || on_box_boundary(gy, g.vd[1]) ||
-                          (DIM == 3 && on_box_boundary(gz, vdz));
-          if (!(bc && Op::ZERO_BC))
-            v = op.load_u((i64)c * g.Nv + gx + (i64)g.vd[0] * (gy + (i64)g.vd[1] * gz));
-        }
-        s_u[i] = v;
+  // 0. everything the epilogue reads for the owned nodes is requested first,
+  //    so that those loads share one memory round trip with the patch loads.
+  constexpr int ITU = OUT_U ? (DIM * (OWN_X * K + 1) * (OWN_Y * K + 1) * (DIM == 3 ? OWN_Z * K + 1 : 1) + NT - 1) / NT : 1;
+  constexpr int ITP = OUT_P ? ((OWN_X * (K - 1) + 1) * (OWN_Y * (K - 1) + 1) * (DIM == 3 ? OWN_Z * (K - 1) + 1 : 1) + NT - 1) / NT : 1;
+  typename Op::Pre pre_u[ITU];
+  T raw_u[ITU];
+  i64 gidx_u[ITU];
+  int lidx_u[ITU];
+  bool bc_u[ITU];
+  typename Op::Pre pre_p[ITP];
+  i64 gidx_p[ITP];
+  int lidx_p[ITP];
+  if constexpr (OUT_U) {
+    const int ox = ax.own_hi - ax.own_lo, oy = ay.own_hi - ay.own_lo, oz = az.own_hi - az.own_lo;
+    const int per = ox * oy * oz;
+#pragma unroll
+    for (int it = 0; it < ITU; ++it) {
+      const int i = threadIdx.x + it * NT;
+      gidx_u[it] = -1;
+      raw_u[it] = 0;
+      if (i < DIM * per) {
+        const int c = i / per;
+        const int r = i - c * per;
+        const int gx = ax.own_lo + r % ox, gy = ay.own_lo + (r / ox) % oy, gz = az.own_lo + r / (ox * oy);
+        lidx_u[it] = c * PV + (gx - ax.node0) + PVX * ((gy - ay.node0) + PVY * (gz - az.node0));
+        gidx_u[it] = (i64)c * g.Nv + gx + (i64)g.vd[0] * (gy + (i64)g.vd[1] * gz);
+        bc_u[it] = on_box_boundary(gx, g.vd[0]) || on_box_boundary(gy, g.vd[1]) ||
+                   (DIM == 3 && on_box_boundary(gz, vdz));
+        pre_u[it] = op.fetch_u(gidx_u[it]);
+        // constrained row: identity for A (and K), zero for B^T and the mass load
+        if constexpr ((BLK & BLK_A) != 0)
+          if (bc_u[it]) raw_u[it] = op.load_u(gidx_u[it]);
       }
-      if constexpr (OUT_U) o_u[i] = 0;
+    }
+  }
+  if constexpr (OUT_P) {
+    const int ox = px.own_hi - px.own_lo, oy = py.own_hi - py.own_lo, oz = pz.own_hi - pz.own_lo;
+    const int per = ox * oy * oz;
+#pragma unroll
+    for (int it = 0; it < ITP; ++it) {
+      const int i = threadIdx.x + it * NT;
+      gidx_p[it] = -1;
+      if (i < per) {
+        const int gx = px.own_lo + i % ox, gy = py.own_lo + (i / ox) % oy, gz = pz.own_lo + i / (ox * oy);
+        lidx_p[it] = (gx - px.node0) + PPX * ((gy - py.node0) + PPY * (gz - pz.node0));
+        gidx_p[it] = gx + (i64)g.pd[0] * (gy + (i64)g.pd[1] * gz);
+        pre_p[it] = op.fetch_p(gidx_p[it]);
+      }
+    }
+  }
+
+  // 1. patch loads (x fastest -> coalesced rows).  All global loads of a
+  //    thread are issued before the first LDS store so that their latencies
+  //    overlap instead of adding up.
+  if constexpr (NEED_U || OUT_U) {
+    constexpr int IT = (DIM * PV + NT - 1) / NT;
+    T vals[IT];
+#pragma unroll
+    for (int it = 0; it < IT; ++it) {
+      const int i = threadIdx.x + it * NT;
+      vals[it] = 0;
+      if constexpr (NEED_U) {
+        if (i < DIM * PV) {
+          const int c = i / PV;
+          const int r = i - c * PV;
+          const int lx = r % PVX, ly = (r / PVX) % PVY, lz = r / (PVX * PVY);
+          const int gx = ax.node0 + lx, gy = ay.node0 + ly, gz = az.node0 + lz;
+          if (gx >= 0 && gx < g.vd[0] && gy >= 0 && gy < g.vd[1] && gz >= 0 && gz < vdz) {
+            const bool bc = on_box_boundary(gx, g.vd[0]) || on_box_boundary(gy, g.vd[1]) ||
+                            (DIM == 3 && on_box_boundary(gz, vdz));
+            if (!(bc && Op::ZERO_BC))
+              vals[it] = op.load_u((i64)c * g.Nv + gx + (i64)g.vd[0] * (gy + (i64)g.vd[1] * gz));
+          }
+        }
+      }
+    }
+#pragma unroll
+    for (int it = 0; it < IT; ++it) {
+      const int i = threadIdx.x + it * NT;
+      if (i < DIM * PV) {
+        if constexpr (NEED_U) s_u[i] = vals[it];
+        if constexpr (OUT_U) o_u[i] = 0;
+      }
     }
   }
   if constexpr (NEED_P || OUT_P) {
-    for (int i = threadIdx.x; i < PP; i += NT) {
-      const int lx = i % PPX, ly = (i / PPX) % PPY, lz = i / (PPX * PPY);
-      const int gx = px.node0 + lx, gy = py.node0 + ly, gz = pz.node0 + lz;
+    constexpr int IT = (PP + NT - 1) / NT;
+    T vals[IT];
+#pragma unroll
+    for (int it = 0; it < IT; ++it) {
+      const int i = threadIdx.x + it * NT;
+      vals[it] = 0;
       if constexpr (NEED_P) {
-        T v = 0;
-        if (gx >= 0 && gx < g.pd[0] && gy >= 0 && gy < g.pd[1] && gz >= 0 && gz < pdz)
-          v = op.load_p(gx + (i64)g.pd[0] * (gy + (i64)g.pd[1] * gz));
-        s_p[i] = v;
+        if (i < PP) {
+          const int lx = i % PPX, ly = (i / PPX) % PPY, lz = i / (PPX * PPY);
+          const int gx = px.node0 + lx, gy = py.node0 + ly, gz = pz.node0 + lz;
+          if (gx >= 0 && gx < g.pd[0] && gy >= 0 && gy < g.pd[1] && gz >= 0 && gz < pdz)
+            vals[it] = op.load_p(gx + (i64)g.pd[0] * (gy + (i64)g.pd[1] * gz));
+        }
       }
-      if constexpr (OUT_P) o_p[i] = 0;
+    }
+#pragma unroll
+    for (int it = 0; it < IT; ++it) {
+      const int i = threadIdx.x + it * NT;
+      if (i < PP) {
+        if constexpr (NEED_P) s_p[i] = vals[it];
+        if constexpr (OUT_P) o_p[i] = 0;
+      }
     }
   }
   __syncthreads();
@@ -298,40 +375,27 @@ tile_apply_kernel(const LevelGeom<T, DIM, K> g, const Op op) {
     __syncthreads();
   }
 
-  // 4. owned nodes through the epilogue
+  // 4. owned nodes through the epilogue (inputs fetched in step 0)
   if constexpr (OUT_U) {
-    const int ox = ax.own_hi - ax.own_lo, oy = ay.own_hi - ay.own_lo, oz = az.own_hi - az.own_lo;
-    const int per = ox * oy * oz;
-    for (int i = threadIdx.x; i < DIM * per; i += NT) {
-      const int c = i / per;
-      const int r = i - c * per;
-      const int gx = ax.own_lo + r % ox, gy = ay.own_lo + (r / ox) % oy, gz = az.own_lo + r / (ox * oy);
-      const int l = (gx - ax.node0) + PVX * ((gy - ay.node0) + PVY * (gz - az.node0));
-      const i64 gi = (i64)c * g.Nv + gx + (i64)g.vd[0] * (gy + (i64)g.vd[1] * gz);
-      const bool bc = on_box_boundary(gx, g.vd[0]) || on_box_boundary(gy, g.vd[1]) ||
-                      (DIM == 3 && on_box_boundary(gz, vdz));
-      if (bc) {
-        // constrained row: identity for A (and K), zero for B^T and the mass load
-        T raw = 0;
-        if constexpr ((BLK & BLK_A) != 0) raw = op.load_u(gi);
-        op.store_u(gi, raw, raw, true);
+#pragma unroll
+    for (int it = 0; it < ITU; ++it) {
+      if (gidx_u[it] < 0) continue;
+      if (bc_u[it]) {
+        op.store_u(gidx_u[it], raw_u[it], raw_u[it], true, pre_u[it]);
       } else {
         T v = 0;
-        if constexpr (NEED_U) v = s_u[c * PV + l];
-        op.store_u(gi, o_u[c * PV + l], v, false);
+        if constexpr (NEED_U) v = s_u[lidx_u[it]];
+        op.store_u(gidx_u[it], o_u[lidx_u[it]], v, false, pre_u[it]);
       }
     }
   }
   if constexpr (OUT_P) {
-    const int ox = px.own_hi - px.own_lo, oy = py.own_hi - py.own_lo, oz = pz.own_hi - pz.own_lo;
-    const int per = ox * oy * oz;
-    for (int i = threadIdx.x; i < per; i += NT) {
-      const int gx = px.own_lo + i % ox, gy = py.own_lo + (i / ox) % oy, gz = pz.own_lo + i / (ox * oy);
-      const int l = (gx - px.node0) + PPX * ((gy - py.node0) + PPY * (gz - pz.node0));
-      const i64 gi = gx + (i64)g.pd[0] * (gy + (i64)g.pd[1] * gz);
+#pragma unroll
+    for (int it = 0; it < ITP; ++it) {
+      if (gidx_p[it] < 0) continue;
       T v = 0;
-      if constexpr (NEED_P) v = s_p[l];
-      op.store_p(gi, o_p[l], v);
+      if constexpr (NEED_P) v = s_p[lidx_p[it]];
+      op.store_p(gidx_p[it], o_p[lidx_p[it]], v, pre_p[it]);
     }
   }
 }

@@ -73,6 +73,39 @@ class EngineBase {
   virtual smg_status solve(double *x, const double *b, double rtol, int maxit, smg_solve_info *info) = 0;
   virtual smg_status solve_stationary(double *x, const double *b, double rtol, int maxit, smg_solve_info *info) = 0;
   virtual void node_coordinates(int l, double *xyz) = 0;
+  virtual void invalidate_graphs() {}
+  bool use_graphs = true;
+
+  // Optional kernel timing: HIP events recorded around each operator-kernel
+  // launch on the launch stream, aggregated per kernel key.
+  struct ProfRec {
+    std::string key;
+    hipEvent_t a, b;
+    double bytes;  // algorithmic HBM bytes of the launch
+  };
+  bool profiling = false;
+  std::vector<ProfRec> prof;
+  std::vector<hipEvent_t> event_pool;
+  size_t event_used = 0;
+  hipEvent_t next_event() {
+    if (event_used == event_pool.size()) {
+      hipEvent_t e;
+      hipError_t r = hipEventCreate(&e);
+      if (r != hipSuccess) throw Error{SMG_EDEVICE, std::string("hipEventCreate: ") + hipGetErrorString(r)};
+      event_pool.push_back(e);
+    }
+    return event_pool[event_used++];
+  }
+  void profile_reset() {
+    prof.clear();
+    event_used = 0;
+  }
+  void destroy_events() {
+    for (hipEvent_t e : event_pool) (void)hipEventDestroy(e);
+    event_pool.clear();
+    event_used = 0;
+  }
+  std::string profile_report();
 
   std::vector<void *> allocations;
   template <typename T>
@@ -85,6 +118,7 @@ class EngineBase {
     return (T *)p;
   }
   void free_all() {
+    destroy_events();
     for (void *p : allocations) (void)hipFree(p);
     allocations.clear();
   }

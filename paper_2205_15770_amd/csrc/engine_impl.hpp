@@ -62,6 +62,60 @@ class EngineT : public EngineBase {
   float *b32 = nullptr, *x32 = nullptr;
   double *lz[4] = {nullptr, nullptr, nullptr, nullptr};  // Lanczos temporaries
   double mp1_sum = 0;
+  // The preconditioning cycle (zero initial guess, fixed internal buffers) is
+  // captured once per precision into a HIP graph and replayed; this removes
+  // the host launch cost of its several hundred small kernels.
+  struct CycleGraph {
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+  };
+  CycleGraph cg[2];
+  hipStream_t cap_stream = nullptr;
+  double *b64 = nullptr, *x64 = nullptr;
+
+  void invalidate_graphs() override {
+    for (CycleGraph &c : cg) {
+      if (c.exec) (void)hipGraphExecDestroy(c.exec);
+      if (c.graph) (void)hipGraphDestroy(c.graph);
+      c.exec = nullptr;
+      c.graph = nullptr;
+    }
+  }
+  ~EngineT() override {
+    invalidate_graphs();
+    if (cap_stream) (void)hipStreamDestroy(cap_stream);
+  }
+
+  // x_L = cycle(0, b_L) for the internal buffers of precision `dt`, by graph
+  // replay (captured on first use) or, while kernel timing is on, eagerly.
+  void cycle_from_zero(int dt) {
+    if (profiling || !use_graphs) {
+      if (dt == SMG_F32) { vset<float>(x32, 0.0f, lv[L].N); cycle_t<float>(L, x32, b32, true); }
+      else { vset<double>(x64, 0.0, lv[L].N); cycle_t<double>(L, x64, b64, true); }
+      return;
+    }
+    CycleGraph &c = cg[dt];
+    if (!c.exec) {
+      if (!cap_stream) SMG_HIP(hipStreamCreateWithFlags(&cap_stream, hipStreamNonBlocking));
+      hipStream_t saved = stream;
+      stream = cap_stream;
+      SMG_HIP(hipStreamBeginCapture(cap_stream, hipStreamCaptureModeThreadLocal));
+      try {
+        if (dt == SMG_F32) { vset<float>(x32, 0.0f, lv[L].N); cycle_t<float>(L, x32, b32, true); }
+        else { vset<double>(x64, 0.0, lv[L].N); cycle_t<double>(L, x64, b64, true); }
+      } catch (...) {
+        hipGraph_t g = nullptr;
+        (void)hipStreamEndCapture(cap_stream, &g);
+        if (g) (void)hipGraphDestroy(g);
+        stream = saved;
+        throw;
+      }
+      SMG_HIP(hipStreamEndCapture(cap_stream, &c.graph));
+      stream = saved;
+      SMG_HIP(hipGraphInstantiate(&c.exec, c.graph, nullptr, nullptr, 0));
+    }
+    SMG_HIP(hipGraphLaunch(c.exec, stream));
+  }
 
   // ---------------------------------------------------------------- helpers
   template <typename T>
@@ -111,8 +165,24 @@ class EngineT : public EngineBase {
   template <typename T, int BLK, class Op>
   void tile(const LevelGeom<T, DIM, K> &g, const Op &op) {
     const unsigned nblk = (unsigned)(g.tiles[0] * g.tiles[1] * g.tiles[2]);
+    hipEvent_t ea = nullptr, eb = nullptr;
+    if (profiling) {
+      ea = next_event();
+      eb = next_event();
+      SMG_HIP(hipEventRecord(ea, stream));
+    }
     hipLaunchKernelGGL((tile_apply_kernel<DIM, K, T, BLK, Op, TX, TY, TZ>), dim3(nblk), dim3(TX * TY * TZ), 0, stream, g, op);
     check_launch();
+    if (profiling) {
+      SMG_HIP(hipEventRecord(eb, stream));
+      char key[160];
+      std::snprintf(key, sizeof(key), "%s/v%d/blk%d/%s/%dx%dx%d", Op::NAME, Op::VARIANT, BLK,
+                    std::is_same<T, double>::value ? "f64" : "f32", g.n[0], g.n[1], g.n[2]);
+      constexpr bool NU = (BLK & (BLK_A | BLK_MASS | BLK_B)) != 0, NP = (BLK & (BLK_BT | BLK_C)) != 0;
+      constexpr bool OU = (BLK & (BLK_A | BLK_MASS | BLK_BT)) != 0, OP = (BLK & (BLK_B | BLK_C)) != 0;
+      const double bytes = op.algo_bytes(NU, NP, OU, OP, (double)(DIM * g.Nv), (double)g.Np);
+      prof.push_back(ProfRec{key, ea, eb, bytes});
+    }
   }
 
   bool has_c() const { return desc.c_pressure != 0.0; }
@@ -400,7 +470,7 @@ class EngineT : public EngineBase {
   void multidot(const double *Vb, int64_t ldv, int nv, const double *w, int64_t n, double *outdev) {
     hipLaunchKernelGGL((k_multidot_partial<double>), dim3(RB), dim3(VB), 0, stream, Vb, (i64)ldv, nv, w, (i64)n, partial);
     check_launch();
-    hipLaunchKernelGGL(k_partial_finish, dim3((nv + 63) / 64), dim3(64), 0, stream, partial, RB, nv, outdev);
+    hipLaunchKernelGGL(k_partial_finish, dim3(nv), dim3(VB), 0, stream, partial, RB, nv, outdev);
     check_launch();
   }
   double dot(const double *a, const double *b, int64_t n) {
@@ -684,7 +754,7 @@ class EngineT : public EngineBase {
     vset<double>(ones, 1.0, nmax);
     for (int i = 0; i < 4; ++i) lz[i] = dalloc<double>(nmax);
     partial = dalloc<double>((int64_t)RB * 256);
-    dvec = dalloc<double>(256);
+    dvec = dalloc<double>(1024);
     // diagonals and M_p 1 on every level
     for (int l = 0; l <= L; ++l) {
       LevelInfo &I = lv[l];
@@ -721,6 +791,8 @@ class EngineT : public EngineBase {
     Z = dalloc<double>((int64_t)restart * lv[L].N);
     b32 = dalloc<float>(lv[L].N);
     x32 = dalloc<float>(lv[L].N);
+    b64 = dalloc<double>(lv[L].N);
+    x64 = dalloc<double>(lv[L].N);
     SMG_HIP(hipStreamSynchronize(stream));
   }
 
@@ -770,13 +842,15 @@ class EngineT : public EngineBase {
   void precondition(const double *v, double *z) {
     const int64_t N = lv[L].N;
     if (desc.precision == SMG_PRECOND_F64) {
-      vset<double>(z, 0.0, N);
-      cycle_t<double>(L, z, v, true);
+      hipLaunchKernelGGL((k_copy<double, double>), dim3(grid_for(N)), dim3(VB), 0, stream, b64, v, (i64)N);
+      check_launch();
+      cycle_from_zero(SMG_F64);
+      hipLaunchKernelGGL((k_copy<double, double>), dim3(grid_for(N)), dim3(VB), 0, stream, z, (const double *)x64, (i64)N);
+      check_launch();
     } else {
       hipLaunchKernelGGL((k_copy<float, double>), dim3(grid_for(N)), dim3(VB), 0, stream, b32, v, (i64)N);
       check_launch();
-      vset<float>(x32, 0.0f, N);
-      cycle_t<float>(L, x32, b32, true);
+      cycle_from_zero(SMG_F32);
       hipLaunchKernelGGL((k_copy<double, float>), dim3(grid_for(N)), dim3(VB), 0, stream, z, (const float *)x32, (i64)N);
       check_launch();
     }
@@ -805,7 +879,7 @@ class EngineT : public EngineBase {
       double beta = norm(V, N);
       rel = beta / bnorm;
       record(rel);
-      std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), gv(m + 1), y(m), h(m + 1);
+      std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), gv(m + 1), y(m), hbuf(513);
       while (it < maxit && rel > rtol) {
         hipLaunchKernelGGL((k_jacobi<double>), dim3(grid_for(N)), dim3(VB), 0, stream, V, (const double *)nullptr, 1.0 / beta, unit_vec(N), (const double *)V, (i64)N);
         check_launch();
@@ -818,21 +892,23 @@ class EngineT : public EngineBase {
           double *vj = V + (int64_t)j * N, *zj = Z + (int64_t)j * N, *w = V + (int64_t)(j + 1) * N;
           precondition(vj, zj);
           vmult_t<double>(L, zj, w);
-          // classical Gram-Schmidt, twice
+          // classical Gram-Schmidt, twice; coefficients and the norm stay on
+          // the device until one copy per iteration
           for (int pass = 0; pass < 2; ++pass) {
-            multidot(V, N, j + 1, w, N, dvec);
-            hipLaunchKernelGGL((k_multi_axpy<double>), dim3(grid_for(N)), dim3(VB), 0, stream, w, (const double *)V, (i64)N, j + 1, (const double *)dvec, -1.0, (i64)N);
+            double *hd = dvec + 256 * pass;
+            multidot(V, N, j + 1, w, N, hd);
+            hipLaunchKernelGGL((k_multi_axpy<double>), dim3(grid_for(N)), dim3(VB), 0, stream, w, (const double *)V, (i64)N, j + 1, (const double *)hd, -1.0, (i64)N);
             check_launch();
-            SMG_HIP(hipMemcpyAsync(h.data(), dvec, sizeof(double) * (j + 1), hipMemcpyDeviceToHost, stream));
-            SMG_HIP(hipStreamSynchronize(stream));
-            for (int i = 0; i <= j; ++i) H[(size_t)i * m + j] += h[i];
           }
-          const double hn = norm(w, N);
+          multidot(w, 0, 1, w, N, dvec + 512);
+          hipLaunchKernelGGL((k_scale_inv_sqrt<double>), dim3(grid_for(N)), dim3(VB), 0, stream, w, (const double *)(dvec + 512), (i64)N);
+          check_launch();
+          SMG_HIP(hipMemcpyAsync(hbuf.data(), dvec, sizeof(double) * 513, hipMemcpyDeviceToHost, stream));
+          SMG_HIP(hipStreamSynchronize(stream));
+          for (int i = 0; i <= j; ++i) H[(size_t)i * m + j] += hbuf[i] + hbuf[256 + i];
+          const double hn = std::sqrt(std::max(hbuf[512], 0.0));
           H[(size_t)(j + 1) * m + j] = hn;
           if (!finite(hn)) { broke = true; break; }
-          if (hn > 0)
-            hipLaunchKernelGGL((k_jacobi<double>), dim3(grid_for(N)), dim3(VB), 0, stream, w, (const double *)nullptr, 1.0 / hn, unit_vec(N), (const double *)w, (i64)N);
-          check_launch();
           for (int i = 0; i < j; ++i) {
             const double t = cs[i] * H[(size_t)i * m + j] + sn[i] * H[(size_t)(i + 1) * m + j];
             H[(size_t)(i + 1) * m + j] = -sn[i] * H[(size_t)i * m + j] + cs[i] * H[(size_t)(i + 1) * m + j];

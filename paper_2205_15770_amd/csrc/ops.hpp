@@ -9,37 +9,62 @@ namespace smg {
 // y = (block of K) x
 template <typename T>
 struct OpApply {
+  static constexpr const char *NAME = "apply";
+  static constexpr int VARIANT = 0;
   static constexpr bool ZERO_BC = true;
   const T *xu, *xp;
   T *yu, *yp;
+  struct Pre {};
   __device__ T load_u(i64 i) const { return xu[i]; }
   __device__ T load_p(i64 i) const { return xp[i]; }
-  __device__ void store_u(i64 i, T t, T, bool) const { yu[i] = t; }
-  __device__ void store_p(i64 i, T t, T) const { yp[i] = t; }
+  __device__ Pre fetch_u(i64) const { return Pre{}; }
+  __device__ Pre fetch_p(i64) const { return Pre{}; }
+  __device__ void store_u(i64 i, T t, T, bool, const Pre &) const { yu[i] = t; }
+  __device__ void store_p(i64 i, T t, T, const Pre &) const { yp[i] = t; }
+  // algorithmic HBM bytes of one launch: every vector read or written once
+  double algo_bytes(bool need_u, bool need_p, bool out_u, bool out_p, double nu, double np) const {
+    return sizeof(T) * ((need_u ? nu : 0) + (need_p ? np : 0) + (out_u ? nu : 0) + (out_p ? np : 0));
+  }
 };
 
 // r = b - (block of K) x
 template <typename T>
 struct OpResidual {
+  static constexpr const char *NAME = "residual";
+  static constexpr int VARIANT = 0;
   static constexpr bool ZERO_BC = true;
   const T *xu, *xp, *bu, *bp;
   T *ru, *rp;
+  struct Pre {
+    T b;
+  };
   __device__ T load_u(i64 i) const { return xu[i]; }
   __device__ T load_p(i64 i) const { return xp[i]; }
-  __device__ void store_u(i64 i, T t, T, bool) const { ru[i] = bu[i] - t; }
-  __device__ void store_p(i64 i, T t, T) const { rp[i] = bp[i] - t; }
+  __device__ Pre fetch_u(i64 i) const { return Pre{bu[i]}; }
+  __device__ Pre fetch_p(i64 i) const { return Pre{bp[i]}; }
+  __device__ void store_u(i64 i, T t, T, bool, const Pre &q) const { ru[i] = q.b - t; }
+  __device__ void store_p(i64 i, T t, T, const Pre &q) const { rp[i] = q.b - t; }
+  double algo_bytes(bool need_u, bool need_p, bool out_u, bool out_p, double nu, double np) const {
+    return sizeof(T) * ((need_u ? nu : 0) + (need_p ? np : 0) + (out_u ? 2 * nu : 0) + (out_p ? 2 * np : 0));
+  }
 };
 
 // y = M_v f on every node, 0 on Dirichlet rows (load vector of a nodal field)
 template <typename T>
 struct OpMass {
+  static constexpr const char *NAME = "mass";
+  static constexpr int VARIANT = 0;
   static constexpr bool ZERO_BC = false;
   const T *f;
   T *y;
+  struct Pre {};
   __device__ T load_u(i64 i) const { return f[i]; }
   __device__ T load_p(i64) const { return 0; }
-  __device__ void store_u(i64 i, T t, T, bool bc) const { y[i] = bc ? T(0) : t; }
-  __device__ void store_p(i64, T, T) const {}
+  __device__ Pre fetch_u(i64) const { return Pre{}; }
+  __device__ Pre fetch_p(i64) const { return Pre{}; }
+  __device__ void store_u(i64 i, T t, T, bool bc, const Pre &) const { y[i] = bc ? T(0) : t; }
+  __device__ void store_p(i64, T, T, const Pre &) const {}
+  double algo_bytes(bool, bool, bool, bool, double nu, double) const { return sizeof(T) * 2 * nu; }
 };
 
 // One step of the Chebyshev-acceleration recurrence for A (velocity vectors),
@@ -49,6 +74,8 @@ struct OpMass {
 // LAST:  out = base + s (x_{k} + d_{k}) instead of storing r, x, d.
 template <typename T, bool FIRST, bool LAST>
 struct OpChebA {
+  static constexpr const char *NAME = "cheb_A";
+  static constexpr int VARIANT = (FIRST ? 1 : 0) + (LAST ? 2 : 0);
   static constexpr bool ZERO_BC = true;
   const T *rin;      // r_0 (FIRST) or r_i
   const T *dinv;     // D_A^-1
@@ -58,29 +85,47 @@ struct OpChebA {
   const T *base;     // LAST: optional base vector (nullptr = 0)
   T *out;            // LAST
   T inv_theta, c1, c2, s;
+  struct Pre {
+    T r, x, dinv, base;
+  };
   __device__ T load_u(i64 i) const {
     if constexpr (FIRST) return dinv[i] * rin[i] * inv_theta;
     else return d[i];
   }
   __device__ T load_p(i64) const { return 0; }
-  __device__ void store_u(i64 i, T t, T v, bool) const {
-    const T rn = rin[i] - t;
-    const T xn = FIRST ? v : x[i] + v;
-    const T dn = c1 * v + c2 * dinv[i] * rn;
+  __device__ Pre fetch_u(i64 i) const {
+    Pre q;
+    q.r = rin[i];
+    q.x = FIRST ? T(0) : x[i];
+    q.dinv = dinv[i];
+    q.base = (LAST && base) ? base[i] : T(0);
+    return q;
+  }
+  __device__ Pre fetch_p(i64) const { return Pre{}; }
+  __device__ void store_u(i64 i, T t, T v, bool, const Pre &q) const {
+    const T rn = q.r - t;
+    const T xn = q.x + v;
+    const T dn = c1 * v + c2 * q.dinv * rn;
     if constexpr (LAST) {
-      out[i] = (base ? base[i] : T(0)) + s * (xn + dn);
+      out[i] = q.base + s * (xn + dn);
     } else {
       r_out[i] = rn;
       x_out[i] = xn;
       d_out[i] = dn;
     }
   }
-  __device__ void store_p(i64, T, T) const {}
+  __device__ void store_p(i64, T, T, const Pre &) const {}
+  double algo_bytes(bool, bool, bool, bool, double nu, double) const {
+    const double reads = FIRST ? 2 : 4, writes = LAST ? (base ? 2 : 1) : 3;
+    return sizeof(T) * nu * (reads + writes);
+  }
 };
 
 // q = B^T d with d = D_S^-1 r / theta formed while loading (FIRST) or d given.
 template <typename T, bool FIRST>
 struct OpGrad {
+  static constexpr const char *NAME = "grad";
+  static constexpr int VARIANT = FIRST ? 1 : 0;
   static constexpr bool ZERO_BC = true;
   const T *rp, *dinv_s, *d;
   T inv_theta;
@@ -90,8 +135,14 @@ struct OpGrad {
     if constexpr (FIRST) return dinv_s[i] * rp[i] * inv_theta;
     else return d[i];
   }
-  __device__ void store_u(i64 i, T t, T, bool) const { q[i] = t; }
-  __device__ void store_p(i64, T, T) const {}
+  struct Pre {};
+  __device__ Pre fetch_u(i64) const { return Pre{}; }
+  __device__ Pre fetch_p(i64) const { return Pre{}; }
+  __device__ void store_u(i64 i, T t, T, bool, const Pre &) const { q[i] = t; }
+  __device__ void store_p(i64, T, T, const Pre &) const {}
+  double algo_bytes(bool, bool, bool, bool, double nu, double np) const {
+    return sizeof(T) * ((FIRST ? 2 : 1) * np + nu);
+  }
 };
 
 // Chebyshev step for S~ = B A_hat^-1 B^T + C (pressure vectors): the kernel
@@ -99,6 +150,8 @@ struct OpGrad {
 // LAST: dp = tau (x_k + d_k) is stored and added to the pressure iterate.
 template <typename T, bool FIRST, bool LAST>
 struct OpChebS {
+  static constexpr const char *NAME = "cheb_S";
+  static constexpr int VARIANT = (FIRST ? 1 : 0) + (LAST ? 2 : 0);
   static constexpr bool ZERO_BC = true;
   const T *w;        // velocity input
   const T *rin;      // r_0 (FIRST) or r_i
@@ -113,34 +166,61 @@ struct OpChebS {
     if constexpr (FIRST) return dinv_s[i] * rin[i] * inv_theta;
     else return d[i];
   }
-  __device__ void store_u(i64, T, T, bool) const {}
-  __device__ void store_p(i64 i, T t, T) const {
-    const T di = FIRST ? dinv_s[i] * rin[i] * inv_theta : d[i];
-    const T rn = rin[i] - t;
-    const T xn = FIRST ? di : x[i] + di;
-    const T dn = c1 * di + c2 * dinv_s[i] * rn;
+  struct Pre {
+    T r, x, d, dinv, p;
+  };
+  __device__ Pre fetch_u(i64) const { return Pre{}; }
+  __device__ Pre fetch_p(i64 i) const {
+    Pre q;
+    q.r = rin[i];
+    q.dinv = dinv_s[i];
+    q.x = FIRST ? T(0) : x[i];
+    q.d = FIRST ? q.dinv * q.r * inv_theta : d[i];
+    q.p = (LAST && p) ? p[i] : T(0);
+    return q;
+  }
+  __device__ void store_u(i64, T, T, bool, const Pre &) const {}
+  __device__ void store_p(i64 i, T t, T, const Pre &q) const {
+    const T di = q.d;
+    const T rn = q.r - t;
+    const T xn = q.x + di;
+    const T dn = c1 * di + c2 * q.dinv * rn;
     if constexpr (LAST) {
       const T delta = tau * (xn + dn);
       dp[i] = delta;
-      if (p) p[i] += delta;
+      if (p) p[i] = q.p + delta;
     } else {
       r_out[i] = rn;
       x_out[i] = xn;
       d_out[i] = dn;
     }
   }
+  double algo_bytes(bool, bool, bool, bool, double nu, double np) const {
+    const double reads = FIRST ? 2 : 4, writes = LAST ? (p ? 3 : 1) : 3;
+    return sizeof(T) * (nu + np * (reads + writes));
+  }
 };
 
 // r_p = B u - C p - g, the argument of the second Uzawa update.
 template <typename T>
 struct OpDivResidual {
+  static constexpr const char *NAME = "div_residual";
+  static constexpr int VARIANT = 0;
   static constexpr bool ZERO_BC = true;
   const T *u, *p_in, *g;
   T *rp;
   __device__ T load_u(i64 i) const { return u[i]; }
   __device__ T load_p(i64 i) const { return p_in[i]; }
-  __device__ void store_u(i64, T, T, bool) const {}
-  __device__ void store_p(i64 i, T t, T) const { rp[i] = t - (g ? g[i] : T(0)); }
+  struct Pre {
+    T g;
+  };
+  __device__ Pre fetch_u(i64) const { return Pre{}; }
+  __device__ Pre fetch_p(i64 i) const { return Pre{g ? g[i] : T(0)}; }
+  __device__ void store_u(i64, T, T, bool, const Pre &) const {}
+  __device__ void store_p(i64 i, T t, T, const Pre &q) const { rp[i] = t - q.g; }
+  double algo_bytes(bool, bool need_p, bool, bool, double nu, double np) const {
+    return sizeof(T) * (nu + (need_p ? np : 0) + (g ? np : 0) + np);
+  }
 };
 
 }  // namespace smg

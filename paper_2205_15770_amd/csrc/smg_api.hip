@@ -1,9 +1,36 @@
 // C ABI of the multigrid library (declarations and contracts in include/smg.h).
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <string>
 
+#include <map>
+
 #include "engine.hpp"
+
+std::string smg::EngineBase::profile_report() {
+  SMG_HIP(hipStreamSynchronize(stream));
+  struct Agg {
+    long count = 0;
+    double ms = 0.0, bytes = 0.0;
+  };
+  std::map<std::string, Agg> agg;
+  for (const ProfRec &r : prof) {
+    float ms = 0.0f;
+    SMG_HIP(hipEventElapsedTime(&ms, r.a, r.b));
+    Agg &e = agg[r.key];
+    e.count += 1;
+    e.ms += ms;
+    e.bytes += r.bytes;
+  }
+  std::string out;
+  char line[320];
+  for (const auto &kv : agg) {
+    std::snprintf(line, sizeof(line), "%s %ld %.6f %.6e\n", kv.first.c_str(), kv.second.count, kv.second.ms, kv.second.bytes);
+    out += line;
+  }
+  return out;
+}
 
 namespace smg {
 EngineBase *make_engine_2_2();
@@ -169,6 +196,7 @@ smg_status smg_destroy(smg_ctx *ctx) {
   if (!ctx) return SMG_OK;
   if (ctx->eng) {
     (void)hipStreamSynchronize(ctx->eng->stream);
+    ctx->eng->invalidate_graphs();
     ctx->eng->free_all();
     delete ctx->eng;
   }
@@ -248,6 +276,7 @@ smg_status smg_set_eigs(smg_ctx *ctx, int level, double beta_A, double beta_S) {
     return fail(SMG_EINVAL, "eigenvalue bounds must be finite and > 0");
   ctx->eng->lv[level].beta_A = beta_A;
   ctx->eng->lv[level].beta_S = beta_S;
+  ctx->eng->invalidate_graphs();  // the bounds are baked into the captured cycle
   return SMG_OK;
 }
 
@@ -344,6 +373,31 @@ smg_status smg_node_coordinates(const smg_ctx *ctx, int level, double *xyz) {
   if (s == SMG_OK) s = check_ptrs({xyz});
   if (s != SMG_OK) return s;
   SMG_TRY(ctx->eng->node_coordinates(level, xyz));
+}
+
+smg_status smg_profile(smg_ctx *ctx, int enable) {
+  smg_status s = check_ctx(ctx);
+  if (s != SMG_OK) return s;
+  SMG_TRY({
+    SMG_HIP(hipStreamSynchronize(ctx->eng->stream));
+    ctx->eng->profile_reset();
+    ctx->eng->profiling = enable != 0;
+  });
+}
+
+smg_status smg_profile_report(smg_ctx *ctx, char *buf, int64_t cap, int64_t *len) {
+  smg_status s = check_ctx(ctx);
+  if (s != SMG_OK) return s;
+  if (cap < 0) return fail(SMG_EINVAL, "cap must be >= 0");
+  SMG_TRY({
+    std::string r = ctx->eng->profile_report();
+    if (len) *len = (int64_t)r.size();
+    if (buf && cap > 0) {
+      const size_t n = std::min((size_t)(cap - 1), r.size());
+      std::memcpy(buf, r.data(), n);
+      buf[n] = '\0';
+    }
+  });
 }
 
 const char *smg_last_error(void) { return g_last_error.c_str(); }

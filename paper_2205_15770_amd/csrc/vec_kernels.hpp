@@ -86,13 +86,21 @@ __global__ void __launch_bounds__(VB) k_multidot_partial(const T *V, i64 ldv, in
   }
 }
 
-// out[j] = sum_b partial[b * nv + j]  (one thread per j, fixed order)
-static __global__ void k_partial_finish(const double *partial, int nblocks, int nv, double *out) {
-  const int j = blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= nv) return;
+// out[j] = sum_b partial[b * nv + j]: one block per j, fixed-order tree sum.
+static __global__ void __launch_bounds__(VB) k_partial_finish(const double *partial, int nblocks, int nv, double *out) {
+  const int j = blockIdx.x;
   double s = 0.0;
-  for (int b = 0; b < nblocks; ++b) s += partial[(i64)b * nv + j];
-  out[j] = s;
+  for (int b = threadIdx.x; b < nblocks; b += VB) s += partial[(i64)b * nv + j];
+  s = block_sum<double>(s);
+  if (threadIdx.x == 0) out[j] = s;
+}
+
+// w *= 1 / sqrt(s2[0])  (normalisation by a norm that stays on the device)
+template <typename T>
+__global__ void k_scale_inv_sqrt(T *w, const double *s2, i64 n) {
+  const double v = s2[0];
+  const double f = v > 0.0 ? 1.0 / sqrt(v) : 0.0;
+  SMG_GRID_LOOP(i, n) w[i] = (T)((double)w[i] * f);
 }
 
 // w -= sum_j h[j] V_j  (h on the device)
