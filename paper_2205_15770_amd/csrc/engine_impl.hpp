@@ -171,7 +171,10 @@ class EngineT : public EngineBase {
       eb = next_event();
       SMG_HIP(hipEventRecord(ea, stream));
     }
-    hipLaunchKernelGGL((tile_apply_kernel<DIM, K, T, BLK, Op, TX, TY, TZ>), dim3(nblk), dim3(TX * TY * TZ), 0, stream, g, op);
+    if constexpr (DIM == 2)
+      hipLaunchKernelGGL((tile2d_kernel<K, T, BLK, Op, TX, TY>), dim3(nblk), dim3(TX * TY), 0, stream, g, op);
+    else
+      hipLaunchKernelGGL((tile_apply_kernel<DIM, K, T, BLK, Op, TX, TY, TZ>), dim3(nblk), dim3(TX * TY * TZ), 0, stream, g, op);
     check_launch();
     if (profiling) {
       SMG_HIP(hipEventRecord(eb, stream));
