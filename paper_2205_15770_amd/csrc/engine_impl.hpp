@@ -5,7 +5,7 @@
 #include <chrono>
 #include <cstdio>
 
-#include "cell_kernel.hpp"
+#include "cell_kernel3d.hpp"
 #include "engine.hpp"
 #include "ops.hpp"
 #include "setup_kernels.hpp"
@@ -171,10 +171,25 @@ class EngineT : public EngineBase {
       eb = next_event();
       SMG_HIP(hipEventRecord(ea, stream));
     }
-    if constexpr (DIM == 2)
+    if constexpr (DIM == 2) {
       hipLaunchKernelGGL((tile2d_kernel<K, T, BLK, Op, TX, TY>), dim3(nblk), dim3(TX * TY), 0, stream, g, op);
-    else
-      hipLaunchKernelGGL((tile_apply_kernel<DIM, K, T, BLK, Op, TX, TY, TZ>), dim3(nblk), dim3(TX * TY * TZ), 0, stream, g, op);
+    } else {
+      // 8 x 8 cell columns per wave, one wave per output field; the z extent
+      // is cut into chunks so that the launch has >= ~2048 waves when the
+      // level is large enough (two per SIMD), chunks of >= 2 cells.
+      constexpr int NF = ((BLK & (BLK_A | BLK_MASS | BLK_BT)) ? 3 : 0) + ((BLK & (BLK_B | BLK_C)) ? 1 : 0);
+      LevelGeom<T, DIM, K> g3 = g;
+      g3.tiles[0] = (g.n[0] + 6) / 7;
+      g3.tiles[1] = (g.n[1] + 6) / 7;
+      const int cols = g3.tiles[0] * g3.tiles[1] * NF;
+      int nzc = (2048 + cols - 1) / cols;
+      const int zmax = (g.n[2] + 1) / 2;
+      nzc = nzc < 1 ? 1 : (nzc > zmax ? zmax : nzc);
+      const int zlen = (g.n[2] + nzc - 1) / nzc;
+      g3.tiles[2] = (g.n[2] + zlen - 1) / zlen;
+      const unsigned nb3 = (unsigned)(cols * g3.tiles[2]);
+      hipLaunchKernelGGL((tile3d_kernel<K, T, BLK, Op, 8, 8>), dim3(nb3), dim3(64), 0, stream, g3, op);
+    }
     check_launch();
     if (profiling) {
       SMG_HIP(hipEventRecord(eb, stream));
