@@ -18,59 +18,128 @@
 // shuffles, the z = K face to the next cell of the column in registers.  After
 // that a cell holds the complete sums of its nodes with local indices [0, K)
 // in every direction (plus the domain high faces), which it writes through the
-// epilogue functor.  The DoFs of the next cell layer are requested before the
-// current layer is computed; the z = 0 plane of a layer is the z = K plane of
-// the layer below and is not read again.
+// epilogue functor.  The DoFs of the next cell (velocity waves: the next
+// layer; pressure waves: the next velocity component) are requested before
+// the current one is computed.
+//
+// Cell matrices: the 1D reference matrices are compile-time literals; on a
+// box cell of widths (h_x, h_y, h_z)
+//   A_cell = mu [sKx Kr(x)Mr(x)Mr + sKy Mr(x)Kr(x)Mr + sKz Mr(x)Mr(x)Kr]
+//            + gamma rho sM Mr(x)Mr(x)Mr,
+//   B_c    = -sB_c (Gr in direction c, Nr in the others),  C = cp sM Mpr^(x)3,
+// with sKx = h_y h_z / h_x (cyclic), sM = h_x h_y h_z, sB_c = prod_{a != c} h_a.
 #pragma once
 #include "cell_kernel.hpp"
+#include "fe1d_const.hpp"
 
 namespace smg {
+
+// Kernel parameters of one level (3D column sweep).
+template <typename T>
+struct Geo3 {
+  int n[3];       // cells per direction
+  int vd[3];      // velocity lattice extent per direction
+  int pd[3];      // pressure lattice extent per direction
+  int tiles[3];   // 8x8 column tiles in x, y; z chunks
+  uint32_t nv_bytes;  // bytes of one velocity component vector
+  T mu, gr, cp;   // viscosity (if mu_cell == nullptr), gamma rho, C = cp M_p
+  const T *mu_cell;
+  T sKx, sKy;     // h_y h_z / h_x, h_x h_z / h_y
+  T rz;           // sKz / sKy = h_y^2 / h_z^2
+  T sM;           // h_x h_y h_z
+  T sB[3];        // h_y h_z, h_x h_z, h_x h_y
+};
 
 template <int K, typename T>
 struct Column3D {
   static constexpr int NV = K + 1, NP = K;
-  const LevelGeom<T, 3, K> &g;
-  int gcx, gcy;      // cell column
-  bool active;       // column inside the mesh
-  bool bx, by;       // column's low node on the x / y boundary (per node below)
-  __device__ i64 vidx(int c, int gx, int gy, int gz) const {
-    return (i64)c * g.Nv + gx + (i64)g.vd[0] * (gy + (i64)g.vd[1] * gz);
+  static constexpr uint32_t ST = sizeof(T);
+  const Geo3<T> &g;
+  int gcx, gcy;        // cell column (may lie outside the mesh for halo lanes)
+  bool active;         // column inside the mesh
+  bool bxl, bxh, byl, byh;  // column touches the low / high x, y boundary
+  uint32_t base_u;     // byte offset of the column's first velocity node
+  uint32_t base_p;     // byte offset of the column's first pressure node
+  uint32_t suy, suz, spy, spz;  // byte strides of the velocity / pressure lattices
+  uint32_t cell0, cell_sz;      // cell index of the column's first cell, cells per layer
+  __device__ Column3D(const Geo3<T> &g_, int cx, int cy) : g(g_), gcx(cx), gcy(cy) {
+    active = cx >= 0 && cx < g.n[0] && cy >= 0 && cy < g.n[1];
+    bxl = cx == 0;
+    bxh = cx == g.n[0] - 1;
+    byl = cy == 0;
+    byh = cy == g.n[1] - 1;
+    // halo lanes outside the mesh read a valid column and discard the values
+    const int ax = cx < 0 ? 0 : (cx >= g.n[0] ? g.n[0] - 1 : cx);
+    const int ay = cy < 0 ? 0 : (cy >= g.n[1] ? g.n[1] - 1 : cy);
+    suy = ST * (uint32_t)g.vd[0];
+    suz = suy * (uint32_t)g.vd[1];
+    spy = ST * (uint32_t)g.pd[0];
+    spz = spy * (uint32_t)g.pd[1];
+    base_u = ST * (uint32_t)(K * ax) + suy * (uint32_t)(K * ay);
+    base_p = ST * (uint32_t)((K - 1) * ax) + spy * (uint32_t)((K - 1) * ay);
+    cell0 = (uint32_t)ax + (uint32_t)g.n[0] * (uint32_t)ay;
+    cell_sz = (uint32_t)g.n[0] * (uint32_t)g.n[1];
   }
-  __device__ i64 pidx(int gx, int gy, int gz) const {
-    return gx + (i64)g.pd[0] * (gy + (i64)g.pd[1] * gz);
+  __device__ T mu_at(int cz) const {
+    if (g.mu_cell != nullptr) return g.mu_cell[cell0 + cell_sz * (uint32_t)cz];
+    return g.mu;
   }
-  __device__ bool vbc(int gx, int gy, int gz) const {
-    return on_box_boundary(gx, g.vd[0]) || on_box_boundary(gy, g.vd[1]) || on_box_boundary(gz, g.vd[2]);
+  // node (x, y, z) of cell layer cz, velocity component c
+  __device__ BOff u_at(int c, int cz, int x, int y, int z) const {
+    return BOff{(uint32_t)c * g.nv_bytes + base_u + suz * (uint32_t)(K * cz + z) + suy * (uint32_t)y,
+                ST * (uint32_t)x};
   }
-  // planes [Z0, NV) of velocity component c of cell layer cz into dst[z - Z0]
+  __device__ BOff p_at(int cz, int x, int y, int z) const {
+    return BOff{base_p + spz * (uint32_t)((K - 1) * cz + z) + spy * (uint32_t)y, ST * (uint32_t)x};
+  }
+  // Dirichlet test of local velocity node (x, y, z) of layer cz (bitwise
+  // forms: no short-circuit branches on lane-varying flags)
+  __device__ bool vbc(int cz, int x, int y, int z) const {
+    return ((x == 0) & bxl) | ((x == K) & bxh) | ((y == 0) & byl) | ((y == K) & byh) |
+           ((z == 0) & (cz == 0)) | ((z == K) & (cz == g.n[2] - 1));
+  }
+  // raw loads: planes [Z0, Z0 + NZ) of velocity component c of layer cz
   template <int Z0, class Op, int NZ>
   __device__ void load_u(const Op &op, int c, int cz, T (&dst)[NZ][NV][NV]) const {
-    static_assert(NZ == NV - Z0, "plane count");
 #pragma unroll
-    for (int z = Z0; z < NV; ++z)
+    for (int z = 0; z < NZ; ++z)
+#pragma unroll
+      for (int y = 0; y < NV; ++y)
+#pragma unroll
+        for (int x = 0; x < NV; ++x) dst[z][y][x] = op.load_u(u_at(c, cz, x, y, Z0 + z));
+  }
+  template <int Z0, class Op, int NZ>
+  __device__ void load_p(const Op &op, int cz, T (&dst)[NZ][NP][NP]) const {
+#pragma unroll
+    for (int z = 0; z < NZ; ++z)
+#pragma unroll
+      for (int y = 0; y < NP; ++y)
+#pragma unroll
+        for (int x = 0; x < NP; ++x) dst[z][y][x] = op.load_p(p_at(cz, x, y, Z0 + z));
+  }
+  // zero what must not enter the cell operator: inactive columns and (ZERO_BC)
+  // Dirichlet nodes.  Applied where the loaded values are first used, not
+  // next to the loads, so the loads stay unconditional and early.
+  template <bool ZERO_BC, int Z0, int NZ>
+  __device__ void mask_u(int cz, T (&a)[NZ][NV][NV]) const {
+#pragma unroll
+    for (int z = 0; z < NZ; ++z)
 #pragma unroll
       for (int y = 0; y < NV; ++y)
 #pragma unroll
         for (int x = 0; x < NV; ++x) {
-          T v = 0;
-          const int gx = K * gcx + x, gy = K * gcy + y, gz = K * cz + z;
-          if (active && !(Op::ZERO_BC && vbc(gx, gy, gz))) v = op.load_u(vidx(c, gx, gy, gz));
-          dst[z - Z0][y][x] = v;
+          const bool keep = active & !(ZERO_BC & vbc(cz, x, y, Z0 + z));
+          a[z][y][x] = keep ? a[z][y][x] : T(0);
         }
   }
-  template <int Z0, class Op, int NZ>
-  __device__ void load_p(const Op &op, int cz, T (&dst)[NZ][NP][NP]) const {
-    static_assert(NZ == NP - Z0, "plane count");
+  template <int NZ>
+  __device__ void mask_p(T (&a)[NZ][NP][NP]) const {
 #pragma unroll
-    for (int z = Z0; z < NP; ++z)
+    for (int z = 0; z < NZ; ++z)
 #pragma unroll
       for (int y = 0; y < NP; ++y)
 #pragma unroll
-        for (int x = 0; x < NP; ++x) {
-          T v = 0;
-          if (active) v = op.load_p(pidx((K - 1) * gcx + x, (K - 1) * gcy + y, (K - 1) * cz + z));
-          dst[z - Z0][y][x] = v;
-        }
+        for (int x = 0; x < NP; ++x) a[z][y][x] = active ? a[z][y][x] : T(0);
   }
 };
 
@@ -98,18 +167,297 @@ __device__ __forceinline__ void hand_over_xy(T (&y)[NZ][N][N], int lcx, int lcy,
     }
 }
 
+// Sweep geometry shared by the wave roles.
+struct Sweep {
+  int lcx, lcy;     // lane position in the tile
+  int z_lo, z_hi;   // owned cell layers [z_lo, z_hi)
+  int z_start;      // first computed layer (halo layer below z_lo if any)
+  bool col_owner;   // column owned by the tile
+  bool last_x, last_y;
+};
+
+// ------------------------------------------------------------ velocity wave
+template <int K, typename T, int BLK, class Op, int COMP, int TX>
+__device__ __forceinline__ void vel_wave(const Geo3<T> &g, const Op &op, const Column3D<K, T> &col, const Sweep &s) {
+  constexpr int NV = K + 1, NP = K;
+  constexpr cfe::TabT<K, T> R = cfe::make_tab_t<K, T>();
+  constexpr bool NEED_U = (BLK & (BLK_A | BLK_MASS)) != 0;
+  constexpr bool NEED_P = (BLK & BLK_BT) != 0;
+  // B_c^T: Gr^T in direction COMP, Nr^T in the others
+  const T(&Bx)[K][K + 1] = COMP == 0 ? R.Gr : R.Nr;
+  const T(&By)[K][K + 1] = COMP == 1 ? R.Gr : R.Nr;
+  const T(&Bz)[K][K + 1] = COMP == 2 ? R.Gr : R.Nr;
+
+  T u[NV][NV][NV], un[K][NV][NV];
+  T p[NP][NP][NP], pn[NP - 1][NP][NP];
+  T carry[NV][NV];
+#pragma unroll
+  for (int j = 0; j < NV; ++j)
+#pragma unroll
+    for (int i = 0; i < NV; ++i) carry[j][i] = 0;
+  if constexpr (NEED_U) {
+    col.template load_u<0>(op, COMP, s.z_start, u);
+    col.template mask_u<Op::ZERO_BC, 0>(s.z_start, u);
+  } else {
+#pragma unroll
+    for (int z = 0; z < NV; ++z)
+#pragma unroll
+      for (int j = 0; j < NV; ++j)
+#pragma unroll
+        for (int i = 0; i < NV; ++i) u[z][j][i] = 0;
+  }
+  if constexpr (NEED_P) {
+    col.template load_p<0>(op, s.z_start, p);
+    col.mask_p(p);
+  }
+  T mu = 0, mu_n = 0;
+  if constexpr ((BLK & BLK_A) != 0) mu = col.mu_at(s.z_start);
+
+  for (int cl = s.z_start; cl < s.z_hi; ++cl) {
+    const bool more = cl + 1 < s.z_hi;
+    if (more) {  // next layer: planes 1..K (plane 0 is this layer's plane K)
+      if constexpr ((BLK & BLK_A) != 0) mu_n = col.mu_at(cl + 1);
+      if constexpr (NEED_U) col.template load_u<1>(op, COMP, cl + 1, un);
+      if constexpr (NEED_P) col.template load_p<1>(op, cl + 1, pn);
+    }
+    const bool owner = s.col_owner && cl >= s.z_lo;
+    const bool last_z = cl == g.n[2] - 1;
+    // epilogue inputs of the owned nodes [0,K)^3
+    typename Op::Pre pre[K][K][K];
+    if (owner) {
+#pragma unroll
+      for (int z = 0; z < K; ++z)
+#pragma unroll
+        for (int y = 0; y < K; ++y)
+#pragma unroll
+          for (int x = 0; x < K; ++x) pre[z][y][x] = op.fetch_u(col.u_at(COMP, cl, x, y, z));
+    }
+
+    T y[NV][NV][NV];
+    if constexpr ((BLK & BLK_A) != 0) {
+      T X[NV][NV];
+      const T ax = mu * g.sKx, bx = g.gr * g.sM;
+#pragma unroll
+      for (int i = 0; i < NV; ++i)
+#pragma unroll
+        for (int j = 0; j < NV; ++j) X[i][j] = ax * R.Kr[i][j] + bx * R.Mr[i][j];
+      T a[NV][NV][NV], t[NV][NV][NV];
+      pass_z<false, false>(R.Mr, u, a, T(1));
+      pass_y<false, false>(R.Mr, a, t, T(1));
+      pass_x<false, false>(X, t, y, T(1));
+      pass_y<false, false>(R.Kr, a, t, T(1));
+      pass_z<false, false>(R.Kr, u, a, T(1));
+      pass_y<false, true>(R.Mr, a, t, g.rz);
+      pass_x<false, true>(R.Mr, t, y, mu * g.sKy);
+    } else if constexpr ((BLK & BLK_MASS) != 0) {
+      T a[NV][NV][NV], t[NV][NV][NV];
+      pass_z<false, false>(R.Mr, u, a, T(1));
+      pass_y<false, false>(R.Mr, a, t, T(1));
+      pass_x<false, false>(R.Mr, t, y, g.sM);
+    }
+    if constexpr ((BLK & BLK_BT) != 0) {
+      constexpr bool ACC = (BLK & (BLK_A | BLK_MASS)) != 0;
+      T s1[NV][NP][NP], s2[NV][NV][NP];
+      pass_z<true, false>(Bz, p, s1, T(1));
+      pass_y<true, false>(By, s1, s2, T(1));
+      pass_x<true, ACC>(Bx, s2, y, -g.sB[COMP]);
+    }
+    hand_over_xy<TX>(y, s.lcx, s.lcy, s.last_x, s.last_y);
+#pragma unroll
+    for (int j = 0; j < NV; ++j)
+#pragma unroll
+      for (int i = 0; i < NV; ++i) {
+        y[0][j][i] += carry[j][i];
+        carry[j][i] = y[K][j][i];
+      }
+    if (owner) {
+      // every owned node from the cell sums; the Dirichlet rows among them are
+      // rewritten below (same lane, program order)
+#pragma unroll
+      for (int z = 0; z < K; ++z)
+#pragma unroll
+        for (int yy = 0; yy < K; ++yy)
+#pragma unroll
+          for (int x = 0; x < K; ++x)
+            op.store_u(col.u_at(COMP, cl, x, yy, z), y[z][yy][x], u[z][yy][x], false, pre[z][yy][x]);
+      if (col.bxl | col.byl | (cl == 0)) {
+        // Dirichlet rows on the low faces: identity (A) or zero
+#pragma unroll
+        for (int z = 0; z < K; ++z)
+#pragma unroll
+          for (int yy = 0; yy < K; ++yy)
+#pragma unroll
+            for (int x = 0; x < K; ++x) {
+              if (!col.vbc(cl, x, yy, z)) continue;
+              const BOff gi = col.u_at(COMP, cl, x, yy, z);
+              T rw = 0;
+              if constexpr ((BLK & BLK_A) != 0) rw = op.load_u(gi);
+              op.store_u(gi, rw, rw, true, pre[z][yy][x]);
+            }
+      }
+      if (s.last_x | s.last_y | last_z) {
+        // nodes on the domain's high faces: Dirichlet rows
+#pragma unroll
+        for (int z = 0; z < NV; ++z)
+#pragma unroll
+          for (int yy = 0; yy < NV; ++yy)
+#pragma unroll
+            for (int x = 0; x < NV; ++x) {
+              if (x < K && yy < K && z < K) continue;
+              if ((x == K && !s.last_x) || (yy == K && !s.last_y) || (z == K && !last_z)) continue;
+              const BOff gi = col.u_at(COMP, cl, x, yy, z);
+              T rw = 0;
+              if constexpr ((BLK & BLK_A) != 0) rw = op.load_u(gi);
+              op.store_u(gi, rw, rw, true, op.fetch_u(gi));
+            }
+      }
+    }
+    if (more) {
+      mu = mu_n;
+      if constexpr (NEED_U) {
+        col.template mask_u<Op::ZERO_BC, 1>(cl + 1, un);
+#pragma unroll
+        for (int j = 0; j < NV; ++j)
+#pragma unroll
+          for (int i = 0; i < NV; ++i) u[0][j][i] = u[K][j][i];
+#pragma unroll
+        for (int z = 1; z < NV; ++z)
+#pragma unroll
+          for (int j = 0; j < NV; ++j)
+#pragma unroll
+            for (int i = 0; i < NV; ++i) u[z][j][i] = un[z - 1][j][i];
+      }
+      if constexpr (NEED_P) {
+        col.mask_p(pn);
+#pragma unroll
+        for (int j = 0; j < NP; ++j)
+#pragma unroll
+          for (int i = 0; i < NP; ++i) p[0][j][i] = p[NP - 1][j][i];
+#pragma unroll
+        for (int z = 1; z < NP; ++z)
+#pragma unroll
+          for (int j = 0; j < NP; ++j)
+#pragma unroll
+            for (int i = 0; i < NP; ++i) p[z][j][i] = pn[z - 1][j][i];
+      }
+    }
+  }
+}
+
+// ------------------------------------------------------------ pressure wave
+template <int K, typename T, int BLK, class Op, int TX>
+__device__ __forceinline__ void pres_wave(const Geo3<T> &g, const Op &op, const Column3D<K, T> &col, const Sweep &s) {
+  constexpr int NV = K + 1, NP = K;
+  constexpr cfe::TabT<K, T> R = cfe::make_tab_t<K, T>();
+  constexpr bool NEED_U = (BLK & BLK_B) != 0;
+  constexpr bool NEED_P = (BLK & BLK_C) != 0;
+  T carry[NP][NP];
+#pragma unroll
+  for (int j = 0; j < NP; ++j)
+#pragma unroll
+    for (int i = 0; i < NP; ++i) carry[j][i] = 0;
+  // velocity component layers are streamed one component at a time with one
+  // request ahead: (layer, component) = (cl, 0), (cl, 1), (cl, 2), (cl + 1, 0)...
+  T ub[NV][NV][NV];
+  T p[NP][NP][NP];
+  if constexpr (NEED_U) col.template load_u<0>(op, 0, s.z_start, ub);
+  if constexpr (NEED_P) col.template load_p<0>(op, s.z_start, p);
+  for (int cl = s.z_start; cl < s.z_hi; ++cl) {
+    const bool more = cl + 1 < s.z_hi;
+    const bool owner = s.col_owner && cl >= s.z_lo;
+    const bool last_z = cl == g.n[2] - 1;
+    typename Op::Pre pre[K - 1][K - 1][K - 1];
+    if (owner) {
+#pragma unroll
+      for (int z = 0; z < K - 1; ++z)
+#pragma unroll
+        for (int yy = 0; yy < K - 1; ++yy)
+#pragma unroll
+          for (int x = 0; x < K - 1; ++x) pre[z][yy][x] = op.fetch_p(col.p_at(cl, x, yy, z));
+    }
+    T pn[NP][NP][NP];
+    if constexpr (NEED_P) {
+      if (more) col.template load_p<0>(op, cl + 1, pn);
+      col.mask_p(p);
+    }
+    T yp[NP][NP][NP];
+#pragma unroll
+    for (int z = 0; z < NP; ++z)
+#pragma unroll
+      for (int j = 0; j < NP; ++j)
+#pragma unroll
+        for (int i = 0; i < NP; ++i) yp[z][j][i] = 0;
+    if constexpr (NEED_U) {
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        T un[NV][NV][NV];
+        if (c < 2) col.template load_u<0>(op, c + 1, cl, un);
+        else if (more) col.template load_u<0>(op, 0, cl + 1, un);
+        col.template mask_u<Op::ZERO_BC, 0>(cl, ub);
+        // B u = -sum_c sB_c (Gr in direction c, Nr in the others) u_c
+        T w1[NV][NV][NP], w2[NV][NP][NP];
+        pass_x<false, false>(c == 0 ? R.Gr : R.Nr, ub, w1, T(1));
+        pass_y<false, false>(c == 1 ? R.Gr : R.Nr, w1, w2, T(1));
+        pass_z<false, true>(c == 2 ? R.Gr : R.Nr, w2, yp, -g.sB[c]);
+#pragma unroll
+        for (int z = 0; z < NV; ++z)
+#pragma unroll
+          for (int j = 0; j < NV; ++j)
+#pragma unroll
+            for (int i = 0; i < NV; ++i) ub[z][j][i] = un[z][j][i];
+      }
+    }
+    if constexpr (NEED_P) {
+      const T sc = ((BLK & BLK_CPLUS) ? g.cp : -g.cp) * g.sM;
+      T q1[NP][NP][NP], q2[NP][NP][NP];
+      pass_x<false, false>(R.Mpr, p, q1, T(1));
+      pass_y<false, false>(R.Mpr, q1, q2, T(1));
+      pass_z<false, true>(R.Mpr, q2, yp, sc);
+    }
+    hand_over_xy<TX>(yp, s.lcx, s.lcy, s.last_x, s.last_y);
+#pragma unroll
+    for (int j = 0; j < NP; ++j)
+#pragma unroll
+      for (int i = 0; i < NP; ++i) {
+        yp[0][j][i] += carry[j][i];
+        carry[j][i] = yp[NP - 1][j][i];
+      }
+    if (owner) {
+#pragma unroll
+      for (int z = 0; z < NP; ++z)
+#pragma unroll
+        for (int yy = 0; yy < NP; ++yy)
+#pragma unroll
+          for (int x = 0; x < NP; ++x) {
+            const bool main = x < K - 1 && yy < K - 1 && z < K - 1;
+            if (main) {
+              op.store_p(col.p_at(cl, x, yy, z), yp[z][yy][x], p[z][yy][x], pre[main ? z : 0][main ? yy : 0][main ? x : 0]);
+            } else if (((x < K - 1) | s.last_x) & ((yy < K - 1) | s.last_y) & ((z < K - 1) | last_z)) {
+              const BOff gi = col.p_at(cl, x, yy, z);
+              op.store_p(gi, yp[z][yy][x], p[z][yy][x], op.fetch_p(gi));
+            }
+          }
+    }
+    if constexpr (NEED_P) {
+      if (more) {
+#pragma unroll
+        for (int z = 0; z < NP; ++z)
+#pragma unroll
+          for (int j = 0; j < NP; ++j)
+#pragma unroll
+            for (int i = 0; i < NP; ++i) p[z][j][i] = pn[z][j][i];
+      }
+    }
+  }
+}
+
 template <int K, typename T, int BLK, class Op, int TX, int TY>
 __global__ void __launch_bounds__(64)
-tile3d_kernel(const LevelGeom<T, 3, K> g, const Op op) {
-  constexpr int NV = K + 1, NP = K;
+tile3d_kernel(const Geo3<T> g, const Op op) {
   static_assert(TX * TY == 64, "one wave per tile");
   constexpr bool OUT_U = (BLK & (BLK_A | BLK_MASS | BLK_BT)) != 0;
   constexpr bool OUT_P = (BLK & (BLK_B | BLK_C)) != 0;
   constexpr int NFIELD = (OUT_U ? 3 : 0) + (OUT_P ? 1 : 0);
-  constexpr bool V_NEED_U = (BLK & (BLK_A | BLK_MASS)) != 0;
-  constexpr bool V_NEED_P = (BLK & BLK_BT) != 0;
-  constexpr bool P_NEED_U = (BLK & BLK_B) != 0;
-  constexpr bool P_NEED_P = (BLK & BLK_C) != 0;
 
   // block -> (field, x tile, z chunk, y tile); the fields of one tile and
   // chunk run on the same XCD and share its L2.
@@ -121,244 +469,27 @@ tile3d_kernel(const LevelGeom<T, 3, K> g, const Op op) {
   const int zc = rest % g.tiles[2];
   const int ty = rest / g.tiles[2];
   const int zlen = (g.n[2] + g.tiles[2] - 1) / g.tiles[2];
-  const int z_lo = zc * zlen;
-  const int z_hi = z_lo + zlen < g.n[2] ? z_lo + zlen : g.n[2];
-  if (z_lo >= z_hi) return;  // whole wave: empty chunk
-  const int z_start = z_lo > 0 ? z_lo - 1 : 0;
+  Sweep s;
+  s.z_lo = zc * zlen;
+  s.z_hi = s.z_lo + zlen < g.n[2] ? s.z_lo + zlen : g.n[2];
+  if (s.z_lo >= s.z_hi) return;  // whole wave: empty chunk
+  s.z_start = s.z_lo > 0 ? s.z_lo - 1 : 0;
+  s.lcx = threadIdx.x % TX;
+  s.lcy = threadIdx.x / TX;
+  const Column3D<K, T> col(g, tx * (TX - 1) - 1 + s.lcx, ty * (TY - 1) - 1 + s.lcy);
+  s.col_owner = col.active && s.lcx > 0 && s.lcy > 0;
+  s.last_x = col.bxh;
+  s.last_y = col.byh;
 
-  const int lane = threadIdx.x;
-  const int lcx = lane % TX, lcy = lane / TX;
-  Column3D<K, T> col{g, tx * (TX - 1) - 1 + lcx, ty * (TY - 1) - 1 + lcy, false, false, false};
-  col.active = col.gcx >= 0 && col.gcx < g.n[0] && col.gcy >= 0 && col.gcy < g.n[1];
-  const bool col_owner = col.active && lcx > 0 && lcy > 0;
-  const bool last_x = col.gcx == g.n[0] - 1, last_y = col.gcy == g.n[1] - 1;
-  const Coef1D<T, K> &cx = g.c[0];
-  const Coef1D<T, K> &cy = g.c[1];
-  const Coef1D<T, K> &cz = g.c[2];
-
-  if (OUT_U && field < 3) {
-    // ------------------------------------------------------ velocity wave
-    const int comp = field;
-    T u[NV][NV][NV], un[K][NV][NV];
-    T p[NP][NP][NP], pn[NP - 1][NP][NP];
-    T carry[NV][NV];
-#pragma unroll
-    for (int j = 0; j < NV; ++j)
-#pragma unroll
-      for (int i = 0; i < NV; ++i) carry[j][i] = 0;
-    if constexpr (V_NEED_U) {
-      col.template load_u<0>(op, comp, z_start, u);
-    } else {
-#pragma unroll
-      for (int z = 0; z < NV; ++z)
-#pragma unroll
-        for (int j = 0; j < NV; ++j)
-#pragma unroll
-          for (int i = 0; i < NV; ++i) u[z][j][i] = 0;
-    }
-    if constexpr (V_NEED_P) col.template load_p<0>(op, z_start, p);
-    // B_c^T = -(N^T or G^T per direction): G in direction comp
-    const auto &Bx = comp == 0 ? cx.G : cx.N;
-    const auto &By = comp == 1 ? cy.G : cy.N;
-    const auto &Bz = comp == 2 ? cz.G : cz.N;
-
-    for (int cl = z_start; cl < z_hi; ++cl) {
-      const bool more = cl + 1 < z_hi;
-      if (more) {
-        if constexpr (V_NEED_U) col.template load_u<1>(op, comp, cl + 1, un);
-        if constexpr (V_NEED_P) col.template load_p<1>(op, cl + 1, pn);
-      }
-      const bool owner = col_owner && cl >= z_lo;
-      const bool last_z = cl == g.n[2] - 1;
-      // epilogue inputs of the owned nodes [0,K)^3
-      typename Op::Pre pre[K][K][K];
-      T raw[K][K][K];
-      if (owner) {
-#pragma unroll
-        for (int z = 0; z < K; ++z)
-#pragma unroll
-          for (int y = 0; y < K; ++y)
-#pragma unroll
-            for (int x = 0; x < K; ++x) {
-              const int gx = K * col.gcx + x, gy = K * col.gcy + y, gz = K * cl + z;
-              const i64 gi = col.vidx(comp, gx, gy, gz);
-              pre[z][y][x] = op.fetch_u(gi);
-              raw[z][y][x] = 0;
-              if constexpr ((BLK & BLK_A) != 0)
-                if (gx == 0 || gy == 0 || gz == 0) raw[z][y][x] = op.load_u(gi);
-            }
-      }
-      T mu = g.mu;
-      if (g.mu_cell != nullptr && col.active) mu = g.mu_cell[col.gcx + (i64)g.n[0] * (col.gcy + (i64)g.n[1] * cl)];
-
-      T y[NV][NV][NV];
-      if constexpr ((BLK & BLK_A) != 0) {
-        T X[NV][NV];
-#pragma unroll
-        for (int i = 0; i < NV; ++i)
-#pragma unroll
-          for (int j = 0; j < NV; ++j) X[i][j] = mu * cx.Kv[i][j] + g.gr * cx.Mv[i][j];
-        T a[NV][NV][NV], t[NV][NV][NV];
-        pass_z<false, false>(cz.Mv, u, a, T(1));
-        pass_y<false, false>(cy.Mv, a, t, T(1));
-        pass_x<false, false>(X, t, y, T(1));
-        pass_y<false, false>(cy.Kv, a, t, mu);
-        pass_z<false, false>(cz.Kv, u, a, mu);
-        pass_y<false, true>(cy.Mv, a, t, T(1));
-        pass_x<false, true>(cx.Mv, t, y, T(1));
-      } else if constexpr ((BLK & BLK_MASS) != 0) {
-        T a[NV][NV][NV], t[NV][NV][NV];
-        pass_z<false, false>(cz.Mv, u, a, T(1));
-        pass_y<false, false>(cy.Mv, a, t, T(1));
-        pass_x<false, false>(cx.Mv, t, y, T(1));
-      }
-      if constexpr ((BLK & BLK_BT) != 0) {
-        constexpr bool ACC = (BLK & (BLK_A | BLK_MASS)) != 0;
-        T s1[NV][NP][NP], s2[NV][NV][NP];
-        pass_z<true, false>(Bz, p, s1, T(1));
-        pass_y<true, false>(By, s1, s2, T(1));
-        pass_x<true, ACC>(Bx, s2, y, T(-1));
-      }
-      hand_over_xy<TX>(y, lcx, lcy, last_x, last_y);
-#pragma unroll
-      for (int j = 0; j < NV; ++j)
-#pragma unroll
-        for (int i = 0; i < NV; ++i) {
-          y[0][j][i] += carry[j][i];
-          carry[j][i] = y[K][j][i];
-        }
-      if (owner) {
-#pragma unroll
-        for (int z = 0; z < K; ++z)
-#pragma unroll
-          for (int yy = 0; yy < K; ++yy)
-#pragma unroll
-            for (int x = 0; x < K; ++x) {
-              const int gx = K * col.gcx + x, gy = K * col.gcy + yy, gz = K * cl + z;
-              const i64 gi = col.vidx(comp, gx, gy, gz);
-              if (gx == 0 || gy == 0 || gz == 0) op.store_u(gi, raw[z][yy][x], raw[z][yy][x], true, pre[z][yy][x]);
-              else op.store_u(gi, y[z][yy][x], u[z][yy][x], false, pre[z][yy][x]);
-            }
-        if (last_x || last_y || last_z) {
-          // nodes on the domain's high faces: Dirichlet rows
-#pragma unroll
-          for (int z = 0; z < NV; ++z)
-#pragma unroll
-            for (int yy = 0; yy < NV; ++yy)
-#pragma unroll
-              for (int x = 0; x < NV; ++x) {
-                if (x < K && yy < K && z < K) continue;
-                if ((x == K && !last_x) || (yy == K && !last_y) || (z == K && !last_z)) continue;
-                const i64 gi = col.vidx(comp, K * col.gcx + x, K * col.gcy + yy, K * cl + z);
-                T rw = 0;
-                if constexpr ((BLK & BLK_A) != 0) rw = op.load_u(gi);
-                op.store_u(gi, rw, rw, true, op.fetch_u(gi));
-              }
-        }
-      }
-      if (more) {
-#pragma unroll
-        for (int j = 0; j < NV; ++j)
-#pragma unroll
-          for (int i = 0; i < NV; ++i) u[0][j][i] = u[K][j][i];
-#pragma unroll
-        for (int z = 1; z < NV; ++z)
-#pragma unroll
-          for (int j = 0; j < NV; ++j)
-#pragma unroll
-            for (int i = 0; i < NV; ++i) u[z][j][i] = un[z - 1][j][i];
-        if constexpr (V_NEED_P) {
-#pragma unroll
-          for (int j = 0; j < NP; ++j)
-#pragma unroll
-            for (int i = 0; i < NP; ++i) p[0][j][i] = p[NP - 1][j][i];
-#pragma unroll
-          for (int z = 1; z < NP; ++z)
-#pragma unroll
-            for (int j = 0; j < NP; ++j)
-#pragma unroll
-              for (int i = 0; i < NP; ++i) p[z][j][i] = pn[z - 1][j][i];
-        }
-      }
-    }
-  } else if constexpr (OUT_P) {
-    // ------------------------------------------------------ pressure wave
-    T carry[NP][NP];
-#pragma unroll
-    for (int j = 0; j < NP; ++j)
-#pragma unroll
-      for (int i = 0; i < NP; ++i) carry[j][i] = 0;
-    T p[NP][NP][NP];
-#pragma unroll
-    for (int z = 0; z < NP; ++z)
-#pragma unroll
-      for (int j = 0; j < NP; ++j)
-#pragma unroll
-        for (int i = 0; i < NP; ++i) p[z][j][i] = 0;
-    for (int cl = z_start; cl < z_hi; ++cl) {
-      const bool owner = col_owner && cl >= z_lo;
-      const bool last_z = cl == g.n[2] - 1;
-      typename Op::Pre pre[K - 1][K - 1][K - 1];
-      if (owner) {
-#pragma unroll
-        for (int z = 0; z < K - 1; ++z)
-#pragma unroll
-          for (int yy = 0; yy < K - 1; ++yy)
-#pragma unroll
-            for (int x = 0; x < K - 1; ++x)
-              pre[z][yy][x] = op.fetch_p(col.pidx((K - 1) * col.gcx + x, (K - 1) * col.gcy + yy, (K - 1) * cl + z));
-      }
-      if constexpr (P_NEED_P) col.template load_p<0>(op, cl, p);
-      T yp[NP][NP][NP];
-#pragma unroll
-      for (int z = 0; z < NP; ++z)
-#pragma unroll
-        for (int j = 0; j < NP; ++j)
-#pragma unroll
-          for (int i = 0; i < NP; ++i) yp[z][j][i] = 0;
-      if constexpr (P_NEED_U) {
-        // B u = -sum_c (G or N per direction) u_c, one component at a time
-#pragma unroll
-        for (int c = 0; c < 3; ++c) {
-          T u[NV][NV][NV];
-          col.template load_u<0>(op, c, cl, u);
-          T w1[NV][NV][NP], w2[NV][NP][NP];
-          pass_x<false, false>(c == 0 ? cx.G : cx.N, u, w1, T(1));
-          pass_y<false, false>(c == 1 ? cy.G : cy.N, w1, w2, T(1));
-          pass_z<false, true>(c == 2 ? cz.G : cz.N, w2, yp, T(-1));
-        }
-      }
-      if constexpr (P_NEED_P) {
-        const T sc = (BLK & BLK_CPLUS) ? g.cp : -g.cp;
-        T q1[NP][NP][NP], q2[NP][NP][NP];
-        pass_x<false, false>(cx.Mp, p, q1, T(1));
-        pass_y<false, false>(cy.Mp, q1, q2, T(1));
-        pass_z<false, true>(cz.Mp, q2, yp, sc);
-      }
-      hand_over_xy<TX>(yp, lcx, lcy, last_x, last_y);
-#pragma unroll
-      for (int j = 0; j < NP; ++j)
-#pragma unroll
-        for (int i = 0; i < NP; ++i) {
-          yp[0][j][i] += carry[j][i];
-          carry[j][i] = yp[NP - 1][j][i];
-        }
-      if (owner) {
-#pragma unroll
-        for (int z = 0; z < NP; ++z)
-#pragma unroll
-          for (int yy = 0; yy < NP; ++yy)
-#pragma unroll
-            for (int x = 0; x < NP; ++x) {
-              const bool main = x < K - 1 && yy < K - 1 && z < K - 1;
-              if (!main && ((x == K - 1 && !last_x) || (yy == K - 1 && !last_y) || (z == K - 1 && !last_z))) continue;
-              const i64 gi = col.pidx((K - 1) * col.gcx + x, (K - 1) * col.gcy + yy, (K - 1) * cl + z);
-              if (main) op.store_p(gi, yp[z][yy][x], p[z][yy][x], pre[main ? z : 0][main ? yy : 0][main ? x : 0]);
-              else op.store_p(gi, yp[z][yy][x], p[z][yy][x], op.fetch_p(gi));
-            }
-      }
+  if constexpr (OUT_U) {
+    switch (field) {
+      case 0: vel_wave<K, T, BLK, Op, 0, TX>(g, op, col, s); return;
+      case 1: vel_wave<K, T, BLK, Op, 1, TX>(g, op, col, s); return;
+      case 2: vel_wave<K, T, BLK, Op, 2, TX>(g, op, col, s); return;
+      default: break;
     }
   }
+  if constexpr (OUT_P) pres_wave<K, T, BLK, Op, TX>(g, op, col, s);
 }
 
 }  // namespace smg

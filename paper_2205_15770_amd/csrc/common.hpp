@@ -35,8 +35,25 @@ struct LevelGeom {
   T gr;            // gamma * rho
   T cp;            // c_pressure (C = cp M_p)
   const T *mu_cell;
+  double h[3];     // cell widths
   Coef1D<T, K> c[DIM];
 };
+
+// Array access by element index, or by a byte offset v (per lane) plus a
+// compile-time byte offset c: the second form maps to global loads/stores with
+// a uniform base address, a 32-bit lane offset and an immediate offset.
+struct BOff {
+  uint32_t v;
+  uint32_t c;
+};
+template <typename T>
+__device__ __forceinline__ T &at(T *p, i64 i) { return p[i]; }
+template <typename T>
+__device__ __forceinline__ const T &at(const T *p, i64 i) { return p[i]; }
+template <typename T>
+__device__ __forceinline__ T &at(T *p, BOff b) { return *(T *)((char *)p + b.v + b.c); }
+template <typename T>
+__device__ __forceinline__ const T &at(const T *p, BOff b) { return *(const T *)((const char *)p + b.v + b.c); }
 
 __device__ __forceinline__ bool on_box_boundary(int i, int extent) { return i == 0 || i == extent - 1; }
 

@@ -141,6 +141,7 @@ class EngineT : public EngineBase {
     g.gr = (T)(desc.gamma * desc.rho);
     g.cp = (T)(unit_cp ? 1.0 : desc.c_pressure);
     g.mu_cell = work<T>(l).mu_cell;
+    for (int a = 0; a < 3; ++a) g.h[a] = I.h[a];
     const int nv = K + 1, np = K;
     for (int a = 0; a < DIM; ++a) {
       const double h = I.h[a];
@@ -173,12 +174,36 @@ class EngineT : public EngineBase {
     }
     if constexpr (DIM == 2) {
       hipLaunchKernelGGL((tile2d_kernel<K, T, BLK, Op, TX, TY>), dim3(nblk), dim3(TX * TY), 0, stream, g, op);
+    } else if constexpr (K != 2) {
+      // Q3-Q2 in 3D: colour-phase tile kernel (the column sweep is built for
+      // Q2-Q1 only; its Q3 variants spill to scratch and are switched off)
+      hipLaunchKernelGGL((tile_apply_kernel<DIM, K, T, BLK, Op, TX, TY, TZ>), dim3(nblk), dim3(TX * TY * TZ), 0, stream,
+                         g, op);
     } else {
       // 8 x 8 cell columns per wave, one wave per output field; the z extent
       // is cut into chunks so that the launch has >= ~2048 waves when the
       // level is large enough (two per SIMD), chunks of >= 2 cells.
       constexpr int NF = ((BLK & (BLK_A | BLK_MASS | BLK_BT)) ? 3 : 0) + ((BLK & (BLK_B | BLK_C)) ? 1 : 0);
-      LevelGeom<T, DIM, K> g3 = g;
+      Geo3<T> g3;
+      std::memset(&g3, 0, sizeof(g3));
+      for (int a = 0; a < 3; ++a) {
+        g3.n[a] = g.n[a];
+        g3.vd[a] = g.vd[a];
+        g3.pd[a] = g.pd[a];
+      }
+      g3.nv_bytes = (uint32_t)(g.Nv * (int64_t)sizeof(T));
+      g3.mu = g.mu;
+      g3.gr = g.gr;
+      g3.cp = g.cp;
+      g3.mu_cell = g.mu_cell;
+      const double hx = g.h[0], hy = g.h[1], hz = g.h[2];
+      g3.sKx = (T)(hy * hz / hx);
+      g3.sKy = (T)(hx * hz / hy);
+      g3.rz = (T)((hy * hy) / (hz * hz));
+      g3.sM = (T)(hx * hy * hz);
+      g3.sB[0] = (T)(hy * hz);
+      g3.sB[1] = (T)(hx * hz);
+      g3.sB[2] = (T)(hx * hy);
       g3.tiles[0] = (g.n[0] + 6) / 7;
       g3.tiles[1] = (g.n[1] + 6) / 7;
       const int cols = g3.tiles[0] * g3.tiles[1] * NF;
@@ -702,6 +727,24 @@ class EngineT : public EngineBase {
 
   void setup() override {
     ref = make_ref1d(K);
+    {
+      // the device kernels use the compile-time copies of these tables
+      constexpr cfe::Tab<K> ct = cfe::make_tab<K>();
+      double e = 0;
+      for (int i = 0; i <= K; ++i)
+        for (int j = 0; j <= K; ++j) {
+          e = std::max(e, std::fabs(ct.Kr[i][j] - ref.Kv[i * (K + 1) + j]));
+          e = std::max(e, std::fabs(ct.Mr[i][j] - ref.Mv[i * (K + 1) + j]));
+        }
+      for (int i = 0; i < K; ++i) {
+        for (int j = 0; j <= K; ++j) {
+          e = std::max(e, std::fabs(ct.Gr[i][j] - ref.G[i * (K + 1) + j]));
+          e = std::max(e, std::fabs(ct.Nr[i][j] - ref.N[i * (K + 1) + j]));
+        }
+        for (int j = 0; j < K; ++j) e = std::max(e, std::fabs(ct.Mpr[i][j] - ref.Mp[i * K + j]));
+      }
+      if (e > 1e-14) throw Error{SMG_EINVAL, "internal: compile-time 1D tables differ from the set-up tables"};
+    }
     sigma = cheb_scaling(desc.cheb_deg_A);
     tau = cheb_scaling(desc.cheb_deg_S);
     std::memset(&ttab, 0, sizeof(ttab));
@@ -735,6 +778,10 @@ class EngineT : public EngineBase {
       I.Nu = DIM * I.Nv;
       I.N = I.Nu + I.Np;
     }
+    // the 3D operator kernel addresses a level vector's velocity block by
+    // 32-bit byte offsets
+    if (DIM == 3 && (double)lv[L].Nu * sizeof(double) >= 4294967296.0)
+      throw Error{SMG_EUNSUPPORTED, "finest level too large: velocity block exceeds 4 GiB"};
     // per-cell viscosity: finest as given, coarser levels by averaging children
     if (desc.mu_cell) {
       std::vector<std::vector<double>> mu(desc.n_levels);

@@ -15,12 +15,18 @@ struct OpApply {
   const T *xu, *xp;
   T *yu, *yp;
   struct Pre {};
-  __device__ T load_u(i64 i) const { return xu[i]; }
-  __device__ T load_p(i64 i) const { return xp[i]; }
-  __device__ Pre fetch_u(i64) const { return Pre{}; }
-  __device__ Pre fetch_p(i64) const { return Pre{}; }
-  __device__ void store_u(i64 i, T t, T, bool, const Pre &) const { yu[i] = t; }
-  __device__ void store_p(i64 i, T t, T, const Pre &) const { yp[i] = t; }
+  template <class I>
+  __device__ T load_u(I i) const { return at(xu, i); }
+  template <class I>
+  __device__ T load_p(I i) const { return at(xp, i); }
+  template <class I>
+  __device__ Pre fetch_u(I) const { return Pre{}; }
+  template <class I>
+  __device__ Pre fetch_p(I) const { return Pre{}; }
+  template <class I>
+  __device__ void store_u(I i, T t, T, bool, const Pre &) const { at(yu, i) = t; }
+  template <class I>
+  __device__ void store_p(I i, T t, T, const Pre &) const { at(yp, i) = t; }
   // algorithmic HBM bytes of one launch: every vector read or written once
   double algo_bytes(bool need_u, bool need_p, bool out_u, bool out_p, double nu, double np) const {
     return sizeof(T) * ((need_u ? nu : 0) + (need_p ? np : 0) + (out_u ? nu : 0) + (out_p ? np : 0));
@@ -38,12 +44,18 @@ struct OpResidual {
   struct Pre {
     T b;
   };
-  __device__ T load_u(i64 i) const { return xu[i]; }
-  __device__ T load_p(i64 i) const { return xp[i]; }
-  __device__ Pre fetch_u(i64 i) const { return Pre{bu[i]}; }
-  __device__ Pre fetch_p(i64 i) const { return Pre{bp[i]}; }
-  __device__ void store_u(i64 i, T t, T, bool, const Pre &q) const { ru[i] = q.b - t; }
-  __device__ void store_p(i64 i, T t, T, const Pre &q) const { rp[i] = q.b - t; }
+  template <class I>
+  __device__ T load_u(I i) const { return at(xu, i); }
+  template <class I>
+  __device__ T load_p(I i) const { return at(xp, i); }
+  template <class I>
+  __device__ Pre fetch_u(I i) const { return Pre{at(bu, i)}; }
+  template <class I>
+  __device__ Pre fetch_p(I i) const { return Pre{at(bp, i)}; }
+  template <class I>
+  __device__ void store_u(I i, T t, T, bool, const Pre &q) const { at(ru, i) = q.b - t; }
+  template <class I>
+  __device__ void store_p(I i, T t, T, const Pre &q) const { at(rp, i) = q.b - t; }
   double algo_bytes(bool need_u, bool need_p, bool out_u, bool out_p, double nu, double np) const {
     return sizeof(T) * ((need_u ? nu : 0) + (need_p ? np : 0) + (out_u ? 2 * nu : 0) + (out_p ? 2 * np : 0));
   }
@@ -58,12 +70,18 @@ struct OpMass {
   const T *f;
   T *y;
   struct Pre {};
-  __device__ T load_u(i64 i) const { return f[i]; }
-  __device__ T load_p(i64) const { return 0; }
-  __device__ Pre fetch_u(i64) const { return Pre{}; }
-  __device__ Pre fetch_p(i64) const { return Pre{}; }
-  __device__ void store_u(i64 i, T t, T, bool bc, const Pre &) const { y[i] = bc ? T(0) : t; }
-  __device__ void store_p(i64, T, T, const Pre &) const {}
+  template <class I>
+  __device__ T load_u(I i) const { return at(f, i); }
+  template <class I>
+  __device__ T load_p(I) const { return 0; }
+  template <class I>
+  __device__ Pre fetch_u(I) const { return Pre{}; }
+  template <class I>
+  __device__ Pre fetch_p(I) const { return Pre{}; }
+  template <class I>
+  __device__ void store_u(I i, T t, T, bool bc, const Pre &) const { at(y, i) = bc ? T(0) : t; }
+  template <class I>
+  __device__ void store_p(I, T, T, const Pre &) const {}
   double algo_bytes(bool, bool, bool, bool, double nu, double) const { return sizeof(T) * 2 * nu; }
 };
 
@@ -88,33 +106,39 @@ struct OpChebA {
   struct Pre {
     T r, x, dinv, base;
   };
-  __device__ T load_u(i64 i) const {
-    if constexpr (FIRST) return dinv[i] * rin[i] * inv_theta;
-    else return d[i];
+  template <class I>
+  __device__ T load_u(I i) const {
+    if constexpr (FIRST) return at(dinv, i) * at(rin, i) * inv_theta;
+    else return at(d, i);
   }
-  __device__ T load_p(i64) const { return 0; }
-  __device__ Pre fetch_u(i64 i) const {
+  template <class I>
+  __device__ T load_p(I) const { return 0; }
+  template <class I>
+  __device__ Pre fetch_u(I i) const {
     Pre q;
-    q.r = rin[i];
-    q.x = FIRST ? T(0) : x[i];
-    q.dinv = dinv[i];
-    q.base = (LAST && base) ? base[i] : T(0);
+    q.r = at(rin, i);
+    q.x = FIRST ? T(0) : at(x, i);
+    q.dinv = at(dinv, i);
+    q.base = (LAST && base) ? at(base, i) : T(0);
     return q;
   }
-  __device__ Pre fetch_p(i64) const { return Pre{}; }
-  __device__ void store_u(i64 i, T t, T v, bool, const Pre &q) const {
+  template <class I>
+  __device__ Pre fetch_p(I) const { return Pre{}; }
+  template <class I>
+  __device__ void store_u(I i, T t, T v, bool, const Pre &q) const {
     const T rn = q.r - t;
     const T xn = q.x + v;
     const T dn = c1 * v + c2 * q.dinv * rn;
     if constexpr (LAST) {
-      out[i] = q.base + s * (xn + dn);
+      at(out, i) = q.base + s * (xn + dn);
     } else {
-      r_out[i] = rn;
-      x_out[i] = xn;
-      d_out[i] = dn;
+      at(r_out, i) = rn;
+      at(x_out, i) = xn;
+      at(d_out, i) = dn;
     }
   }
-  __device__ void store_p(i64, T, T, const Pre &) const {}
+  template <class I>
+  __device__ void store_p(I, T, T, const Pre &) const {}
   double algo_bytes(bool, bool, bool, bool, double nu, double) const {
     const double reads = FIRST ? 2 : 4, writes = LAST ? (base ? 2 : 1) : 3;
     return sizeof(T) * nu * (reads + writes);
@@ -130,16 +154,22 @@ struct OpGrad {
   const T *rp, *dinv_s, *d;
   T inv_theta;
   T *q;
-  __device__ T load_u(i64) const { return 0; }
-  __device__ T load_p(i64 i) const {
-    if constexpr (FIRST) return dinv_s[i] * rp[i] * inv_theta;
-    else return d[i];
+  template <class I>
+  __device__ T load_u(I) const { return 0; }
+  template <class I>
+  __device__ T load_p(I i) const {
+    if constexpr (FIRST) return at(dinv_s, i) * at(rp, i) * inv_theta;
+    else return at(d, i);
   }
   struct Pre {};
-  __device__ Pre fetch_u(i64) const { return Pre{}; }
-  __device__ Pre fetch_p(i64) const { return Pre{}; }
-  __device__ void store_u(i64 i, T t, T, bool, const Pre &) const { q[i] = t; }
-  __device__ void store_p(i64, T, T, const Pre &) const {}
+  template <class I>
+  __device__ Pre fetch_u(I) const { return Pre{}; }
+  template <class I>
+  __device__ Pre fetch_p(I) const { return Pre{}; }
+  template <class I>
+  __device__ void store_u(I i, T t, T, bool, const Pre &) const { at(q, i) = t; }
+  template <class I>
+  __device__ void store_p(I, T, T, const Pre &) const {}
   double algo_bytes(bool, bool, bool, bool, double nu, double np) const {
     return sizeof(T) * ((FIRST ? 2 : 1) * np + nu);
   }
@@ -161,38 +191,44 @@ struct OpChebS {
   T *r_out, *x_out, *d_out;
   T *p, *dp;         // LAST
   T inv_theta, c1, c2, tau;
-  __device__ T load_u(i64 i) const { return w[i]; }
-  __device__ T load_p(i64 i) const {
-    if constexpr (FIRST) return dinv_s[i] * rin[i] * inv_theta;
-    else return d[i];
+  template <class I>
+  __device__ T load_u(I i) const { return at(w, i); }
+  template <class I>
+  __device__ T load_p(I i) const {
+    if constexpr (FIRST) return at(dinv_s, i) * at(rin, i) * inv_theta;
+    else return at(d, i);
   }
   struct Pre {
     T r, x, d, dinv, p;
   };
-  __device__ Pre fetch_u(i64) const { return Pre{}; }
-  __device__ Pre fetch_p(i64 i) const {
+  template <class I>
+  __device__ Pre fetch_u(I) const { return Pre{}; }
+  template <class I>
+  __device__ Pre fetch_p(I i) const {
     Pre q;
-    q.r = rin[i];
-    q.dinv = dinv_s[i];
-    q.x = FIRST ? T(0) : x[i];
-    q.d = FIRST ? q.dinv * q.r * inv_theta : d[i];
-    q.p = (LAST && p) ? p[i] : T(0);
+    q.r = at(rin, i);
+    q.dinv = at(dinv_s, i);
+    q.x = FIRST ? T(0) : at(x, i);
+    q.d = FIRST ? q.dinv * q.r * inv_theta : at(d, i);
+    q.p = (LAST && p) ? at(p, i) : T(0);
     return q;
   }
-  __device__ void store_u(i64, T, T, bool, const Pre &) const {}
-  __device__ void store_p(i64 i, T t, T, const Pre &q) const {
+  template <class I>
+  __device__ void store_u(I, T, T, bool, const Pre &) const {}
+  template <class I>
+  __device__ void store_p(I i, T t, T, const Pre &q) const {
     const T di = q.d;
     const T rn = q.r - t;
     const T xn = q.x + di;
     const T dn = c1 * di + c2 * q.dinv * rn;
     if constexpr (LAST) {
       const T delta = tau * (xn + dn);
-      dp[i] = delta;
-      if (p) p[i] = q.p + delta;
+      at(dp, i) = delta;
+      if (p) at(p, i) = q.p + delta;
     } else {
-      r_out[i] = rn;
-      x_out[i] = xn;
-      d_out[i] = dn;
+      at(r_out, i) = rn;
+      at(x_out, i) = xn;
+      at(d_out, i) = dn;
     }
   }
   double algo_bytes(bool, bool, bool, bool, double nu, double np) const {
@@ -209,15 +245,21 @@ struct OpDivResidual {
   static constexpr bool ZERO_BC = true;
   const T *u, *p_in, *g;
   T *rp;
-  __device__ T load_u(i64 i) const { return u[i]; }
-  __device__ T load_p(i64 i) const { return p_in[i]; }
+  template <class I>
+  __device__ T load_u(I i) const { return at(u, i); }
+  template <class I>
+  __device__ T load_p(I i) const { return at(p_in, i); }
   struct Pre {
     T g;
   };
-  __device__ Pre fetch_u(i64) const { return Pre{}; }
-  __device__ Pre fetch_p(i64 i) const { return Pre{g ? g[i] : T(0)}; }
-  __device__ void store_u(i64, T, T, bool, const Pre &) const {}
-  __device__ void store_p(i64 i, T t, T, const Pre &q) const { rp[i] = t - q.g; }
+  template <class I>
+  __device__ Pre fetch_u(I) const { return Pre{}; }
+  template <class I>
+  __device__ Pre fetch_p(I i) const { return Pre{g ? at(g, i) : T(0)}; }
+  template <class I>
+  __device__ void store_u(I, T, T, bool, const Pre &) const {}
+  template <class I>
+  __device__ void store_p(I i, T t, T, const Pre &q) const { at(rp, i) = t - q.g; }
   double algo_bytes(bool, bool need_p, bool, bool, double nu, double np) const {
     return sizeof(T) * (nu + (need_p ? np : 0) + (g ? np : 0) + np);
   }
