@@ -9,6 +9,7 @@
 #include "engine.hpp"
 #include "ops.hpp"
 #include "setup_kernels.hpp"
+#include "transfer_kernels.hpp"
 #include "vec_kernels.hpp"
 
 namespace smg {
@@ -423,61 +424,52 @@ class EngineT : public EngineBase {
   }
 
   // ------------------------------------------------------------ transfers
-  TransferField tfield(int lf, bool velocity) {
-    TransferField F;
-    std::memset(&F, 0, sizeof(F));
+  template <typename T>
+  XferGeo<T> xfer_geo(int lf, bool velocity) {
+    XferGeo<T> g;
+    std::memset(&g, 0, sizeof(g));
     const LevelInfo &f = lv[lf], &c = lv[lf - 1];
-    F.deg = velocity ? K : K - 1;
     for (int a = 0; a < 3; ++a) {
-      F.cdim[a] = velocity ? c.vd[a] : c.pd[a];
-      F.fdim[a] = velocity ? f.vd[a] : f.pd[a];
-      F.ncell_f[a] = f.n[a];
+      g.cdim[a] = velocity ? c.vd[a] : c.pd[a];
+      g.fdim[a] = velocity ? f.vd[a] : f.pd[a];
+      g.ncell_f[a] = f.n[a];
     }
-    F.coff = velocity ? 0 : c.Nu;
-    F.foff = velocity ? 0 : f.Nu;
-    F.ncomp = velocity ? DIM : 1;
-    F.cstride = velocity ? c.Nv : 0;
-    F.fstride = velocity ? f.Nv : 0;
-    F.bc = velocity ? 1 : 0;
-    return F;
+    g.coff = velocity ? 0 : c.Nu;
+    g.foff = velocity ? 0 : f.Nu;
+    g.cstride = velocity ? c.Nv : 0;
+    g.fstride = velocity ? f.Nv : 0;
+    for (int i = 0; i < 28; ++i) g.W[i] = (T)ttab.W[velocity ? 0 : 1][i];
+    return g;
   }
 
   template <typename T>
   void prolongate_t(int lf, const T *wc, T *xf) {
-    TransferField fv = tfield(lf, true), fp = tfield(lf, false);
-    const i64 nfv = lv[lf].Nv, nfp = lv[lf].Np;
-    const i64 total = nfv * DIM + nfp;
-    hipLaunchKernelGGL((k_prolongate_add<T, DIM>), dim3(grid_for(total)), dim3(VB), 0, stream, wc, xf, fv, fp, ttab, nfv, nfp);
-    check_launch();
+    for (int field = 0; field < 2; ++field) {
+      const bool vel = field == 0;
+      const XferGeo<T> g = xfer_geo<T>(lf, vel);
+      const unsigned nz = (unsigned)((DIM == 3 ? g.fdim[2] : 1) * (vel ? DIM : 1));
+      const dim3 grid((unsigned)((g.fdim[0] + 127) / 128), (unsigned)g.fdim[1], nz);
+      if (vel)
+        hipLaunchKernelGGL((k_prolong<T, DIM, K, true>), grid, dim3(128), 0, stream, wc, xf, g);
+      else
+        hipLaunchKernelGGL((k_prolong<T, DIM, K - 1, false>), grid, dim3(128), 0, stream, wc, xf, g);
+      check_launch();
+    }
   }
 
   template <typename T>
   void restrict_t(int lf, const T *rf, T *rc) {
-    Work<T> &W = work<T>(lf);
+    constexpr int CX = 128;
     for (int field = 0; field < 2; ++field) {
       const bool vel = field == 0;
-      TransferField F = tfield(lf, vel);
-      int dims[3] = {F.fdim[0], F.fdim[1], F.fdim[2]};
-      const T *in = rf;
-      i64 in_off = F.foff, in_cs = vel ? F.fstride : 0;
-      for (int dir = 0; dir < DIM; ++dir) {
-        int od[3] = {dims[0], dims[1], dims[2]};
-        od[dir] = F.cdim[dir];
-        const bool lastp = dir == DIM - 1;
-        T *out = lastp ? rc : (dir % 2 == 0 ? W.t1 : W.t2);
-        const i64 per = (i64)od[0] * od[1] * od[2];
-        const i64 out_off = lastp ? F.coff : 0;
-        const i64 out_cs = lastp ? (vel ? F.cstride : 0) : per;
-        hipLaunchKernelGGL((k_restrict_pass<T>), dim3(grid_for(per * F.ncomp)), dim3(VB), 0, stream,
-                           in, out, dir, F.deg, F.ncell_f[dir], dims[0], dims[1], dims[2], od[0], od[1], od[2],
-                           F.ncomp, in_cs, out_cs, in_off, out_off, ttab, field, (int)(dir == 0 && F.bc),
-                           (int)(lastp && F.bc), F.fdim[0], F.fdim[1], F.fdim[2], F.cdim[0], F.cdim[1], F.cdim[2], DIM);
-        check_launch();
-        in = out;
-        in_off = out_off;
-        in_cs = out_cs;
-        for (int a = 0; a < 3; ++a) dims[a] = od[a];
-      }
+      const XferGeo<T> g = xfer_geo<T>(lf, vel);
+      const unsigned nz = (unsigned)((DIM == 3 ? g.cdim[2] : 1) * (vel ? DIM : 1));
+      const dim3 grid((unsigned)((g.cdim[0] + CX - 1) / CX), (unsigned)g.cdim[1], nz);
+      if (vel)
+        hipLaunchKernelGGL((k_restrict<T, DIM, K, true, CX>), grid, dim3(256), 0, stream, rf, rc, g);
+      else
+        hipLaunchKernelGGL((k_restrict<T, DIM, K - 1, false, CX>), grid, dim3(256), 0, stream, rf, rc, g);
+      check_launch();
     }
   }
 

@@ -116,132 +116,10 @@ __global__ void k_multi_axpy(T *w, const T *V, i64 ldv, int nv, const double *h,
 // ---------------------------------------------------------------------------
 // transfers (Sec. 3.2): canonical injection P per field, R = P^T
 // ---------------------------------------------------------------------------
-struct TransferField {
-  int deg;              // polynomial degree of the field (k or k-1)
-  int cdim[3], fdim[3]; // lattice extents, coarse and fine
-  int ncell_f[3];       // fine cells per direction
-  i64 coff, foff;       // offsets of the field in the coarse / fine vectors
-  int ncomp;            // consecutive components (d for velocity, 1 for pressure)
-  i64 cstride, fstride; // distance between components
-  int bc;               // 1: Dirichlet field (velocity)
-};
-
+// 1D prolongation weights of both fields (host tables, see transfer kernels)
 struct TransferTables {
   double W[2][7 * 4];   // W[field][f * (deg+1) + j], f = 0..2deg; field 0 = velocity, 1 = pressure
 };
-
-// coarse cell index of fine lattice node f and its position 0..2deg in it
-__device__ __forceinline__ void fine_in_coarse(int f, int deg, int nf_cells, int &cc, int &pos) {
-  int cf = f / deg;
-  if (cf > nf_cells - 1) cf = nf_cells - 1;
-  cc = cf >> 1;
-  pos = f - 2 * deg * cc;
-}
-
-// x_f += P w_c for every field; one thread per fine node and component.
-template <typename T, int DIM>
-__global__ void k_prolongate_add(const T *wc, T *xf, TransferField fv, TransferField fp, TransferTables tab, i64 n_fine_v, i64 n_fine_p) {
-  const i64 total = n_fine_v * fv.ncomp + n_fine_p;
-  SMG_GRID_LOOP(gi, total) {
-    const bool isv = gi < n_fine_v * fv.ncomp;
-    const TransferField &F = isv ? fv : fp;
-    const double *W = isv ? tab.W[0] : tab.W[1];
-    i64 node, comp = 0;
-    if (isv) { comp = gi / n_fine_v; node = gi - comp * n_fine_v; } else { node = gi - n_fine_v * fv.ncomp; }
-    int fi[3] = {0, 0, 0};
-    i64 r = node;
-    for (int a = 0; a < DIM; ++a) { fi[a] = (int)(r % F.fdim[a]); r /= F.fdim[a]; }
-    bool fbc = false;
-    if (F.bc)
-      for (int a = 0; a < DIM; ++a) fbc |= (fi[a] == 0 || fi[a] == F.fdim[a] - 1);
-    if (fbc) continue;
-    int cc[3], pos[3];
-    for (int a = 0; a < DIM; ++a) fine_in_coarse(fi[a], F.deg, F.ncell_f[a], cc[a], pos[a]);
-    const int nd = F.deg + 1;
-    double s = 0.0;
-    const int jz_n = DIM == 3 ? nd : 1;
-    for (int jz = 0; jz < jz_n; ++jz) {
-      const double wz = DIM == 3 ? W[pos[2] * nd + jz] : 1.0;
-      const int cz = DIM == 3 ? F.deg * cc[2] + jz : 0;
-      if (wz == 0.0) continue;
-      for (int jy = 0; jy < nd; ++jy) {
-        const double wy = W[pos[1] * nd + jy];
-        if (wy == 0.0) continue;
-        const int cy = F.deg * cc[1] + jy;
-        for (int jx = 0; jx < nd; ++jx) {
-          const double wx = W[pos[0] * nd + jx];
-          if (wx == 0.0) continue;
-          const int cx = F.deg * cc[0] + jx;
-          bool cbc = false;
-          if (F.bc)
-            cbc = cx == 0 || cx == F.cdim[0] - 1 || cy == 0 || cy == F.cdim[1] - 1 ||
-                  (DIM == 3 && (cz == 0 || cz == F.cdim[2] - 1));
-          if (cbc) continue;
-          const i64 ci = F.coff + comp * F.cstride + cx + (i64)F.cdim[0] * (cy + (i64)F.cdim[1] * cz);
-          s += wx * wy * wz * (double)wc[ci];
-        }
-      }
-    }
-    const i64 fidx = F.foff + comp * F.fstride + node;
-    xf[fidx] = (T)((double)xf[fidx] + s);
-  }
-}
-
-// One direction of R = P^T: in has fine extent along `dir`, out coarse
-// extent; other directions as given by in_dim/out_dim.  `mask_in` zeroes
-// Dirichlet inputs (first pass), `mask_out` zeroes Dirichlet outputs (last pass),
-// both judged on the full fine/coarse lattices fdim/cdim.
-template <typename T>
-__global__ void k_restrict_pass(const T *in, T *out, int dir, int deg, int n_cells_f,
-                                int in_d0, int in_d1, int in_d2, int out_d0, int out_d1, int out_d2,
-                                int ncomp, i64 in_cstride, i64 out_cstride, i64 in_off, i64 out_off,
-                                TransferTables tab, int field, int mask_in, int mask_out,
-                                int f0, int f1, int f2, int c0, int c1, int c2, int dim) {
-  const i64 per = (i64)out_d0 * out_d1 * out_d2;
-  const i64 total = per * ncomp;
-  const double *W = tab.W[field];
-  const int nd = deg + 1;
-  const int in_dims[3] = {in_d0, in_d1, in_d2};
-  const int fd[3] = {f0, f1, f2}, cd[3] = {c0, c1, c2};
-  SMG_GRID_LOOP(gi, total) {
-    const i64 comp = gi / per;
-    i64 r = gi - comp * per;
-    int o[3];
-    o[0] = (int)(r % out_d0); r /= out_d0;
-    o[1] = (int)(r % out_d1); r /= out_d1;
-    o[2] = (int)r;
-    // coarse index J along dir
-    const int J = o[dir];
-    bool obc = false;
-    if (mask_out) {
-      for (int a = 0; a < dim; ++a) obc |= (o[a] == 0 || o[a] == cd[a] - 1);
-    }
-    double s = 0.0;
-    if (!obc) {
-      int flo = 2 * J - 2 * deg, fhi = 2 * J + 2 * deg;
-      if (flo < 0) flo = 0;
-      if (fhi > in_dims[dir] - 1) fhi = in_dims[dir] - 1;
-      for (int f = flo; f <= fhi; ++f) {
-        int cc, pos;
-        fine_in_coarse(f, deg, n_cells_f, cc, pos);
-        const int j = J - deg * cc;
-        if (j < 0 || j > deg) continue;
-        const double w = W[pos * nd + j];
-        if (w == 0.0) continue;
-        int ii[3] = {o[0], o[1], o[2]};
-        ii[dir] = f;
-        if (mask_in) {
-          bool ibc = false;
-          for (int a = 0; a < dim; ++a) ibc |= (ii[a] == 0 || ii[a] == fd[a] - 1);
-          if (ibc) continue;
-        }
-        const i64 idx = in_off + comp * in_cstride + ii[0] + (i64)in_dims[0] * (ii[1] + (i64)in_dims[1] * ii[2]);
-        s += w * (double)in[idx];
-      }
-    }
-    out[out_off + comp * out_cstride + o[0] + (i64)out_d0 * (o[1] + (i64)out_d1 * o[2])] = (T)s;
-  }
-}
 
 // ---------------------------------------------------------------------------
 // coarse solve: x0 = Kinv[0:N0, 0:N0] b0 (border column multiplies zero),
