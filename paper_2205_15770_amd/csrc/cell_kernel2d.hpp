@@ -1,0 +1,262 @@
+// Wave-tile application of the Taylor-Hood saddle-point operator
+// K = [A B^T; B -C] on axis-aligned box cells in 2D (Sec. 3.1: K x =
+// sum_tau P_tau K_tau P_tau^T x, cell matrices by sum factorisation).
+//
+// Work decomposition (gfx950): one wave64 per tile of 8 x 8 cells, one cell
+// per lane (lane = x + 8 y).  The tile owns 7 x 7 cells; lane column 0 and
+// lane row 0 are halo cells whose results are computed only to be handed
+// over.  A lane applies both velocity blocks and the pressure block of its
+// cell.  Contributions to nodes shared with the right / upper neighbour go to
+// lane + 1 / lane + 8 by lane shuffles; afterwards each cell holds the
+// complete sums of its nodes with local indices [0, K) (plus the domain high
+// faces) and writes them through the epilogue functor.  No LDS, no barriers,
+// no atomics; every output entry is written once.
+//
+// Cell matrices: compile-time 1D reference matrices and per-direction
+// scalars; on a cell of widths (h_x, h_y)
+//   A_cell = mu [sKx Kr(x)Mr + sKy Mr(x)Kr] + gamma rho sM Mr(x)Mr,
+//   B_c    = -sB_c (Gr in direction c, Nr in the other),  C = cp sM Mpr(x)Mpr,
+// with sKx = h_y / h_x, sKy = h_x / h_y, sM = h_x h_y, sB_x = h_y, sB_y = h_x.
+#pragma once
+#include "cell_kernel.hpp"
+#include "fe1d_const.hpp"
+
+namespace smg {
+
+template <typename T>
+struct Geo2 {
+  int n[2];        // cells per direction
+  int vd[2];       // velocity lattice extent per direction
+  int pd[2];       // pressure lattice extent per direction
+  int tiles[2];    // 8x8 wave tiles per direction
+  uint32_t nv_bytes;  // bytes of one velocity component vector
+  T mu, gr, cp;
+  const T *mu_cell;
+  T sKx, sKy, sM;
+  T sB[2];
+};
+
+template <int K, typename T, int BLK, class Op>
+__global__ void __launch_bounds__(64)
+wave2d_kernel(const Geo2<T> g, const Op op) {
+  constexpr int NV = K + 1, NP = K, TX = 8;
+  constexpr uint32_t ST = sizeof(T);
+  constexpr cfe::TabT<K, T> R = cfe::make_tab_t<K, T>();
+  constexpr bool OUT_U = (BLK & (BLK_A | BLK_MASS | BLK_BT)) != 0;
+  constexpr bool OUT_P = (BLK & (BLK_B | BLK_C)) != 0;
+  constexpr bool NEED_U = (BLK & (BLK_A | BLK_MASS | BLK_B)) != 0;
+  constexpr bool NEED_P = (BLK & (BLK_BT | BLK_C)) != 0;
+
+  const int b = xcd_contiguous_tile(blockIdx.x, gridDim.x);
+  const int tx = b % g.tiles[0], ty = b / g.tiles[0];
+  const int lcx = threadIdx.x % TX, lcy = threadIdx.x / TX;
+  const int gcx = tx * (TX - 1) - 1 + lcx, gcy = ty * (TX - 1) - 1 + lcy;
+  const bool active = gcx >= 0 && gcx < g.n[0] && gcy >= 0 && gcy < g.n[1];
+  const bool owner = active && lcx > 0 && lcy > 0;
+  const bool bxl = gcx == 0, bxh = gcx == g.n[0] - 1, byl = gcy == 0, byh = gcy == g.n[1] - 1;
+  // halo lanes outside the mesh read a valid cell and discard the values
+  const int ax = gcx < 0 ? 0 : (gcx >= g.n[0] ? g.n[0] - 1 : gcx);
+  const int ay = gcy < 0 ? 0 : (gcy >= g.n[1] ? g.n[1] - 1 : gcy);
+  const uint32_t suy = ST * (uint32_t)g.vd[0], spy = ST * (uint32_t)g.pd[0];
+  const uint32_t base_u = ST * (uint32_t)(K * ax) + suy * (uint32_t)(K * ay);
+  const uint32_t base_p = ST * (uint32_t)((K - 1) * ax) + spy * (uint32_t)((K - 1) * ay);
+  auto u_at = [&](int c, int x, int y) { return BOff{(uint32_t)c * g.nv_bytes + base_u + suy * (uint32_t)y, ST * (uint32_t)x}; };
+  auto p_at = [&](int x, int y) { return BOff{base_p + spy * (uint32_t)y, ST * (uint32_t)x}; };
+  auto vbc = [&](int x, int y) { return ((x == 0) & bxl) | ((x == K) & bxh) | ((y == 0) & byl) | ((y == K) & byh); };
+
+  // 1. requests: cell DoFs, viscosity, epilogue inputs of the owned nodes
+  T u[2][1][NV][NV], p[1][NP][NP];
+  if constexpr (NEED_U) {
+#pragma unroll
+    for (int c = 0; c < 2; ++c)
+#pragma unroll
+      for (int y = 0; y < NV; ++y)
+#pragma unroll
+        for (int x = 0; x < NV; ++x) u[c][0][y][x] = op.load_u(u_at(c, x, y));
+  }
+  if constexpr (NEED_P) {
+#pragma unroll
+    for (int y = 0; y < NP; ++y)
+#pragma unroll
+      for (int x = 0; x < NP; ++x) p[0][y][x] = op.load_p(p_at(x, y));
+  }
+  T mu = g.mu;
+  if constexpr ((BLK & BLK_A) != 0)
+    if (g.mu_cell != nullptr) mu = g.mu_cell[(uint32_t)ax + (uint32_t)g.n[0] * (uint32_t)ay];
+  typename Op::Pre pre_u[2][K][K];
+  typename Op::Pre pre_p[K - 1][K - 1];
+  if (owner) {
+    if constexpr (OUT_U) {
+#pragma unroll
+      for (int c = 0; c < 2; ++c)
+#pragma unroll
+        for (int y = 0; y < K; ++y)
+#pragma unroll
+          for (int x = 0; x < K; ++x) pre_u[c][y][x] = op.fetch_u(u_at(c, x, y));
+    }
+    if constexpr (OUT_P) {
+#pragma unroll
+      for (int y = 0; y < K - 1; ++y)
+#pragma unroll
+        for (int x = 0; x < K - 1; ++x) pre_p[y][x] = op.fetch_p(p_at(x, y));
+    }
+  }
+  // keep the requests above unconditional: no load below this point may be
+  // moved into a branch by the select that follows
+  __asm__ volatile("" ::: "memory");
+
+  // 2. mask: inactive cells, Dirichlet inputs (ZERO_BC)
+  if constexpr (NEED_U) {
+#pragma unroll
+    for (int c = 0; c < 2; ++c)
+#pragma unroll
+      for (int y = 0; y < NV; ++y)
+#pragma unroll
+        for (int x = 0; x < NV; ++x) {
+          const bool keep = active & !(Op::ZERO_BC & vbc(x, y));
+          u[c][0][y][x] = keep ? u[c][0][y][x] : T(0);
+        }
+  } else {
+#pragma unroll
+    for (int c = 0; c < 2; ++c)
+#pragma unroll
+      for (int y = 0; y < NV; ++y)
+#pragma unroll
+        for (int x = 0; x < NV; ++x) u[c][0][y][x] = 0;
+  }
+  if constexpr (NEED_P) {
+#pragma unroll
+    for (int y = 0; y < NP; ++y)
+#pragma unroll
+      for (int x = 0; x < NP; ++x) p[0][y][x] = active ? p[0][y][x] : T(0);
+  } else {
+#pragma unroll
+    for (int y = 0; y < NP; ++y)
+#pragma unroll
+      for (int x = 0; x < NP; ++x) p[0][y][x] = 0;
+  }
+
+  // 3. cell matrices
+  T yu[2][1][NV][NV], yp[1][NP][NP];
+  if constexpr ((BLK & BLK_A) != 0) {
+    T X[NV][NV];
+    const T axk = mu * g.sKx, bxm = g.gr * g.sM;
+#pragma unroll
+    for (int i = 0; i < NV; ++i)
+#pragma unroll
+      for (int j = 0; j < NV; ++j) X[i][j] = axk * R.Kr[i][j] + bxm * R.Mr[i][j];
+    const T sy = mu * g.sKy;
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+      T t[1][NV][NV];
+      pass_y<false, false>(R.Mr, u[c], t, T(1));
+      pass_x<false, false>(X, t, yu[c], T(1));
+      pass_y<false, false>(R.Kr, u[c], t, T(1));
+      pass_x<false, true>(R.Mr, t, yu[c], sy);
+    }
+  } else if constexpr ((BLK & BLK_MASS) != 0) {
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+      T t[1][NV][NV];
+      pass_y<false, false>(R.Mr, u[c], t, T(1));
+      pass_x<false, false>(R.Mr, t, yu[c], g.sM);
+    }
+  }
+  if constexpr ((BLK & BLK_BT) != 0) {
+    constexpr bool ACC = (BLK & (BLK_A | BLK_MASS)) != 0;
+    T s[1][NV][NP];
+    pass_y<true, false>(R.Nr, p, s, T(1));
+    pass_x<true, ACC>(R.Gr, s, yu[0], -g.sB[0]);
+    T s2[1][NP][NV];
+    pass_x<true, false>(R.Nr, p, s2, T(1));
+    pass_y<true, ACC>(R.Gr, s2, yu[1], -g.sB[1]);
+  } else if constexpr (!OUT_U) {
+#pragma unroll
+    for (int c = 0; c < 2; ++c)
+#pragma unroll
+      for (int y = 0; y < NV; ++y)
+#pragma unroll
+        for (int x = 0; x < NV; ++x) yu[c][0][y][x] = 0;
+  }
+  if constexpr (OUT_P) {
+    if constexpr ((BLK & BLK_B) != 0) {
+      T w[1][NV][NP];
+      pass_x<false, false>(R.Gr, u[0], w, T(1));
+      pass_y<false, false>(R.Nr, w, yp, -g.sB[0]);
+      pass_x<false, false>(R.Nr, u[1], w, T(1));
+      pass_y<false, true>(R.Gr, w, yp, -g.sB[1]);
+    }
+    if constexpr ((BLK & BLK_C) != 0) {
+      constexpr bool ACC = (BLK & BLK_B) != 0;
+      const T sc = ((BLK & BLK_CPLUS) ? g.cp : -g.cp) * g.sM;
+      T q[1][NP][NP];
+      pass_x<false, false>(R.Mpr, p, q, T(1));
+      pass_y<false, ACC>(R.Mpr, q, yp, sc);
+    }
+  }
+
+  // 4. hand-over to the right (lane + 1) and upper (lane + 8) neighbours
+  if constexpr (OUT_U) {
+#pragma unroll
+    for (int c = 0; c < 2; ++c) hand_over_xy<TX>(yu[c], lcx, lcy, bxh, byh);
+  }
+  if constexpr (OUT_P) hand_over_xy<TX>(yp, lcx, lcy, bxh, byh);
+
+  // 5. owned nodes
+  if (!owner) return;
+  if constexpr (OUT_U) {
+#pragma unroll
+    for (int c = 0; c < 2; ++c)
+#pragma unroll
+      for (int y = 0; y < K; ++y)
+#pragma unroll
+        for (int x = 0; x < K; ++x) op.store_u(u_at(c, x, y), yu[c][0][y][x], u[c][0][y][x], false, pre_u[c][y][x]);
+    if (bxl | byl) {
+      // Dirichlet rows on the low faces (rewritten: same lane, program order)
+#pragma unroll
+      for (int c = 0; c < 2; ++c)
+#pragma unroll
+        for (int y = 0; y < K; ++y)
+#pragma unroll
+          for (int x = 0; x < K; ++x) {
+            if (!vbc(x, y)) continue;
+            const BOff gi = u_at(c, x, y);
+            T rw = 0;
+            if constexpr ((BLK & BLK_A) != 0) rw = op.load_u(gi);
+            op.store_u(gi, rw, rw, true, pre_u[c][y][x]);
+          }
+    }
+    if (bxh | byh) {
+      // nodes on the domain's high faces: Dirichlet rows
+#pragma unroll
+      for (int c = 0; c < 2; ++c)
+#pragma unroll
+        for (int y = 0; y < NV; ++y)
+#pragma unroll
+          for (int x = 0; x < NV; ++x) {
+            if (x < K && y < K) continue;
+            if ((x == K && !bxh) || (y == K && !byh)) continue;
+            const BOff gi = u_at(c, x, y);
+            T rw = 0;
+            if constexpr ((BLK & BLK_A) != 0) rw = op.load_u(gi);
+            op.store_u(gi, rw, rw, true, op.fetch_u(gi));
+          }
+    }
+  }
+  if constexpr (OUT_P) {
+#pragma unroll
+    for (int y = 0; y < NP; ++y)
+#pragma unroll
+      for (int x = 0; x < NP; ++x) {
+        const bool main = x < K - 1 && y < K - 1;
+        if (main) {
+          op.store_p(p_at(x, y), yp[0][y][x], p[0][y][x], pre_p[main ? y : 0][main ? x : 0]);
+        } else if (((x < K - 1) | bxh) & ((y < K - 1) | byh)) {
+          const BOff gi = p_at(x, y);
+          op.store_p(gi, yp[0][y][x], p[0][y][x], op.fetch_p(gi));
+        }
+      }
+  }
+}
+
+}  // namespace smg

@@ -143,30 +143,6 @@ struct Column3D {
   }
 };
 
-// Hand the x = N-1 and y = N-1 faces of a cell array to the neighbouring lanes
-// (x: lane + 1 within a row of TX lanes, y: lane + TX) and add what arrives
-// from the other side to the x = 0 / y = 0 faces.  Faces that were handed
-// over are cleared unless they lie on the domain's high boundary.
-template <int TX, typename T, int NZ, int N>
-__device__ __forceinline__ void hand_over_xy(T (&y)[NZ][N][N], int lcx, int lcy, bool last_x, bool last_y) {
-#pragma unroll
-  for (int z = 0; z < NZ; ++z)
-#pragma unroll
-    for (int j = 0; j < N; ++j) {
-      const T r = __shfl_up(y[z][j][N - 1], 1, TX);
-      if (lcx > 0) y[z][j][0] += r;
-      if (!last_x) y[z][j][N - 1] = 0;
-    }
-#pragma unroll
-  for (int z = 0; z < NZ; ++z)
-#pragma unroll
-    for (int i = 0; i < N; ++i) {
-      const T r = __shfl_up(y[z][N - 1][i], TX, 64);
-      if (lcy > 0) y[z][0][i] += r;
-      if (!last_y) y[z][N - 1][i] = 0;
-    }
-}
-
 // Sweep geometry shared by the wave roles.
 struct Sweep {
   int lcx, lcy;     // lane position in the tile

@@ -5,6 +5,7 @@
 #include <chrono>
 #include <cstdio>
 
+#include "cell_kernel2d.hpp"
 #include "cell_kernel3d.hpp"
 #include "engine.hpp"
 #include "ops.hpp"
@@ -174,7 +175,28 @@ class EngineT : public EngineBase {
       SMG_HIP(hipEventRecord(ea, stream));
     }
     if constexpr (DIM == 2) {
-      hipLaunchKernelGGL((tile2d_kernel<K, T, BLK, Op, TX, TY>), dim3(nblk), dim3(TX * TY), 0, stream, g, op);
+      // 8 x 8 cells per wave, one cell per lane
+      Geo2<T> g2;
+      std::memset(&g2, 0, sizeof(g2));
+      for (int a = 0; a < 2; ++a) {
+        g2.n[a] = g.n[a];
+        g2.vd[a] = g.vd[a];
+        g2.pd[a] = g.pd[a];
+        g2.tiles[a] = (g.n[a] + 6) / 7;
+      }
+      g2.nv_bytes = (uint32_t)(g.Nv * (int64_t)sizeof(T));
+      g2.mu = g.mu;
+      g2.gr = g.gr;
+      g2.cp = g.cp;
+      g2.mu_cell = g.mu_cell;
+      const double hx = g.h[0], hy = g.h[1];
+      g2.sKx = (T)(hy / hx);
+      g2.sKy = (T)(hx / hy);
+      g2.sM = (T)(hx * hy);
+      g2.sB[0] = (T)hy;
+      g2.sB[1] = (T)hx;
+      const unsigned nb2 = (unsigned)(g2.tiles[0] * g2.tiles[1]);
+      hipLaunchKernelGGL((wave2d_kernel<K, T, BLK, Op>), dim3(nb2), dim3(64), 0, stream, g2, op);
     } else if constexpr (K != 2) {
       // Q3-Q2 in 3D: colour-phase tile kernel (the column sweep is built for
       // Q2-Q1 only; its Q3 variants spill to scratch and are switched off)
@@ -770,9 +792,9 @@ class EngineT : public EngineBase {
       I.Nu = DIM * I.Nv;
       I.N = I.Nu + I.Np;
     }
-    // the 3D operator kernel addresses a level vector's velocity block by
-    // 32-bit byte offsets
-    if (DIM == 3 && (double)lv[L].Nu * sizeof(double) >= 4294967296.0)
+    // the operator kernels address a level vector's velocity block by 32-bit
+    // byte offsets
+    if ((double)lv[L].Nu * sizeof(double) >= 4294967296.0)
       throw Error{SMG_EUNSUPPORTED, "finest level too large: velocity block exceeds 4 GiB"};
     // per-cell viscosity: finest as given, coarser levels by averaging children
     if (desc.mu_cell) {
