@@ -40,7 +40,7 @@ class StokesMG:
     def __init__(self, dim=2, fe_degree=2, n_coarse=(4, 4, 4), n_levels=3, box_lo=(0.0, 0.0, 0.0),
                  box_hi=(1.0, 1.0, 1.0), mu=1.0, mu_cell=None, gamma=0.0, rho=1.0, c_pressure=0.0,
                  cheb_deg_A=1, cheb_deg_S=1, smooth_steps=2, cycle_index=1, schur_diag="d",
-                 precision="f64", fgmres_restart=30, stream=None):
+                 precision="f64", fgmres_restart=30, stream=None, fine_vertices=None):
         import torch
         self.lib = _lib.load()
         d = _lib.SmgDesc()
@@ -53,6 +53,11 @@ class StokesMG:
             d.box_hi[a] = float((list(box_hi) + [1.0] * 3)[a])
         d.mu, d.gamma, d.rho, d.c_pressure = float(mu), float(gamma), float(rho), float(c_pressure)
         self._mu_cell = None
+        self._verts = None
+        if fine_vertices is not None:
+            # (n_f + 1)^d vertices x d coordinates, x fastest (read during create)
+            self._verts = np.ascontiguousarray(fine_vertices, dtype=np.float64).reshape(-1)
+            d.fine_vertices = self._verts.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
         if mu_cell is not None:
             self._mu_cell = np.ascontiguousarray(mu_cell, dtype=np.float64)
             d.mu_cell = self._mu_cell.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
@@ -71,6 +76,7 @@ class StokesMG:
         _lib.check(self.lib.smg_create(ctypes.byref(d), ctypes.byref(h)))
         self._h = h
         self._mu_cell = None
+        self._verts = None
 
     # -- housekeeping ---------------------------------------------------
     def close(self):

@@ -35,6 +35,8 @@ struct LevelGeom {
   T gr;            // gamma * rho
   T cp;            // c_pressure (C = cp M_p)
   const T *mu_cell;
+  const T *verts;  // vertex coordinates of general cells (nullptr: box cells)
+  T *gs;           // scratch of length N for the general-cell path
   double h[3];     // cell widths
   Coef1D<T, K> c[DIM];
 };

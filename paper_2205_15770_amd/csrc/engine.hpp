@@ -35,9 +35,10 @@ struct Work {
   T *cr = nullptr, *cx = nullptr, *cd[2] = {nullptr, nullptr};  // Chebyshev state, A
   T *rp = nullptr, *dp = nullptr;                     // pressure (Np)
   T *sr = nullptr, *sx = nullptr, *sd[2] = {nullptr, nullptr};  // Chebyshev state, S~
-  T *t1 = nullptr, *t2 = nullptr;                     // transfer intermediates (length N)
+  T *t1 = nullptr, *t2 = nullptr;                     // scratch (length N): general-cell accumulation
   T *dinvA = nullptr, *dinvS = nullptr;               // inverse diagonals
   T *mu_cell = nullptr;                               // per-cell viscosity (optional)
+  T *verts = nullptr;                                 // vertex coordinates (general cells)
 };
 
 struct LevelInfo {

@@ -6,6 +6,7 @@
 #include <cstdio>
 
 #include "cell_kernel2d.hpp"
+#include "gen_kernel.hpp"
 #include "cell_kernel3d.hpp"
 #include "engine.hpp"
 #include "ops.hpp"
@@ -55,6 +56,8 @@ class EngineT : public EngineBase {
 
   Ref1D ref;
   TransferTables ttab;
+  bool general = false;                      // cells given by vertices
+  std::vector<std::vector<double>> hverts;   // per level, host copy (node coordinates)
   double *Kinv = nullptr;
   int n0 = 0;
   double sigma = 0, tau = 0;
@@ -143,6 +146,8 @@ class EngineT : public EngineBase {
     g.gr = (T)(desc.gamma * desc.rho);
     g.cp = (T)(unit_cp ? 1.0 : desc.c_pressure);
     g.mu_cell = work<T>(l).mu_cell;
+    g.verts = work<T>(l).verts;
+    g.gs = work<T>(l).t1;
     for (int a = 0; a < 3; ++a) g.h[a] = I.h[a];
     const int nv = K + 1, np = K;
     for (int a = 0; a < DIM; ++a) {
@@ -174,7 +179,9 @@ class EngineT : public EngineBase {
       eb = next_event();
       SMG_HIP(hipEventRecord(ea, stream));
     }
-    if constexpr (DIM == 2) {
+    if (general) {
+      gen_tile<T, BLK, Op>(g, op);
+    } else if constexpr (DIM == 2) {
       // 8 x 8 cells per wave, one cell per lane
       Geo2<T> g2;
       std::memset(&g2, 0, sizeof(g2));
@@ -248,6 +255,98 @@ class EngineT : public EngineBase {
       constexpr bool OU = (BLK & (BLK_A | BLK_MASS | BLK_BT)) != 0, OP = (BLK & (BLK_B | BLK_C)) != 0;
       const double bytes = op.algo_bytes(NU, NP, OU, OP, (double)(DIM * g.Nv), (double)g.Np);
       prof.push_back(ProfRec{key, ea, eb, bytes});
+    }
+  }
+
+  // General (vertex-given) cells: 2^d colour launches accumulate the cell
+  // sums into the level scratch, then one pass applies Dirichlet rows and
+  // the epilogue functor.
+  template <typename T, int BLK, class Op>
+  void gen_tile(const LevelGeom<T, DIM, K> &g, const Op &op) {
+    GenGeo<T> gg;
+    std::memset(&gg, 0, sizeof(gg));
+    for (int a = 0; a < 3; ++a) {
+      gg.n[a] = g.n[a];
+      gg.vd[a] = g.vd[a];
+      gg.pd[a] = g.pd[a];
+    }
+    gg.Nv = g.Nv;
+    gg.Np = g.Np;
+    gg.mu = g.mu;
+    gg.gr = g.gr;
+    gg.cp = g.cp;
+    gg.mu_cell = g.mu_cell;
+    gg.verts = g.verts;
+    gg.tu = g.gs;
+    gg.tp = g.gs + (int64_t)DIM * g.Nv;
+    const int64_t n_all = (int64_t)DIM * g.Nv + g.Np;
+    vset<T>(g.gs, (T)0, n_all);
+    constexpr int NN = DIM == 3 ? (K + 1) * (K + 1) * (K + 1) : (K + 1) * (K + 1);
+    constexpr int CPB = 64 / NN;
+    for (int colour = 0; colour < (1 << DIM); ++colour) {
+      int64_t ncells = 1;
+      for (int a = 0; a < 3; ++a) {
+        gg.off[a] = a < DIM ? (colour >> a) & 1 : 0;
+        gg.ncol[a] = a < DIM ? (g.n[a] - gg.off[a] + 1) / 2 : 1;
+        ncells *= gg.ncol[a];
+      }
+      if (ncells == 0) continue;
+      const unsigned nb = (unsigned)((ncells + CPB - 1) / CPB);
+      hipLaunchKernelGGL((gen_apply_kernel<DIM, K, T, BLK, Op>), dim3(nb), dim3(64), 0, stream, gg, op);
+      check_launch();
+    }
+    hipLaunchKernelGGL((gen_epilogue_kernel<DIM, T, BLK, Op>), dim3(grid_for(n_all)), dim3(VB), 0, stream, gg, op);
+    check_launch();
+  }
+
+  // Diagonals of general cells by probing with the operator kernels:
+  // velocity nodes whose lattice coordinates agree modulo k+1 share no cell,
+  // so A e (e = indicator of one residue class) equals diag(A) on that class;
+  // pressure nodes whose coordinates agree modulo 3 (k = 2) / 5 (k = 3)
+  // share no velocity node of their cells, so B D_A^-1 B^T e equals
+  // diag(B D_A^-1 B^T) there (and M_p e equals diag(M_p)).
+  void probe_diagonals(int l) {
+    LevelInfo &I = lv[l];
+    auto g = geom<double>(l);
+    auto gu = geom<double>(l, true);
+    double *e = lz[0], *q = lz[1], *s = lz[2], *mpe = lz[3];
+    const int mv = K + 1;
+    const int ncv = DIM == 3 ? mv * mv * mv : mv * mv;
+    for (int col = 0; col < ncv; ++col) {
+      const int c0 = col % mv, c1 = (col / mv) % mv, c2 = DIM == 3 ? col / (mv * mv) : 0;
+      hipLaunchKernelGGL((k_probe_fill<DIM>), dim3(grid_for(I.N)), dim3(VB), 0, stream, e, I.Nv, I.Np, 0, mv, c0, c1,
+                         c2, I.vd[0], I.vd[1], I.pd[0], I.pd[1]);
+      check_launch();
+      tile<double, BLK_A>(g, OpApply<double>{e, nullptr, q, nullptr});
+      hipLaunchKernelGGL((k_probe_take<DIM>), dim3(grid_for(I.Nu)), dim3(VB), 0, stream, I.DA, (const double *)q,
+                         (const double *)nullptr, 0.0, I.Nv, DIM, mv, c0, c1, c2, I.vd[0], I.vd[1]);
+      check_launch();
+    }
+    const int mp = K == 2 ? 3 : 5;
+    const int ncp = DIM == 3 ? mp * mp * mp : mp * mp;
+    const bool schur_p = desc.schur_diag == SMG_SCHUR_P;
+    for (int col = 0; col < ncp; ++col) {
+      const int c0 = col % mp, c1 = (col / mp) % mp, c2 = DIM == 3 ? col / (mp * mp) : 0;
+      hipLaunchKernelGGL((k_probe_fill<DIM>), dim3(grid_for(I.N)), dim3(VB), 0, stream, e, I.Nv, I.Np, 1, mp, c0, c1,
+                         c2, I.vd[0], I.vd[1], I.pd[0], I.pd[1]);
+      check_launch();
+      const double *ep = e + I.Nu;
+      // M_p e (unit c_p)
+      tile<double, BLK_C | BLK_CPLUS>(gu, OpApply<double>{nullptr, ep, nullptr, mpe});
+      if (schur_p) {
+        // D~_S_p = diag(M_p) (+ c_p diag(M_p))
+        hipLaunchKernelGGL((k_probe_take<DIM>), dim3(grid_for(I.Np)), dim3(VB), 0, stream, I.DS, (const double *)mpe,
+                           (const double *)mpe, desc.c_pressure, I.Np, 1, mp, c0, c1, c2, I.pd[0], I.pd[1]);
+      } else {
+        // D~_S_d = diag(B D_A^-1 B^T) (+ c_p diag(M_p))
+        tile<double, BLK_BT>(g, OpApply<double>{nullptr, ep, q, nullptr});
+        hipLaunchKernelGGL((k_div_by<double>), dim3(grid_for(I.Nu)), dim3(VB), 0, stream, q, (const double *)I.DA, I.Nu);
+        check_launch();
+        tile<double, BLK_B>(g, OpApply<double>{q, nullptr, nullptr, s});
+        hipLaunchKernelGGL((k_probe_take<DIM>), dim3(grid_for(I.Np)), dim3(VB), 0, stream, I.DS, (const double *)s,
+                           (const double *)mpe, desc.c_pressure, I.Np, 1, mp, c0, c1, c2, I.pd[0], I.pd[1]);
+      }
+      check_launch();
     }
   }
 
@@ -729,7 +828,7 @@ class EngineT : public EngineBase {
     W.sx = dalloc<T>(I.Np);
     W.sd[0] = dalloc<T>(I.Np);
     W.sd[1] = dalloc<T>(I.Np);
-    W.t1 = dalloc<T>(I.N);
+    if (!W.t1) W.t1 = dalloc<T>(I.N);
     W.t2 = dalloc<T>(I.N);
     W.dinvA = dalloc<T>(I.Nu);
     W.dinvS = dalloc<T>(I.Np);
@@ -834,18 +933,52 @@ class EngineT : public EngineBase {
     for (int i = 0; i < 4; ++i) lz[i] = dalloc<double>(nmax);
     partial = dalloc<double>((int64_t)RB * 256);
     dvec = dalloc<double>(1024);
+    // general cells: vertex coordinates of every level (level l takes the
+    // finest-level vertex at the same lattice point)
+    if (desc.fine_vertices) {
+      general = true;
+      hverts.resize(L + 1);
+      const LevelInfo &F = lv[L];
+      const int64_t fx = F.n[0] + 1, fy = F.n[1] + 1;
+      for (int l = 0; l <= L; ++l) {
+        const LevelInfo &I = lv[l];
+        const int s = 1 << (L - l);
+        const int nz = DIM == 3 ? I.n[2] + 1 : 1;
+        std::vector<double> &hv = hverts[l];
+        hv.resize((size_t)(I.n[0] + 1) * (I.n[1] + 1) * nz * DIM);
+        size_t o = 0;
+        for (int k = 0; k < nz; ++k)
+          for (int j = 0; j <= I.n[1]; ++j)
+            for (int i = 0; i <= I.n[0]; ++i) {
+              const int64_t fv = (int64_t)i * s + fx * ((int64_t)j * s + fy * (int64_t)k * s);
+              for (int a = 0; a < DIM; ++a) hv[o++] = desc.fine_vertices[fv * DIM + a];
+            }
+        lv[l].w64.verts = dalloc<double>((int64_t)hv.size());
+        lv[l].w32.verts = dalloc<float>((int64_t)hv.size());
+        SMG_HIP(hipMemcpyAsync(lv[l].w64.verts, hv.data(), hv.size() * sizeof(double), hipMemcpyHostToDevice, stream));
+        hipLaunchKernelGGL((k_copy<float, double>), dim3(grid_for((int64_t)hv.size())), dim3(VB), 0, stream,
+                           lv[l].w32.verts, (const double *)lv[l].w64.verts, (i64)hv.size());
+        check_launch();
+      }
+    }
     // diagonals and M_p 1 on every level
     for (int l = 0; l <= L; ++l) {
       LevelInfo &I = lv[l];
       I.DA = dalloc<double>(I.Nu);
       I.DS = dalloc<double>(I.Np);
       I.mp1 = dalloc<double>(I.Np);
+      lv[l].w64.t1 = dalloc<double>(I.N);
+      lv[l].w32.t1 = dalloc<float>(I.N);
       auto g = geom<double>(l);
-      hipLaunchKernelGGL((k_diag_A<DIM, K>), dim3(grid_for(I.Nv)), dim3(VB), 0, stream, g, I.DA);
-      check_launch();
-      const int kind = desc.schur_diag == SMG_SCHUR_D ? 0 : (desc.schur_diag == SMG_SCHUR_LOC ? 1 : 2);
-      hipLaunchKernelGGL((k_diag_S<DIM, K>), dim3(grid_for(I.Np)), dim3(VB), 0, stream, g, kind, (const double *)I.DA, I.DS);
-      check_launch();
+      if (general) {
+        probe_diagonals(l);
+      } else {
+        hipLaunchKernelGGL((k_diag_A<DIM, K>), dim3(grid_for(I.Nv)), dim3(VB), 0, stream, g, I.DA);
+        check_launch();
+        const int kind = desc.schur_diag == SMG_SCHUR_D ? 0 : (desc.schur_diag == SMG_SCHUR_LOC ? 1 : 2);
+        hipLaunchKernelGGL((k_diag_S<DIM, K>), dim3(grid_for(I.Np)), dim3(VB), 0, stream, g, kind, (const double *)I.DA, I.DS);
+        check_launch();
+      }
       auto gu = geom<double>(l, true);
       tile<double, BLK_C | BLK_CPLUS>(gu, OpApply<double>{nullptr, ones, nullptr, I.mp1});
       alloc_work<double>(l);
@@ -1072,6 +1205,31 @@ class EngineT : public EngineBase {
 
   void node_coordinates(int l, double *xyz) override {
     const LevelInfo &I = lv[l];
+    if (general) {
+      // image of the GLL lattice under each cell's multilinear map
+      const std::vector<double> &hv = hverts[l];
+      for (int64_t node = 0; node < I.Nv; ++node) {
+        int64_t r = node;
+        int c[3] = {0, 0, 0};
+        double t[3] = {0, 0, 0};
+        for (int a = 0; a < DIM; ++a) {
+          const int i = (int)(r % I.vd[a]);
+          r /= I.vd[a];
+          c[a] = i / K;
+          if (c[a] > I.n[a] - 1) c[a] = I.n[a] - 1;
+          t[a] = ref.zv[i - c[a] * K];
+        }
+        for (int a = 0; a < DIM; ++a) xyz[node * DIM + a] = 0.0;
+        for (int v = 0; v < (1 << DIM); ++v) {
+          double w = 1.0;
+          int o[3] = {v & 1, (v >> 1) & 1, (v >> 2) & 1};
+          for (int b = 0; b < DIM; ++b) w *= o[b] ? t[b] : 1.0 - t[b];
+          const int64_t vid = (c[0] + o[0]) + (int64_t)(I.n[0] + 1) * ((c[1] + o[1]) + (int64_t)(I.n[1] + 1) * (DIM == 3 ? c[2] + o[2] : 0));
+          for (int a = 0; a < DIM; ++a) xyz[node * DIM + a] += w * hv[vid * DIM + a];
+        }
+      }
+      return;
+    }
     for (int64_t node = 0; node < I.Nv; ++node) {
       int64_t r = node;
       for (int a = 0; a < DIM; ++a) {

@@ -193,5 +193,37 @@ struct Ref {
   static constexpr TabT<K, T> t = make_tab_t<K, T>();
 };
 
+// Quadrature-point tables for general (multilinear) cells: the k+1 Gauss
+// points x_q and weights w_q on (0, 1); V[q][i] = l_i(x_q) (velocity GLL
+// basis), Vp[q][i] = psi_i(x_q) (pressure basis), and the collocation
+// derivative D[q][j] = lg_j'(x_q) of the Lagrange basis lg on the Gauss points
+// (exact for the degree-k restrictions of Q_k fields to coordinate lines).
+template <int K, typename T>
+struct QTab {
+  T x[K + 1], w[K + 1];
+  T V[K + 1][K + 1];
+  T D[K + 1][K + 1];
+  T Vp[K + 1][K];
+};
+
+template <int K, typename T>
+constexpr QTab<K, T> make_qtab() {
+  constexpr int NQ = K + 1;
+  QTab<K, T> t{};
+  const Rule<NQ> q = gauss<NQ>();
+  const Pts<K + 1> zv = gll<K + 1>();
+  const Pts<K> zp = gll<K>();
+  Pts<NQ> zq{};
+  for (int i = 0; i < NQ; ++i) zq.z[i] = q.x[i];
+  for (int a = 0; a < NQ; ++a) {
+    t.x[a] = (T)q.x[a];
+    t.w[a] = (T)q.w[a];
+    for (int i = 0; i <= K; ++i) t.V[a][i] = (T)lagrange(zv, i, q.x[a]);
+    for (int j = 0; j < NQ; ++j) t.D[a][j] = (T)lagrange_deriv(zq, j, q.x[a]);
+    for (int i = 0; i < K; ++i) t.Vp[a][i] = (T)lagrange(zp, i, q.x[a]);
+  }
+  return t;
+}
+
 }  // namespace cfe
 }  // namespace smg

@@ -1,0 +1,424 @@
+// Operator application on general (multilinear) cells: meshes given by their
+// vertices (Sec. 2: each cell is the image of the unit cell under the
+// bi-/trilinear map of its 2^d vertices; Sec. 3.1: K x = sum_tau P_tau K_tau
+// P_tau^T x with the cell integrals evaluated by Gauss quadrature, k+1 points
+// per direction, and sum factorisation).
+//
+// At each quadrature point: J = sum_v x_v (x) grad N_v, JxW = det J w_q, the
+// physical gradients grad u_c = J^-T grad^ u_c, and the integrands of
+//   a(u, v) = int mu grad u_c . grad v_c + gamma rho u_c v_c,
+//   b(v, q) = -int q div v,   (C p, q) = c_p int p q.
+//
+// Work decomposition: one wave64 per 64 / (k+1)^d cells, one lane per node /
+// quadrature point (for these tensor-product spaces both are (k+1)^d).  The
+// 1D passes run through LDS (one pass = each lane contracts k+1 neighbours of
+// its line).  Cells are processed in 2^d colours (cells of equal index parity
+// share no node), one launch per colour adding into an accumulation vector;
+// a separate epilogue pass over all nodes then applies the Dirichlet rows and
+// the caller's fused vector algebra (the same functors as the box kernels).
+#pragma once
+#include "cell_kernel.hpp"
+#include "fe1d_const.hpp"
+
+namespace smg {
+
+template <typename T>
+struct GenGeo {
+  int n[3], vd[3], pd[3];
+  i64 Nv, Np;
+  int ncol[3];      // cells of the launch colour per direction
+  int off[3];       // colour: parity of the cell index per direction
+  T mu, gr, cp;
+  const T *mu_cell;
+  const T *verts;   // (n+1)^d vertices x d coordinates, x fastest
+  T *tu, *tp;       // accumulated cell sums (velocity [u_1|..|u_d], pressure)
+};
+
+// a[i] for a lane-dependent i without dynamic indexing into private memory
+template <int N, typename T>
+__device__ __forceinline__ T pick(const T (&a)[N], int i) {
+  T r = a[0];
+#pragma unroll
+  for (int j = 1; j < N; ++j) r = (i == j) ? a[j] : r;
+  return r;
+}
+
+template <int DIM, int K, typename T, int BLK, class Op>
+__global__ void __launch_bounds__(64) gen_apply_kernel(const GenGeo<T> g, const Op op) {
+  constexpr int NV = K + 1, NP = K;
+  constexpr int NN = DIM == 3 ? NV * NV * NV : NV * NV;   // nodes = quadrature points
+  constexpr int NPN = DIM == 3 ? NP * NP * NP : NP * NP;  // pressure nodes
+  constexpr int CPB = 64 / NN;                             // cells per wave
+  constexpr int NVERT = 1 << DIM;
+  constexpr cfe::QTab<K, T> Q = cfe::make_qtab<K, T>();
+  constexpr bool NEED_U = (BLK & (BLK_A | BLK_MASS | BLK_B)) != 0;
+  constexpr bool NEED_P = (BLK & (BLK_BT | BLK_C)) != 0;
+  constexpr bool OUT_U = (BLK & (BLK_A | BLK_MASS | BLK_BT)) != 0;
+  constexpr bool OUT_P = (BLK & (BLK_B | BLK_C)) != 0;
+  __shared__ T lds[CPB][3][NN];
+
+  const int tid = threadIdx.x;
+  const int slot = tid / NN;
+  const int q = tid - slot * NN;
+  const bool in_slot = slot < CPB;
+  const int sl = in_slot ? slot : 0;
+  const i64 ci = (i64)blockIdx.x * CPB + slot;
+  const i64 ncells = (i64)g.ncol[0] * g.ncol[1] * (DIM == 3 ? g.ncol[2] : 1);
+  const bool live = in_slot && ci < ncells;
+  int cx = 0, cy = 0, cz = 0;
+  if (live) {
+    const i64 r = ci / g.ncol[0];
+    cx = 2 * (int)(ci - r * g.ncol[0]) + g.off[0];
+    cy = 2 * (int)(r % g.ncol[1]) + g.off[1];
+    cz = DIM == 3 ? 2 * (int)(r / g.ncol[1]) + g.off[2] : 0;
+  }
+  const int qx = q % NV, qy = (q / NV) % NV, qz = DIM == 3 ? q / (NV * NV) : 0;
+  const int qd[3] = {qx, qy, qz};
+  T *A = lds[sl][0], *Bf = lds[sl][1], *Cf = lds[sl][2];
+
+  // per-lane rows / columns of the 1D quadrature tables
+  T rV[3][NV], rD[3][NV], cV[3][NV], cD[3][NV];
+#pragma unroll
+  for (int d = 0; d < 3; ++d)
+#pragma unroll
+    for (int i = 0; i < NV; ++i) {
+      T vr = Q.V[0][i], dr = Q.D[0][i], vc = Q.V[i][0], dc = Q.D[i][0];
+#pragma unroll
+      for (int j = 1; j < NV; ++j) {
+        vr = qd[d] == j ? Q.V[j][i] : vr;
+        dr = qd[d] == j ? Q.D[j][i] : dr;
+        vc = qd[d] == j ? Q.V[i][j] : vc;
+        dc = qd[d] == j ? Q.D[i][j] : dc;
+      }
+      rV[d][i] = vr;
+      rD[d][i] = dr;
+      cV[d][i] = vc;
+      cD[d][i] = dc;
+    }
+  auto lidx = [](int x, int y, int z) { return x + NV * (y + NV * z); };
+  // one pass along direction d with per-lane coefficients m[i]: out(q) = sum_i m[i] in(q with coordinate d = i)
+  auto pass = [&](const T *in, const T (&m)[NV], int d) {
+    T s = 0;
+#pragma unroll
+    for (int i = 0; i < NV; ++i) {
+      const int k = d == 0 ? lidx(i, qy, qz) : (d == 1 ? lidx(qx, i, qz) : lidx(qx, qy, i));
+      s += m[i] * in[k];
+    }
+    return s;
+  };
+
+  // ---- geometry at this lane's quadrature point
+  T Jinv[3][3] = {{1, 0, 0}, {0, 1, 0}, {0, 0, 1}};
+  T JxW = 0;
+  T mu = g.mu;
+  if (live) {
+    const T xi[3] = {pick(Q.x, qx), pick(Q.x, qy), DIM == 3 ? pick(Q.x, qz) : T(0)};
+    T J[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+#pragma unroll
+    for (int v = 0; v < NVERT; ++v) {
+      const int o[3] = {v & 1, (v >> 1) & 1, (v >> 2) & 1};
+      const i64 vid = (cx + o[0]) + (i64)(g.n[0] + 1) * ((cy + o[1]) + (i64)(g.n[1] + 1) * (DIM == 3 ? cz + o[2] : 0));
+#pragma unroll
+      for (int b = 0; b < DIM; ++b) {
+        T dn = o[b] ? T(1) : T(-1);
+#pragma unroll
+        for (int c = 0; c < DIM; ++c)
+          if (c != b) dn *= o[c] ? xi[c] : T(1) - xi[c];
+#pragma unroll
+        for (int a = 0; a < DIM; ++a) J[a][b] += g.verts[vid * DIM + a] * dn;
+      }
+    }
+    T det;
+    if constexpr (DIM == 2) {
+      det = J[0][0] * J[1][1] - J[0][1] * J[1][0];
+      const T id = T(1) / det;
+      Jinv[0][0] = J[1][1] * id;
+      Jinv[0][1] = -J[0][1] * id;
+      Jinv[1][0] = -J[1][0] * id;
+      Jinv[1][1] = J[0][0] * id;
+      JxW = det * pick(Q.w, qx) * pick(Q.w, qy);
+    } else {
+      const T c00 = J[1][1] * J[2][2] - J[1][2] * J[2][1];
+      const T c01 = J[1][2] * J[2][0] - J[1][0] * J[2][2];
+      const T c02 = J[1][0] * J[2][1] - J[1][1] * J[2][0];
+      det = J[0][0] * c00 + J[0][1] * c01 + J[0][2] * c02;
+      const T id = T(1) / det;
+      Jinv[0][0] = c00 * id;
+      Jinv[1][0] = c01 * id;
+      Jinv[2][0] = c02 * id;
+      Jinv[0][1] = (J[0][2] * J[2][1] - J[0][1] * J[2][2]) * id;
+      Jinv[1][1] = (J[0][0] * J[2][2] - J[0][2] * J[2][0]) * id;
+      Jinv[2][1] = (J[0][1] * J[2][0] - J[0][0] * J[2][1]) * id;
+      Jinv[0][2] = (J[0][1] * J[1][2] - J[0][2] * J[1][1]) * id;
+      Jinv[1][2] = (J[0][2] * J[1][0] - J[0][0] * J[1][2]) * id;
+      Jinv[2][2] = (J[0][0] * J[1][1] - J[0][1] * J[1][0]) * id;
+      JxW = det * pick(Q.w, qx) * pick(Q.w, qy) * pick(Q.w, qz);
+    }
+    if (g.mu_cell != nullptr) mu = g.mu_cell[cx + (i64)g.n[0] * (cy + (i64)g.n[1] * cz)];
+  }
+
+  // ---- this lane's global velocity node
+  const int gx = K * cx + qx, gy = K * cy + qy, gz = K * cz + qz;
+  const i64 vnode = gx + (i64)g.vd[0] * (gy + (i64)g.vd[1] * gz);
+  const bool vbc = on_box_boundary(gx, g.vd[0]) || on_box_boundary(gy, g.vd[1]) ||
+                   (DIM == 3 && on_box_boundary(gz, g.vd[2]));
+
+  // ---- velocity: values and reference gradients at the quadrature points
+  T uq[DIM], gref[DIM][3];
+#pragma unroll
+  for (int c = 0; c < DIM; ++c) {
+    uq[c] = 0;
+    gref[c][0] = gref[c][1] = gref[c][2] = 0;
+  }
+  if constexpr (NEED_U) {
+#pragma unroll
+    for (int c = 0; c < DIM; ++c) {
+      T v = 0;
+      if (live && !(Op::ZERO_BC && vbc)) v = op.load_u((i64)c * g.Nv + vnode);
+      if (in_slot) A[q] = v;
+      __syncthreads();
+      T t = pass(A, rV[0], 0);
+      if (in_slot) Bf[q] = t;
+      __syncthreads();
+      t = pass(Bf, rV[1], 1);
+      if constexpr (DIM == 3) {
+        if (in_slot) A[q] = t;
+        __syncthreads();
+        t = pass(A, rV[2], 2);
+      }
+      // values at the quadrature points now in a buffer the gradient passes read
+      T *Fq = DIM == 3 ? Bf : A;
+      __syncthreads();
+      if (in_slot) Fq[q] = t;
+      __syncthreads();
+      uq[c] = t;
+#pragma unroll
+      for (int d = 0; d < DIM; ++d) gref[c][d] = pass(Fq, rD[d], d);
+      __syncthreads();
+    }
+  }
+
+  // ---- pressure at the quadrature points (shapes K^d -> (K+1) K^(d-1) -> ...)
+  T pq = 0;
+  if constexpr (NEED_P) {
+    T v = 0;
+    if (live && q < NPN) {
+      const int px = q % NP, py = (q / NP) % NP, pz = DIM == 3 ? q / (NP * NP) : 0;
+      const i64 pn = ((K - 1) * cx + px) + (i64)g.pd[0] * (((K - 1) * cy + py) + (i64)g.pd[1] * ((K - 1) * cz + pz));
+      v = op.load_p(pn);
+    }
+    if (in_slot) A[q] = v;
+    __syncthreads();
+    // x: (NP, NP, NP) -> (NV, NP, NP)
+    {
+      const int o = q, ox = o % NV, oy = (o / NV) % NP, oz = o / (NV * NP);
+      T s = 0;
+      if (o < NV * NP * (DIM == 3 ? NP : 1)) {
+#pragma unroll
+        for (int i = 0; i < NP; ++i) {
+          T m = Q.Vp[0][i];
+#pragma unroll
+          for (int j = 1; j < NV; ++j) m = ox == j ? Q.Vp[j][i] : m;
+          s += m * A[i + NP * (oy + NP * oz)];
+        }
+      }
+      __syncthreads();
+      if (in_slot) Bf[q] = s;
+      __syncthreads();
+    }
+    // y: (NV, NP, NP) -> (NV, NV, NP)
+    T s = 0;
+    {
+      const int o = q, ox = o % NV, oy = (o / NV) % NV, oz = o / (NV * NV);
+      if (o < NV * NV * (DIM == 3 ? NP : 1)) {
+#pragma unroll
+        for (int i = 0; i < NP; ++i) {
+          T m = Q.Vp[0][i];
+#pragma unroll
+          for (int j = 1; j < NV; ++j) m = oy == j ? Q.Vp[j][i] : m;
+          s += m * Bf[ox + NV * (i + NP * oz)];
+        }
+      }
+    }
+    if constexpr (DIM == 3) {
+      __syncthreads();
+      if (in_slot) A[q] = s;
+      __syncthreads();
+      // z: (NV, NV, NP) -> (NV, NV, NV)
+      T s3 = 0;
+#pragma unroll
+      for (int i = 0; i < NP; ++i) {
+        T m = Q.Vp[0][i];
+#pragma unroll
+        for (int j = 1; j < NV; ++j) m = qz == j ? Q.Vp[j][i] : m;
+        s3 += m * A[qx + NV * (qy + NV * i)];
+      }
+      s = s3;
+    }
+    pq = s;
+    __syncthreads();
+  }
+
+  // ---- integrands at the quadrature point
+  T vcoef[DIM], gcoef[DIM][3];
+  T pcoef = 0;
+  {
+    T gphys[DIM][3];
+#pragma unroll
+    for (int c = 0; c < DIM; ++c)
+#pragma unroll
+      for (int a = 0; a < DIM; ++a) {
+        T s = 0;
+#pragma unroll
+        for (int b = 0; b < DIM; ++b) s += Jinv[b][a] * gref[c][b];
+        gphys[c][a] = s;
+      }
+#pragma unroll
+    for (int c = 0; c < DIM; ++c) {
+      T val = 0;
+      if constexpr ((BLK & BLK_A) != 0) val += g.gr * uq[c];
+      if constexpr ((BLK & BLK_MASS) != 0) val += uq[c];
+      vcoef[c] = val * JxW;
+      T G[3] = {0, 0, 0};
+#pragma unroll
+      for (int a = 0; a < DIM; ++a) {
+        if constexpr ((BLK & BLK_A) != 0) G[a] += mu * gphys[c][a];
+        if constexpr ((BLK & BLK_BT) != 0)
+          if (a == c) G[a] -= pq;
+      }
+#pragma unroll
+      for (int b = 0; b < DIM; ++b) {
+        T s = 0;
+#pragma unroll
+        for (int a = 0; a < DIM; ++a) s += Jinv[b][a] * G[a];
+        gcoef[c][b] = s * JxW;
+      }
+    }
+    if constexpr ((BLK & BLK_B) != 0) {
+      T div = 0;
+#pragma unroll
+      for (int c = 0; c < DIM; ++c) div += gphys[c][c];
+      pcoef -= div;
+    }
+    if constexpr ((BLK & BLK_C) != 0) pcoef += ((BLK & BLK_CPLUS) ? g.cp : -g.cp) * pq;
+    pcoef *= JxW;
+  }
+
+  // ---- velocity test functions: integrate back, add into the accumulation vector
+  if constexpr (OUT_U) {
+#pragma unroll
+    for (int c = 0; c < DIM; ++c) {
+      if (in_slot) {
+        A[q] = gcoef[c][0];
+        Bf[q] = gcoef[c][1];
+        if constexpr (DIM == 3) Cf[q] = gcoef[c][2];
+      }
+      __syncthreads();
+      T w = vcoef[c] + pass(A, cD[0], 0) + pass(Bf, cD[1], 1);
+      if constexpr (DIM == 3) w += pass(Cf, cD[2], 2);
+      __syncthreads();
+      if (in_slot) A[q] = w;
+      __syncthreads();
+      T t = pass(A, cV[0], 0);
+      if (in_slot) Bf[q] = t;
+      __syncthreads();
+      t = pass(Bf, cV[1], 1);
+      if constexpr (DIM == 3) {
+        if (in_slot) A[q] = t;
+        __syncthreads();
+        t = pass(A, cV[2], 2);
+      }
+      __syncthreads();
+      if (live) g.tu[(i64)c * g.Nv + vnode] += t;
+    }
+  }
+
+  // ---- pressure test functions
+  if constexpr (OUT_P) {
+    if (in_slot) A[q] = pcoef;
+    __syncthreads();
+    T s = 0;
+    if constexpr (DIM == 3) {
+      // z: (NV, NV, NV) -> (NV, NV, NP)
+      const int o = q, ox = o % NV, oy = (o / NV) % NV, oz = o / (NV * NV);
+      if (o < NV * NV * NP) {
+#pragma unroll
+        for (int i = 0; i < NV; ++i) {
+          T m = Q.Vp[i][0];
+#pragma unroll
+          for (int j = 1; j < NP; ++j) m = oz == j ? Q.Vp[i][j] : m;
+          s += m * A[ox + NV * (oy + NV * i)];
+        }
+      }
+      __syncthreads();
+      if (in_slot) A[q] = s;
+      __syncthreads();
+    }
+    // y: (NV, NV, NP) -> (NV, NP, NP)
+    {
+      const int o = q, ox = o % NV, oy = (o / NV) % NP, oz = o / (NV * NP);
+      s = 0;
+      if (o < NV * NP * (DIM == 3 ? NP : 1)) {
+#pragma unroll
+        for (int i = 0; i < NV; ++i) {
+          T m = Q.Vp[i][0];
+#pragma unroll
+          for (int j = 1; j < NP; ++j) m = oy == j ? Q.Vp[i][j] : m;
+          s += m * A[ox + NV * (i + NV * oz)];
+        }
+      }
+      __syncthreads();
+      if (in_slot) Bf[q] = s;
+      __syncthreads();
+    }
+    // x: (NV, NP, NP) -> (NP, NP, NP)
+    {
+      const int o = q, ox = o % NP, oy = (o / NP) % NP, oz = o / (NP * NP);
+      s = 0;
+      if (o < NPN) {
+#pragma unroll
+        for (int i = 0; i < NV; ++i) {
+          T m = Q.Vp[i][0];
+#pragma unroll
+          for (int j = 1; j < NP; ++j) m = ox == j ? Q.Vp[i][j] : m;
+          s += m * Bf[i + NV * (oy + NP * oz)];
+        }
+      }
+      if (live && q < NPN) {
+        const i64 pn = ((K - 1) * cx + ox) + (i64)g.pd[0] * (((K - 1) * cy + oy) + (i64)g.pd[1] * ((K - 1) * cz + oz));
+        g.tp[pn] += s;
+      }
+    }
+  }
+}
+
+// Dirichlet rows and the caller's epilogue on every node, from the
+// accumulated cell sums.
+template <int DIM, typename T, int BLK, class Op>
+__global__ void gen_epilogue_kernel(const GenGeo<T> g, const Op op) {
+  constexpr bool NEED_U = (BLK & (BLK_A | BLK_MASS | BLK_B)) != 0;
+  constexpr bool NEED_P = (BLK & (BLK_BT | BLK_C)) != 0;
+  constexpr bool OUT_U = (BLK & (BLK_A | BLK_MASS | BLK_BT)) != 0;
+  constexpr bool OUT_P = (BLK & (BLK_B | BLK_C)) != 0;
+  const i64 nu = OUT_U ? (i64)DIM * g.Nv : 0;
+  const i64 total = nu + (OUT_P ? g.Np : 0);
+  SMG_GRID_LOOP(i, total) {
+    if (i < nu) {
+      const i64 node = i % g.Nv;
+      const int x = (int)(node % g.vd[0]);
+      const i64 r = node / g.vd[0];
+      const int y = (int)(r % g.vd[1]);
+      const int z = (int)(r / g.vd[1]);
+      const bool bc = on_box_boundary(x, g.vd[0]) || on_box_boundary(y, g.vd[1]) ||
+                      (DIM == 3 && on_box_boundary(z, g.vd[2]));
+      const T v = NEED_U ? op.load_u(i) : T(0);
+      const T t = bc ? ((BLK & BLK_A) != 0 ? v : T(0)) : g.tu[i];
+      op.store_u(i, t, bc ? t : v, bc, op.fetch_u(i));
+    } else {
+      const i64 j = i - nu;
+      op.store_p(j, g.tp[j], NEED_P ? op.load_p(j) : T(0), op.fetch_p(j));
+    }
+  }
+}
+
+}  // namespace smg

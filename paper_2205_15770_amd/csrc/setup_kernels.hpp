@@ -149,4 +149,50 @@ __global__ void k_diag_S(const LevelGeom<double, DIM, K> g, int kind, const doub
   }
 }
 
+// ---------------------------------------------------------------------------
+// Probing (general cells): indicator of one residue class of lattice nodes
+// and extraction of the probed diagonal entries.
+// ---------------------------------------------------------------------------
+template <int DIM>
+__device__ __forceinline__ bool in_class(i64 node, int d0, int d1, int m, int c0, int c1, int c2) {
+  const int x = (int)(node % d0);
+  const i64 r = node / d0;
+  const int y = (int)(r % d1);
+  const int z = (int)(r / d1);
+  return x % m == c0 && y % m == c1 && (DIM == 2 || z % m == c2);
+}
+
+// e = 1 on the nodes of `field` (0: every velocity component, 1: pressure)
+// whose lattice coordinates are congruent to (c0, c1, c2) modulo m, else 0.
+template <int DIM>
+__global__ void k_probe_fill(double *e, i64 Nv, i64 Np, int field, int m, int c0, int c1, int c2, int v0, int v1,
+                             int p0, int p1) {
+  const i64 nu = (i64)DIM * Nv;
+  SMG_GRID_LOOP(i, nu + Np) {
+    bool on = false;
+    if (i < nu) {
+      if (field == 0) on = in_class<DIM>(i % Nv, v0, v1, m, c0, c1, c2);
+    } else if (field == 1) {
+      on = in_class<DIM>(i - nu, p0, p1, m, c0, c1, c2);
+    }
+    e[i] = on ? 1.0 : 0.0;
+  }
+}
+
+// D[i] = y[i] (+ zs z[i]) for the nodes i of the residue class; n nodes per
+// component, ncomp components.
+template <int DIM>
+__global__ void k_probe_take(double *D, const double *y, const double *z, double zs, i64 n, int ncomp, int m, int c0,
+                             int c1, int c2, int d0, int d1) {
+  SMG_GRID_LOOP(i, n * ncomp) {
+    if (!in_class<DIM>(i % n, d0, d1, m, c0, c1, c2)) continue;
+    D[i] = y[i] + (z ? zs * z[i] : 0.0);
+  }
+}
+
+template <typename T>
+__global__ void k_div_by(T *q, const double *d, i64 n) {
+  SMG_GRID_LOOP(i, n) q[i] = (T)((double)q[i] / d[i]);
+}
+
 }  // namespace smg

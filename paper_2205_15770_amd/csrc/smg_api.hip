@@ -114,7 +114,8 @@ smg_status validate(const smg_desc *d) {
   if (d->schur_diag < 0 || d->schur_diag > 2) return fail(SMG_EINVAL, "schur_diag must be 0, 1 or 2");
   if (d->precision != SMG_PRECOND_F64 && d->precision != SMG_PRECOND_F32) return fail(SMG_EINVAL, "precision must be 0 or 1");
   if (d->fgmres_restart < 1 || d->fgmres_restart > 200) return fail(SMG_EINVAL, "fgmres_restart must be in [1, 200]");
-  if (d->fine_vertices) return fail(SMG_EUNSUPPORTED, "non-Cartesian (vertex-given) meshes are not built");
+  if (d->fine_vertices && d->schur_diag == SMG_SCHUR_LOC)
+    return fail(SMG_EUNSUPPORTED, "the local Schur diagonal is built for box cells only");
   if (d->mu_cell) {
     double nf = 1.0;
     for (int a = 0; a < d->dim; ++a) nf *= (double)d->n_coarse[a] * std::ldexp(1.0, d->n_levels - 1);
@@ -166,8 +167,8 @@ smg_status smg_create(const smg_desc *desc, smg_ctx **out) {
   else if (desc->dim == 3 && desc->fe_degree == 2) eng = smg::make_engine_3_2();
   else eng = smg::make_engine_3_3();
   eng->desc = *desc;
-  eng->desc.fine_vertices = nullptr;
-  eng->desc.mu_cell = desc->mu_cell;  // read during setup only
+  eng->desc.fine_vertices = desc->fine_vertices;  // read during setup only
+  eng->desc.mu_cell = desc->mu_cell;              // read during setup only
   smg_ctx *ctx = new smg_ctx();
   ctx->eng = eng;
   try {
@@ -176,6 +177,7 @@ smg_status smg_create(const smg_desc *desc, smg_ctx **out) {
     ctx->device = dev;
     eng->setup();
     eng->desc.mu_cell = nullptr;
+    eng->desc.fine_vertices = nullptr;
   } catch (const smg::Error &e) {
     eng->free_all();
     delete eng;

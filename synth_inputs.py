@@ -132,15 +132,17 @@ def manufactured_f(X, mu=1.0, gamma=0.0, rho=1.0):
 # perturbed vertices and per-cell viscosity (3D Q3-Q2 workload)
 # ---------------------------------------------------------------------------
 def perturbed_box_vertices(n, dim=3, amplitude=0.2, seed=4):
-    """Vertices of the unit-box lattice with n cells per direction, interior
-    vertices moved by U[-amplitude h, amplitude h] per coordinate; x fastest."""
-    h = 1.0 / n
-    ax = np.linspace(0.0, 1.0, n + 1)
-    grids = np.meshgrid(*([ax] * dim), indexing="ij")
+    """Vertices of the unit-box lattice with n cells per direction (an int, or
+    one count per direction), interior vertices moved by U[-amplitude h_a,
+    amplitude h_a] in coordinate a; x fastest."""
+    ns = [int(n)] * dim if np.isscalar(n) else [int(v) for v in n][:dim]
+    axes = [np.linspace(0.0, 1.0, v + 1) for v in ns]
+    grids = np.meshgrid(*axes, indexing="ij")
     V = np.stack([g.transpose(tuple(range(dim))[::-1]).reshape(-1) for g in grids], axis=1)
-    idx = np.indices((n + 1,) * dim).reshape(dim, -1)[::-1].T
-    interior = np.all((idx > 0) & (idx < n), axis=1)
+    idx = np.indices(tuple(v + 1 for v in ns)).reshape(dim, -1)[::-1].T
+    interior = np.all((idx > 0) & (idx < np.array(ns)), axis=1)
     rng = np.random.default_rng(seed)
+    h = 1.0 / np.array(ns, dtype=np.float64)
     shift = rng.uniform(-amplitude * h, amplitude * h, size=V.shape)
     V[interior] += shift[interior]
     return V
