@@ -34,7 +34,12 @@ WORKLOADS = {
     "stokes2d_q2q1_512": dict(dim=2, fe_degree=2, n_coarse=(8, 8), n_levels=7, mu=1.0, rho=1.0, gamma=1e3,
                               desc="2D generalized Stokes Q2-Q1, 512x512 cells, 7 levels, gamma=1e3"),
     "stokes3d_q2q1_64": dict(dim=3, fe_degree=2, n_coarse=(2, 2, 2), n_levels=6, mu=1.0, rho=1.0, gamma=0.0,
-                             desc="3D Stokes Q2-Q1, 64^3 cells, 6 levels"),
+                             force="manufactured", desc="3D Stokes Q2-Q1, 64^3 cells, 6 levels, manufactured f"),
+    "stokes3d_q3q2_32_pert": dict(dim=3, fe_degree=3, n_coarse=(2, 2, 2), n_levels=5, mu=1.0, rho=1.0, gamma=0.0,
+                                  force="manufactured", perturb=(0.2, 4), log_mu=(1.0, 100.0, 5),
+                                  desc="3D Stokes Q3-Q2, 32^3 trilinear cells (interior vertices moved by "
+                                       "<= 0.2 h, seed 4), mu = exp(8 Fourier modes) in [1, 100] (seed 5), "
+                                       "5 levels, manufactured f"),
 }
 
 
@@ -61,12 +66,17 @@ def parse():
     return ap.parse_args()
 
 
-def rhs(mg, level, dim, seed=2):
-    """b = [M_v f, 0] for a nodal random force f (the library's mass kernel)."""
+def rhs(mg, level, dim, seed=2, force="random"):
+    """b = [M_v f, 0] for a nodal force f (the library's mass kernel): random
+    U[-1,1] per velocity DoF, or the nodal interpolant of the manufactured f."""
     import torch
     import synth_inputs as si
     nu, np_ = mg.sizes(level)
-    f = torch.tensor(si.nodal_random_f(dim, nu // dim, seed=seed).ravel(), dtype=torch.float64, device="cuda")
+    if force == "manufactured":
+        fn = si.manufactured_f(mg.node_coordinates(level), 1.0, 0.0, 1.0).T
+    else:
+        fn = si.nodal_random_f(dim, nu // dim, seed=seed)
+    f = torch.tensor(fn.ravel(), dtype=torch.float64, device="cuda")
     b = torch.zeros(nu + np_, dtype=torch.float64, device="cuda")
     from paper_2205_15770_amd import SMG_BLOCK_MASS
     mg.apply_block(level, SMG_BLOCK_MASS, f, b[:nu])
@@ -166,13 +176,22 @@ def main():
     common = dict(dim=wl["dim"], fe_degree=wl["fe_degree"], n_coarse=wl["n_coarse"], n_levels=wl["n_levels"],
                   mu=wl["mu"], rho=wl["rho"], gamma=wl["gamma"], cheb_deg_A=1, cheb_deg_S=1, smooth_steps=2,
                   cycle_index=1, schur_diag="d")
+    n_fine = cells(wl)[:wl["dim"]]
+    if "perturb" in wl:
+        import synth_inputs as si
+        amp, seed = wl["perturb"]
+        common["fine_vertices"] = si.perturbed_box_vertices(n_fine, dim=wl["dim"], amplitude=amp, seed=seed)
+    if "log_mu" in wl:
+        import synth_inputs as si
+        lo, hi, seed = wl["log_mu"]
+        common["mu_cell"] = si.fourier_log_viscosity(n_fine[0], dim=wl["dim"], mu_min=lo, mu_max=hi, seed=seed)
     L = wl["n_levels"] - 1
     t_setup0 = time.perf_counter()
     mg = StokesMG(precision="f32", **common)
     torch.cuda.synchronize()
     t_setup = time.perf_counter() - t_setup0
     N = mg.n_total(L)
-    b = rhs(mg, L, wl["dim"])
+    b = rhs(mg, L, wl["dim"], force=wl.get("force", "random"))
     x = torch.zeros(N, dtype=torch.float64, device="cuda")
     print(f"# setup {t_setup:.2f} s, N = {N}", file=sys.stderr, flush=True)
     # the dominant operator kernel of the cycle: the finest-level Chebyshev

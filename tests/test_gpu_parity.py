@@ -274,6 +274,34 @@ def test_node_coordinates_general_cells(name):
         assert np.abs(X - ora.meshes[l].velocity_node_coordinates()).max() < 1e-14
 
 
+def test_c1_protocol_16x16_stationary():
+    """The 16^2 Q2-Q1 configuration with the paper's stationary protocol:
+    3 levels, mu = 1, gamma = 0, manufactured f, (k_A, k_S, m) = (3, 3, 2),
+    D~_S_d, V-cycle, to 1e-10 relative residual.  Residual history, rate q
+    and solution against the oracle running the same iteration."""
+    from paper_2205_15770_amd import StokesMG
+    from oracle.krylov import stationary, rate_q
+    meshes = make_hierarchy(2, (4, 4), 3, 2)
+    ora = Multigrid(meshes, mu=1.0, gamma=0.0, rho=1.0, k_A=3, k_S=3, schur="d", smooth_steps=2, cycle_index=1)
+    gpu = StokesMG(dim=2, fe_degree=2, n_coarse=(4, 4), n_levels=3, mu=1.0, gamma=0.0, rho=1.0,
+                   cheb_deg_A=3, cheb_deg_S=3, smooth_steps=2, cycle_index=1, schur_diag="d")
+    assert gpu.n_total(2) == 2467
+    _inject_betas(ora, gpu)
+    L = 2
+    asm = ora.levels[L]
+    X = meshes[L].velocity_node_coordinates()
+    b = asm.rhs_from_nodal_f(si.manufactured_f(X, 1.0, 0.0, 1.0).T)
+    x = torch.zeros(len(b), dtype=torch.float64, device="cuda")
+    info = gpu.solve_stationary(x, _dev(b), rtol=1e-10, maxit=30)
+    xo, hist = stationary(asm.K, lambda x, b: ora.cycle(L, x, b), b, rtol=1e-10, maxit=30)
+    h = np.array(hist) / hist[0]
+    assert info["iterations"] == len(hist) - 1
+    assert np.allclose(info["history"], h, rtol=1e-6, atol=1e-14)
+    assert abs(info["rate_q"] - rate_q(hist)) < 1e-6
+    assert _rel(x, pressure_mean_free(asm, xo)) < 1e-8
+    gpu.close()
+
+
 def test_vmult_is_deterministic():
     ora, gpu = _setup("2d_k2")
     l = ora.L
