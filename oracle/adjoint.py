@@ -1,0 +1,70 @@
+"""Adjoint-state gradients of a solve (oracle; test infrastructure only).
+
+The discrete saddle-point system of Section 1, K(mu) x = b(f), with
+b = [Z M_v f; 0] (nodal force field f, Z zeroing the constrained velocity
+rows), is symmetric (K = K^T; the Dirichlet rows and columns are the
+identity).  For an objective J(x) the adjoint state lam solves K lam = dJ/dx
+and, since K depends on the per-cell viscosity only through the first term of
+the form a of Section 2 (mu_tau int_tau grad u : grad v),
+
+  dJ/d log mu_tau = - mu_tau  lam_u^T A_tau^grad u     (constrained entries zeroed),
+  dJ/df           = M_v^T Z lam_u = M_v (Z lam_u)      (per component, every node),
+
+with A_tau^grad the cell stiffness matrix int_tau grad phi_i . grad phi_j.
+Everything here is assembled from the same per-cell quadrature as
+`assemble.element_matrices`, and the solves are direct (sparse LU of the
+bordered system that fixes the pressure mean).
+"""
+import numpy as np
+import scipy.sparse as sp
+import scipy.sparse.linalg as spla
+
+from .assemble import element_matrices
+
+
+def bordered_solve(asm, rhs):
+    """x with K x = rhs and M_p-weighted pressure mean zero (the bordered
+    system [K m; m^T 0] of the coarse solve, here on any level)."""
+    nu = asm.A.shape[0]
+    n = asm.K.shape[0]
+    m = np.zeros(n)
+    m[nu:] = asm.Mp @ np.ones(n - nu)
+    Kb = sp.bmat([[asm.K, sp.csr_matrix(m[:, None])], [sp.csr_matrix(m[None, :]), None]]).tocsc()
+    return spla.spsolve(Kb, np.concatenate([rhs, [0.0]]))[:-1]
+
+
+def rhs_from_force(asm, f_nodal):
+    """b = [Z M_v f; 0] for a nodal velocity field f of shape (d, Nv)."""
+    return asm.rhs_from_nodal_f(np.asarray(f_nodal).reshape(asm.mesh.dim, -1))
+
+
+def velocity_objective(asm, x, u_target):
+    """J = sum over velocity DoFs of (u - u_target)^2, and dJ/dx."""
+    nu = asm.A.shape[0]
+    du = x[:nu] - u_target
+    g = np.zeros_like(x)
+    g[:nu] = 2.0 * du
+    return float(du @ du), g
+
+
+def gradients(asm, x, lam):
+    """(dJ/d log mu per cell, dJ/df per velocity DoF) from the state x and the
+    adjoint state lam of the constrained system."""
+    mesh = asm.mesh
+    d = mesh.dim
+    Nv = mesh.n_vnode
+    free = asm.free_u
+    u = x[:d * Nv] * free
+    lu = lam[:d * Nv] * free
+    mu = mesh.mu(1.0)
+    cells = np.arange(mesh.ncell)
+    stiff, _, _, _ = element_matrices(mesh, cells, np.ones(mesh.ncell), 0.0, 1.0)
+    vn = mesh.cell_velocity_nodes(cells)
+    g_mu = np.zeros(mesh.ncell)
+    for c in range(d):
+        uc = u[c * Nv:(c + 1) * Nv][vn]           # (nc, nv)
+        lc = lu[c * Nv:(c + 1) * Nv][vn]
+        g_mu -= np.einsum("ci,cij,cj->c", lc, stiff, uc)
+    g_mu *= mu
+    g_f = np.concatenate([asm.Mv @ lu[c * Nv:(c + 1) * Nv] for c in range(d)])
+    return g_mu, g_f
