@@ -82,9 +82,11 @@ typedef enum { SMG_SCHUR_D = 0, SMG_SCHUR_LOC = 1, SMG_SCHUR_P = 2 } smg_schur_d
  *   SMG_BLOCK_B    y = B u                       u length d*Nv, y length Np
  *   SMG_BLOCK_MASS y = M_v f per component       f, y length d*Nv; f is used at
  *                  every node (also on the boundary), y is 0 on Dirichlet rows:
- *                  the load vector <F, v> of a nodal FE field f (Sec. 2).     */
+ *                  the load vector <F, v> of a nodal FE field f (Sec. 2).
+ *   SMG_BLOCK_MP   y = M_p p                     p, y length Np: the pressure mass
+ *                  matrix (its row sums M_p 1 weight the pressure mean).      */
 typedef enum {
-  SMG_BLOCK_K = 0, SMG_BLOCK_A = 1, SMG_BLOCK_BT = 2, SMG_BLOCK_B = 3, SMG_BLOCK_MASS = 4
+  SMG_BLOCK_K = 0, SMG_BLOCK_A = 1, SMG_BLOCK_BT = 2, SMG_BLOCK_B = 3, SMG_BLOCK_MASS = 4, SMG_BLOCK_MP = 5
 } smg_block;
 
 typedef enum { SMG_PRECOND_F64 = 0, SMG_PRECOND_F32 = 1 } smg_precision;
@@ -207,6 +209,20 @@ smg_status smg_solve_stationary(smg_ctx *ctx, double *x, const double *b, double
 /* HOST array xyz (Nv x d, node-major) <- physical coordinates of the velocity
  * lattice nodes of level l (for evaluating nodal data such as f). */
 smg_status smg_node_coordinates(const smg_ctx *ctx, int level, double *xyz);
+
+/* Adjoint-state gradients on the finest level.  For the solution x of
+ * K(mu) x = [Z M_v f; 0] (Z zeroes the Dirichlet rows; f a nodal velocity
+ * field) and an objective J(x), let lam solve K lam = dJ/dx (K = K^T, so
+ * smg_solve with that right-hand side).  K depends on the per-cell viscosity
+ * only through mu_tau int_tau grad u : grad v (Sec. 2, form a), hence
+ *   g_logmu[tau] = dJ/d log mu_tau = -mu_tau int_tau grad lam_u : grad u,
+ *   g_f          = dJ/df          = M_v Z lam_u   (every velocity node),
+ * with the Dirichlet entries of x and lam taken as zero (cell integrals by
+ * the operator's quadrature, on box or vertex-given cells).
+ * x, lam: DEVICE FP64, length N of the finest level.  g_logmu: DEVICE FP64,
+ * one entry per finest cell (x fastest), or NULL.  g_f: DEVICE FP64, length
+ * d*Nv, or NULL.  Asynchronous on the context's stream. */
+smg_status smg_gradient(smg_ctx *ctx, const double *x, const double *lam, double *g_logmu, double *g_f);
 
 /* Kernel timing for measurement: with enable != 0, every later operator-kernel
  * launch of this context is bracketed by two HIP events recorded on the

@@ -13,10 +13,10 @@ import numpy as np
 
 from . import _lib
 from ._lib import (SMG_F64, SMG_F32, SMG_BLOCK_K, SMG_BLOCK_A, SMG_BLOCK_BT, SMG_BLOCK_B,
-                   SMG_BLOCK_MASS, SMG_SCHUR_D, SMG_SCHUR_LOC, SMG_SCHUR_P, SmgError)
+                   SMG_BLOCK_MASS, SMG_BLOCK_MP, SMG_SCHUR_D, SMG_SCHUR_LOC, SMG_SCHUR_P, SmgError)
 
 __all__ = ["StokesMG", "SmgError", "SMG_BLOCK_K", "SMG_BLOCK_A", "SMG_BLOCK_BT", "SMG_BLOCK_B",
-           "SMG_BLOCK_MASS"]
+           "SMG_BLOCK_MASS", "SMG_BLOCK_MP"]
 
 _SCHUR = {"d": SMG_SCHUR_D, "loc": SMG_SCHUR_LOC, "p": SMG_SCHUR_P}
 
@@ -128,8 +128,10 @@ class StokesMG:
 
     def apply_block(self, level, block, x, y=None):
         nu, np_ = self.sizes(level)
-        n_in = {SMG_BLOCK_K: nu + np_, SMG_BLOCK_A: nu, SMG_BLOCK_BT: np_, SMG_BLOCK_B: nu, SMG_BLOCK_MASS: nu}[block]
-        n_out = {SMG_BLOCK_K: nu + np_, SMG_BLOCK_A: nu, SMG_BLOCK_BT: nu, SMG_BLOCK_B: np_, SMG_BLOCK_MASS: nu}[block]
+        n_in = {SMG_BLOCK_K: nu + np_, SMG_BLOCK_A: nu, SMG_BLOCK_BT: np_, SMG_BLOCK_B: nu, SMG_BLOCK_MASS: nu,
+                SMG_BLOCK_MP: np_}[block]
+        n_out = {SMG_BLOCK_K: nu + np_, SMG_BLOCK_A: nu, SMG_BLOCK_BT: nu, SMG_BLOCK_B: np_, SMG_BLOCK_MASS: nu,
+                 SMG_BLOCK_MP: np_}[block]
         self._check(x, n_in, "x")
         y = self._like(x, n_out) if y is None else y
         self._check(y, n_out, "y")
@@ -234,6 +236,32 @@ class StokesMG:
             key, cnt, ms, nbytes = line.rsplit(" ", 3)
             out[key] = (int(cnt), float(ms), float(nbytes))
         return out
+
+    def gradient(self, x, lam, g_logmu=None, g_f=None, want_logmu=True, want_f=True):
+        """Adjoint-state gradients (smg_gradient): given the finest-level state x
+        and adjoint state lam (float64 GPU vectors), returns (dJ/dlog mu per
+        finest cell, dJ/df per velocity DoF); either may be skipped."""
+        import torch
+        L = self.n_levels - 1
+        n = self.n_total(L)
+        nu, _ = self.sizes(L)
+        for t, nm in ((x, "x"), (lam, "lam")):
+            self._check(t, n, nm)
+            if t.dtype != torch.float64:
+                raise TypeError("gradient works on float64 vectors")
+        ncell = int(np.prod(self.cells(L)))
+        if want_logmu and g_logmu is None:
+            g_logmu = torch.empty(ncell, dtype=torch.float64, device=x.device)
+        if want_f and g_f is None:
+            g_f = torch.empty(nu, dtype=torch.float64, device=x.device)
+        _lib.check(self.lib.smg_gradient(self._h, _ptr(x), _ptr(lam),
+                                         _ptr(g_logmu) if want_logmu else None,
+                                         _ptr(g_f) if want_f else None))
+        return (g_logmu if want_logmu else None), (g_f if want_f else None)
+
+    def cells(self, level):
+        """Cells per direction of a level."""
+        return [int(c) * 2 ** level for c in list(self.desc.n_coarse)[:self.dim]]
 
     def node_coordinates(self, level):
         nu, _ = self.sizes(level)

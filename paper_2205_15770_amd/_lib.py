@@ -12,7 +12,7 @@ LIB_PATH = os.path.join(HERE, "libsmg.so")
 SMG_OK, SMG_EINVAL, SMG_ENOMEM, SMG_EDEVICE, SMG_ENOTCONV, SMG_EBREAKDOWN, SMG_EUNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
 SMG_F64, SMG_F32 = 0, 1
 SMG_SCHUR_D, SMG_SCHUR_LOC, SMG_SCHUR_P = 0, 1, 2
-SMG_BLOCK_K, SMG_BLOCK_A, SMG_BLOCK_BT, SMG_BLOCK_B, SMG_BLOCK_MASS = 0, 1, 2, 3, 4
+SMG_BLOCK_K, SMG_BLOCK_A, SMG_BLOCK_BT, SMG_BLOCK_B, SMG_BLOCK_MASS, SMG_BLOCK_MP = 0, 1, 2, 3, 4, 5
 SMG_PRECOND_F64, SMG_PRECOND_F32 = 0, 1
 
 STATUS_NAMES = {0: "SMG_OK", -1: "SMG_EINVAL", -2: "SMG_ENOMEM", -3: "SMG_EDEVICE",
@@ -22,7 +22,7 @@ EXPORTS = ["smg_desc_default", "smg_create", "smg_destroy", "smg_sizes", "smg_se
            "smg_vmult", "smg_residual", "smg_apply_block", "smg_get_diagonal", "smg_get_eigs",
            "smg_set_eigs", "smg_chebyshev", "smg_smooth", "smg_restrict", "smg_prolongate_add",
            "smg_coarse_solve", "smg_vcycle", "smg_solve", "smg_solve_stationary",
-           "smg_node_coordinates", "smg_profile", "smg_profile_report", "smg_last_error"]
+           "smg_node_coordinates", "smg_gradient", "smg_profile", "smg_profile_report", "smg_last_error"]
 
 
 class SmgDesc(ctypes.Structure):
@@ -86,6 +86,7 @@ def load(path=LIB_PATH):
         "smg_solve": (I, [P, P, P, D, I, ctypes.POINTER(SmgSolveInfo)]),
         "smg_solve_stationary": (I, [P, P, P, D, I, ctypes.POINTER(SmgSolveInfo)]),
         "smg_node_coordinates": (I, [P, I, P]),
+        "smg_gradient": (I, [P, P, P, P, P]),
         "smg_profile": (I, [P, I]),
         "smg_profile_report": (I, [P, ctypes.c_char_p, ctypes.c_int64, i64p]),
         "smg_last_error": (ctypes.c_char_p, []),

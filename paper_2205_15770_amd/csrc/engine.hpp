@@ -74,6 +74,7 @@ class EngineBase {
   virtual smg_status solve(double *x, const double *b, double rtol, int maxit, smg_solve_info *info) = 0;
   virtual smg_status solve_stationary(double *x, const double *b, double rtol, int maxit, smg_solve_info *info) = 0;
   virtual void node_coordinates(int l, double *xyz) = 0;
+  virtual void gradient(const double *x, const double *lam, double *g_logmu, double *g_f) = 0;
   virtual void invalidate_graphs() {}
   bool use_graphs = true;
 

@@ -280,14 +280,23 @@ class EngineT : public EngineBase {
     gg.tu = g.gs;
     gg.tp = g.gs + (int64_t)DIM * g.Nv;
     const int64_t n_all = (int64_t)DIM * g.Nv + g.Np;
-    vset<T>(g.gs, (T)0, n_all);
+    gen_accumulate<T, BLK, Op>(gg, op);
+    hipLaunchKernelGGL((gen_epilogue_kernel<DIM, T, BLK, Op>), dim3(grid_for(n_all)), dim3(VB), 0, stream, gg, op);
+    check_launch();
+  }
+
+  // cell sums of all 2^d colours into gg.tu / gg.tp (zeroed first)
+  template <typename T, int BLK, class Op>
+  void gen_accumulate(GenGeo<T> &gg, const Op &op) {
+    const int64_t n_all = (int64_t)DIM * gg.Nv + gg.Np;
+    vset<T>(gg.tu, (T)0, n_all);
     constexpr int NN = DIM == 3 ? (K + 1) * (K + 1) * (K + 1) : (K + 1) * (K + 1);
     constexpr int CPB = 64 / NN;
     for (int colour = 0; colour < (1 << DIM); ++colour) {
       int64_t ncells = 1;
       for (int a = 0; a < 3; ++a) {
         gg.off[a] = a < DIM ? (colour >> a) & 1 : 0;
-        gg.ncol[a] = a < DIM ? (g.n[a] - gg.off[a] + 1) / 2 : 1;
+        gg.ncol[a] = a < DIM ? (gg.n[a] - gg.off[a] + 1) / 2 : 1;
         ncells *= gg.ncol[a];
       }
       if (ncells == 0) continue;
@@ -295,8 +304,60 @@ class EngineT : public EngineBase {
       hipLaunchKernelGGL((gen_apply_kernel<DIM, K, T, BLK, Op>), dim3(nb), dim3(64), 0, stream, gg, op);
       check_launch();
     }
-    hipLaunchKernelGGL((gen_epilogue_kernel<DIM, T, BLK, Op>), dim3(grid_for(n_all)), dim3(VB), 0, stream, gg, op);
-    check_launch();
+  }
+
+  // finest-level vertex coordinates for the general-cell kernels (box meshes:
+  // the lattice of the box, built on first use)
+  void ensure_vertices() {
+    if (lv[L].w64.verts) return;
+    const LevelInfo &I = lv[L];
+    const int nz = DIM == 3 ? I.n[2] + 1 : 1;
+    std::vector<double> hv((size_t)(I.n[0] + 1) * (I.n[1] + 1) * nz * DIM);
+    size_t o = 0;
+    for (int k = 0; k < nz; ++k)
+      for (int j = 0; j <= I.n[1]; ++j)
+        for (int i = 0; i <= I.n[0]; ++i) {
+          const int ii[3] = {i, j, k};
+          for (int a = 0; a < DIM; ++a) hv[o++] = desc.box_lo[a] + I.h[a] * ii[a];
+        }
+    lv[L].w64.verts = dalloc<double>((int64_t)hv.size());
+    SMG_HIP(hipMemcpyAsync(lv[L].w64.verts, hv.data(), hv.size() * sizeof(double), hipMemcpyHostToDevice, stream));
+    SMG_HIP(hipStreamSynchronize(stream));
+  }
+
+  // adjoint-state gradients on the finest level (FP64)
+  void gradient(const double *x, const double *lam, double *g_logmu, double *g_f) override {
+    ensure_vertices();
+    auto g = geom<double>(L);
+    GenGeo<double> gg;
+    std::memset(&gg, 0, sizeof(gg));
+    for (int a = 0; a < 3; ++a) {
+      gg.n[a] = g.n[a];
+      gg.vd[a] = g.vd[a];
+      gg.pd[a] = g.pd[a];
+    }
+    gg.Nv = g.Nv;
+    gg.Np = g.Np;
+    gg.mu = g.mu;
+    gg.mu_cell = g.mu_cell;
+    gg.verts = lv[L].w64.verts;
+    gg.tu = g.gs;
+    gg.tp = g.gs + (int64_t)DIM * g.Nv;
+    if (g_logmu) {
+      constexpr int NN = DIM == 3 ? (K + 1) * (K + 1) * (K + 1) : (K + 1) * (K + 1);
+      constexpr int CPB = 64 / NN;
+      const int64_t ncells = (int64_t)g.n[0] * g.n[1] * g.n[2];
+      hipLaunchKernelGGL((gen_grad_logmu_kernel<DIM, K>), dim3((unsigned)((ncells + CPB - 1) / CPB)), dim3(64), 0,
+                         stream, gg, x, lam, g_logmu);
+      check_launch();
+    }
+    if (g_f) {
+      // M_v (Z lam_u) on every node: cell sums of the mass form, no Dirichlet rows
+      gen_accumulate<double, BLK_MASS>(gg, OpApply<double>{lam, nullptr, nullptr, nullptr});
+      hipLaunchKernelGGL((k_copy<double, double>), dim3(grid_for((int64_t)DIM * g.Nv)), dim3(VB), 0, stream, g_f,
+                         (const double *)gg.tu, (i64)((int64_t)DIM * g.Nv));
+      check_launch();
+    }
   }
 
   // Diagonals of general cells by probing with the operator kernels:
@@ -384,6 +445,9 @@ class EngineT : public EngineBase {
       case SMG_BLOCK_A: tile<T, BLK_A>(g, OpApply<T>{x, nullptr, y, nullptr}); break;
       case SMG_BLOCK_BT: tile<T, BLK_BT>(g, OpApply<T>{nullptr, x, y, nullptr}); break;
       case SMG_BLOCK_B: tile<T, BLK_B>(g, OpApply<T>{x, nullptr, nullptr, y}); break;
+      case SMG_BLOCK_MP:
+        tile<T, BLK_C | BLK_CPLUS>(geom<T>(l, true), OpApply<T>{nullptr, x, nullptr, y});
+        break;
       case SMG_BLOCK_MASS: {
         auto gm = g;
         tile<T, BLK_MASS>(gm, OpMass<T>{x, y});

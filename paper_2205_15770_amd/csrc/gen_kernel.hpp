@@ -421,4 +421,164 @@ __global__ void gen_epilogue_kernel(const GenGeo<T> g, const Op op) {
   }
 }
 
+// Adjoint-state gradient with respect to the per-cell log-viscosity:
+//   out[tau] = - mu_tau int_tau sum_c grad lam_c . grad u_c
+// (constrained velocity entries of u and lam taken as zero), every cell of
+// the level in one launch; one lane per quadrature point, LDS passes as in
+// gen_apply_kernel, then a sum over the cell's lanes.  FP64.
+template <int DIM, int K>
+__global__ void __launch_bounds__(64) gen_grad_logmu_kernel(const GenGeo<double> g, const double *x,
+                                                            const double *lam, double *out) {
+  using T = double;
+  constexpr int NV = K + 1;
+  constexpr int NN = DIM == 3 ? NV * NV * NV : NV * NV;
+  constexpr int CPB = 64 / NN;
+  constexpr int NVERT = 1 << DIM;
+  constexpr cfe::QTab<K, T> Q = cfe::make_qtab<K, T>();
+  __shared__ T lds[CPB][2][NN];
+
+  const int tid = threadIdx.x;
+  const int slot = tid / NN;
+  const int q = tid - slot * NN;
+  const bool in_slot = slot < CPB;
+  const int sl = in_slot ? slot : 0;
+  const i64 ncells = (i64)g.n[0] * g.n[1] * (DIM == 3 ? g.n[2] : 1);
+  const i64 ci = (i64)blockIdx.x * CPB + slot;
+  const bool live = in_slot && ci < ncells;
+  int cx = 0, cy = 0, cz = 0;
+  if (live) {
+    cx = (int)(ci % g.n[0]);
+    const i64 r = ci / g.n[0];
+    cy = (int)(r % g.n[1]);
+    cz = DIM == 3 ? (int)(r / g.n[1]) : 0;
+  }
+  const int qx = q % NV, qy = (q / NV) % NV, qz = DIM == 3 ? q / (NV * NV) : 0;
+  const int qd[3] = {qx, qy, qz};
+  T *A = lds[sl][0], *Bf = lds[sl][1];
+  T rV[3][NV], rD[3][NV];
+#pragma unroll
+  for (int d = 0; d < 3; ++d)
+#pragma unroll
+    for (int i = 0; i < NV; ++i) {
+      T vr = Q.V[0][i], dr = Q.D[0][i];
+#pragma unroll
+      for (int j = 1; j < NV; ++j) {
+        vr = qd[d] == j ? Q.V[j][i] : vr;
+        dr = qd[d] == j ? Q.D[j][i] : dr;
+      }
+      rV[d][i] = vr;
+      rD[d][i] = dr;
+    }
+  auto lidx = [](int a, int b, int c) { return a + NV * (b + NV * c); };
+  auto pass = [&](const T *in, const T (&m)[NV], int d) {
+    T s = 0;
+#pragma unroll
+    for (int i = 0; i < NV; ++i) {
+      const int k = d == 0 ? lidx(i, qy, qz) : (d == 1 ? lidx(qx, i, qz) : lidx(qx, qy, i));
+      s += m[i] * in[k];
+    }
+    return s;
+  };
+  // geometry
+  T Jinv[3][3] = {{1, 0, 0}, {0, 1, 0}, {0, 0, 1}};
+  T JxW = 0, mu = g.mu;
+  if (live) {
+    const T xi[3] = {pick(Q.x, qx), pick(Q.x, qy), DIM == 3 ? pick(Q.x, qz) : T(0)};
+    T J[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+#pragma unroll
+    for (int v = 0; v < NVERT; ++v) {
+      const int o[3] = {v & 1, (v >> 1) & 1, (v >> 2) & 1};
+      const i64 vid = (cx + o[0]) + (i64)(g.n[0] + 1) * ((cy + o[1]) + (i64)(g.n[1] + 1) * (DIM == 3 ? cz + o[2] : 0));
+#pragma unroll
+      for (int b = 0; b < DIM; ++b) {
+        T dn = o[b] ? T(1) : T(-1);
+#pragma unroll
+        for (int c = 0; c < DIM; ++c)
+          if (c != b) dn *= o[c] ? xi[c] : T(1) - xi[c];
+#pragma unroll
+        for (int a = 0; a < DIM; ++a) J[a][b] += g.verts[vid * DIM + a] * dn;
+      }
+    }
+    T det;
+    if constexpr (DIM == 2) {
+      det = J[0][0] * J[1][1] - J[0][1] * J[1][0];
+      const T id = T(1) / det;
+      Jinv[0][0] = J[1][1] * id;
+      Jinv[0][1] = -J[0][1] * id;
+      Jinv[1][0] = -J[1][0] * id;
+      Jinv[1][1] = J[0][0] * id;
+      JxW = det * pick(Q.w, qx) * pick(Q.w, qy);
+    } else {
+      const T c00 = J[1][1] * J[2][2] - J[1][2] * J[2][1];
+      const T c01 = J[1][2] * J[2][0] - J[1][0] * J[2][2];
+      const T c02 = J[1][0] * J[2][1] - J[1][1] * J[2][0];
+      det = J[0][0] * c00 + J[0][1] * c01 + J[0][2] * c02;
+      const T id = T(1) / det;
+      Jinv[0][0] = c00 * id;
+      Jinv[1][0] = c01 * id;
+      Jinv[2][0] = c02 * id;
+      Jinv[0][1] = (J[0][2] * J[2][1] - J[0][1] * J[2][2]) * id;
+      Jinv[1][1] = (J[0][0] * J[2][2] - J[0][2] * J[2][0]) * id;
+      Jinv[2][1] = (J[0][1] * J[2][0] - J[0][0] * J[2][1]) * id;
+      Jinv[0][2] = (J[0][1] * J[1][2] - J[0][2] * J[1][1]) * id;
+      Jinv[1][2] = (J[0][2] * J[1][0] - J[0][0] * J[1][2]) * id;
+      Jinv[2][2] = (J[0][0] * J[1][1] - J[0][1] * J[1][0]) * id;
+      JxW = det * pick(Q.w, qx) * pick(Q.w, qy) * pick(Q.w, qz);
+    }
+    if (g.mu_cell != nullptr) mu = g.mu_cell[cx + (i64)g.n[0] * (cy + (i64)g.n[1] * cz)];
+  }
+  const int gx = K * cx + qx, gy = K * cy + qy, gz = K * cz + qz;
+  const i64 vnode = gx + (i64)g.vd[0] * (gy + (i64)g.vd[1] * gz);
+  const bool vbc = on_box_boundary(gx, g.vd[0]) || on_box_boundary(gy, g.vd[1]) ||
+                   (DIM == 3 && on_box_boundary(gz, g.vd[2]));
+  // physical gradient at this lane's point of the field `src` (component c)
+  auto grad_at = [&](const double *src, int c, T (&gp)[3]) {
+    T v = 0;
+    if (live && !vbc) v = src[(i64)c * g.Nv + vnode];
+    if (in_slot) A[q] = v;
+    __syncthreads();
+    T t = pass(A, rV[0], 0);
+    if (in_slot) Bf[q] = t;
+    __syncthreads();
+    t = pass(Bf, rV[1], 1);
+    if constexpr (DIM == 3) {
+      if (in_slot) A[q] = t;
+      __syncthreads();
+      t = pass(A, rV[2], 2);
+    }
+    T *Fq = DIM == 3 ? Bf : A;
+    __syncthreads();
+    if (in_slot) Fq[q] = t;
+    __syncthreads();
+    T gr[3] = {0, 0, 0};
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) gr[d] = pass(Fq, rD[d], d);
+    __syncthreads();
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      T s = 0;
+#pragma unroll
+      for (int b = 0; b < DIM; ++b) s += Jinv[b][a] * gr[b];
+      gp[a] = s;
+    }
+  };
+  T acc = 0;
+#pragma unroll
+  for (int c = 0; c < DIM; ++c) {
+    T gu[3], gl[3];
+    grad_at(x, c, gu);
+    grad_at(lam, c, gl);
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) acc += gu[a] * gl[a];
+  }
+  acc *= JxW;
+  if (in_slot) A[q] = acc;
+  __syncthreads();
+  if (live && q == 0) {
+    T s = 0;
+    for (int i = 0; i < NN; ++i) s += A[i];
+    out[ci] = -mu * s;
+  }
+}
+
 }  // namespace smg

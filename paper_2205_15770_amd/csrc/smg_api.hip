@@ -245,7 +245,7 @@ smg_status smg_apply_block(smg_ctx *ctx, int level, int dtype, int block, const 
   if (s == SMG_OK) s = check_dtype(dtype);
   if (s == SMG_OK) s = check_ptrs({x, y});
   if (s != SMG_OK) return s;
-  if (block < SMG_BLOCK_K || block > SMG_BLOCK_MASS) return fail(SMG_EINVAL, "unknown block");
+  if (block < SMG_BLOCK_K || block > SMG_BLOCK_MP) return fail(SMG_EINVAL, "unknown block");
   if (x == y) return fail(SMG_EINVAL, "x and y must be distinct");
   SMG_TRY(ctx->eng->apply_block(level, dtype, block, x, y));
 }
@@ -375,6 +375,13 @@ smg_status smg_node_coordinates(const smg_ctx *ctx, int level, double *xyz) {
   if (s == SMG_OK) s = check_ptrs({xyz});
   if (s != SMG_OK) return s;
   SMG_TRY(ctx->eng->node_coordinates(level, xyz));
+}
+
+smg_status smg_gradient(smg_ctx *ctx, const double *x, const double *lam, double *g_logmu, double *g_f) {
+  smg_status s = check_ctx(ctx);
+  if (s == SMG_OK) s = check_ptrs({x, lam});
+  if (s != SMG_OK) return s;
+  SMG_TRY(ctx->eng->gradient(x, lam, g_logmu, g_f));
 }
 
 smg_status smg_profile(smg_ctx *ctx, int enable) {
