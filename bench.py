@@ -61,6 +61,10 @@ def parse():
     ap.add_argument("--workload", default="stokes2d_q2q1_512", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--quick", action="store_true", help="skip the secondary measurements")
+    ap.add_argument("--adjoint-check", type=int, default=0, metavar="NDIR",
+                    help="also time the differentiable solve (forward + adjoint backward of "
+                         "J = ||u - u_target||^2) and compare NDIR directional derivatives with "
+                         "central differences (step 1e-5, solves to 1e-11)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run one plain 512 MiB device copy (scale reference for HBM counters)")
     return ap.parse_args()
@@ -122,6 +126,61 @@ def traffic_from_profiles(kernel_key):
         return None
     k = rec.get("kernels", {}).get(kernel_key)
     return None if k is None else k.get("bytes_per_launch")
+
+
+def adjoint_check(wl, common, b, ndir):
+    """Forward + adjoint backward of J = ||u - u_target||^2 (u_target the nodal
+    interpolant of a seeded smooth random field, seed 6), gradients with
+    respect to the per-cell log-viscosity and the nodal force; NDIR central
+    differences of J along random directions of both.  FGMRES stagnates near
+    1e-12 on this problem (cond(K) with mu spanning [1, 100]), so the solves
+    go to 1e-11 and the step is 1e-5 (truncation error ~1e-10 relative)."""
+    import numpy as np
+    import torch
+    import synth_inputs as si
+    from paper_2205_15770_amd import StokesMG, SMG_BLOCK_MASS
+    from paper_2205_15770_amd.adjoint import solve
+    prob = {k: v for k, v in common.items() if k != "mu_cell"}
+    prob["precision"] = "f64"
+    L = wl["n_levels"] - 1
+    mg = StokesMG(**common)
+    X = mg.node_coordinates(L)
+    nu, _ = mg.sizes(L)
+    mg.close()
+    ut = torch.tensor(si.smooth_random_field(X, seed=6).T.ravel(), dtype=torch.float64, device="cuda")
+    fn = si.manufactured_f(X, 1.0, 0.0, 1.0).T.ravel()
+    f0 = torch.tensor(fn, dtype=torch.float64, device="cuda")
+    mu = common.get("mu_cell")
+    ncell = int(np.prod(cells(wl)[:wl["dim"]]))
+    lm0 = torch.tensor(np.log(mu) if mu is not None else np.zeros(ncell), dtype=torch.float64, device="cuda")
+
+    def J(f, lm, rtol):
+        x = solve(f, lm, rtol=rtol, maxit=500, **prob)
+        return ((x[:nu] - ut) ** 2).sum()
+
+    f = f0.clone().requires_grad_(True)
+    lm = lm0.clone().requires_grad_(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    loss = J(f, lm, 1e-11)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    loss.backward()
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    rng = np.random.default_rng(20)
+    h = 1e-5
+    errs = []
+    for _ in range(ndir):
+        dl = torch.tensor(rng.standard_normal(ncell), dtype=torch.float64, device="cuda")
+        df = torch.tensor(rng.standard_normal(nu), dtype=torch.float64, device="cuda")
+        with torch.no_grad():
+            fd = (J(f0 + h * df, lm0 + h * dl, 1e-11) - J(f0 - h * df, lm0 - h * dl, 1e-11)).item() / (2 * h)
+        an = (lm.grad @ dl + f.grad @ df).item()
+        errs.append(abs(fd - an) / max(abs(an), 1e-300))
+    return {"J": loss.item(), "forward_s_incl_setup": round(t1 - t0, 3), "backward_s": round(t2 - t1, 3),
+            "fd_directions": ndir, "fd_step": h, "fd_rel_err_max": max(errs) if errs else None,
+            "fd_rel_err_median": float(np.median(errs)) if errs else None}
 
 
 def cpu_baseline():
@@ -269,6 +328,8 @@ def main():
                           "rel_residual_mixed": infos[-1]["rel_residual"], "rel_residual_f64": i64["rel_residual"],
                           "rel_diff_mixed_vs_f64_solution": err}
         mg64.close()
+    if args.adjoint_check:
+        extra["adjoint"] = adjoint_check(wl, common, b, args.adjoint_check)
     if args.calibrate_copy:
         src = torch.ones(64 * 1024 * 1024, dtype=torch.float64, device="cuda")
         dst = torch.empty_like(src)
