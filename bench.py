@@ -58,7 +58,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="stokes2d_q2q1_512", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default="stokes2d_q2q1_512", choices=sorted(WORKLOADS) + ["batch2d_q2q1_64"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--quick", action="store_true", help="skip the secondary measurements")
     ap.add_argument("--adjoint-check", type=int, default=0, metavar="NDIR",
@@ -183,6 +183,75 @@ def adjoint_check(wl, common, b, ndir):
             "fd_rel_err_median": float(np.median(errs)) if errs else None}
 
 
+def bench_batch(args):
+    """64 independent 2D generalized Stokes Q2-Q1 instances (side counts
+    log-uniform in [32, 512] snapped to c 2^j, c in 4..7, seed 7; gamma ~
+    U[0, 1e4]; nodal random f, seed 8 + i), solved together to 1e-8 by
+    smg_batch_solve with the autotuned host-thread count; FP32-mixed and FP64
+    cycles.  value = total DoFs solved per second."""
+    import numpy as np
+    import torch
+    import synth_inputs as si
+    from paper_2205_15770_amd import StokesBatch, SMG_BLOCK_MASS
+    inst = si.batch_instances()
+    out = {}
+    for prec in ("f32", "f64"):
+        probs = [dict(dim=2, fe_degree=2, n_coarse=(d["c"], d["c"]), n_levels=d["levels"], mu=1.0, rho=1.0,
+                      gamma=d["gamma"], cheb_deg_A=1, cheb_deg_S=1, smooth_steps=2, cycle_index=1, schur_diag="d",
+                      precision=prec) for d in inst]
+        t0 = time.perf_counter()
+        batch = StokesBatch(probs)
+        torch.cuda.synchronize()
+        t_setup = time.perf_counter() - t0
+        xs, bs = [], []
+        for i, mg in enumerate(batch.solvers):
+            L = mg.n_levels - 1
+            nu, np_ = mg.sizes(L)
+            f = torch.tensor(si.nodal_random_f(2, nu // 2, seed=8 + i).ravel(), dtype=torch.float64, device="cuda")
+            b = torch.zeros(nu + np_, dtype=torch.float64, device="cuda")
+            torch.cuda.synchronize()
+            mg.apply_block(L, SMG_BLOCK_MASS, f, b[:nu])
+            bs.append(b)
+            xs.append(torch.zeros(nu + np_, dtype=torch.float64, device="cuda"))
+        torch.cuda.synchronize()
+        ntot = sum(mg.n_total(mg.n_levels - 1) for mg in batch.solvers)
+        best, tune = batch.autotune(xs, bs)
+        print(f"# batch {prec}: setup {t_setup:.2f} s, N = {ntot}, threads {best} {tune}", file=sys.stderr, flush=True)
+        for _ in range(max(args.warmup, 1)):
+            for x in xs:
+                x.zero_()
+            batch.solve(xs, bs, rtol=1e-8, maxit=300)
+        times, infos = [], None
+        for _ in range(args.steps):
+            for x in xs:
+                x.zero_()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            infos = batch.solve(xs, bs, rtol=1e-8, maxit=300)
+            torch.cuda.synchronize()
+            times.append(time.perf_counter() - t0)
+        per = np.array([i["t_solve_ms"] for i in infos])
+        its = np.array([i["iterations"] for i in infos])
+        wall = float(np.median(times))
+        out[prec] = {"wall_ms": round(wall * 1e3, 2), "gdofs": round(ntot / wall / 1e9, 4), "threads": best,
+                     "autotune_ms": {str(k): round(v, 2) for k, v in tune.items()},
+                     "instance_ms_min_median_max": [round(float(per.min()), 2), round(float(np.median(per)), 2),
+                                                    round(float(per.max()), 2)],
+                     "iterations_min_max": [int(its.min()), int(its.max())],
+                     "max_rel_residual": max(i["rel_residual"] for i in infos), "setup_s": round(t_setup, 2)}
+        batch.close()
+        torch.cuda.synchronize()
+    res = {"metric": "GDoF/s Stokes vmult; solve time to 1e-8 resid, FP32-mixed vs FP64",
+           "value": out["f32"]["gdofs"], "unit": "GDoF/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+           "ms_per_step": out["f32"]["wall_ms"], "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": "f32 cycle / f64 outer", "data": "synthetic",
+           "config": {"workload": "batch2d_q2q1_64", "instances": len(inst), "dofs": ntot,
+                      "description": "64 2D generalized Stokes Q2-Q1 instances, n log-uniform in [32, 512], "
+                                     "gamma ~ U[0, 1e4], solved together to 1e-8 (smg_batch_solve)"},
+           "batch": out, "speedup_mixed_vs_f64": round(out["f64"]["wall_ms"] / out["f32"]["wall_ms"], 3)}
+    print(json.dumps(res))
+
+
 def cpu_baseline():
     """The oracle (assembled CSR, FP64, same smoother and FGMRES) on a bounded
     sample: the same generalized Stokes problem on a 256 x 256 mesh."""
@@ -231,6 +300,9 @@ def main():
     import torch
     from paper_2205_15770_amd import StokesMG
     torch.cuda.set_device(0)
+    if args.workload == "batch2d_q2q1_64":
+        bench_batch(args)
+        return
     wl = WORKLOADS[args.workload]
     common = dict(dim=wl["dim"], fe_degree=wl["fe_degree"], n_coarse=wl["n_coarse"], n_levels=wl["n_levels"],
                   mu=wl["mu"], rho=wl["rho"], gamma=wl["gamma"], cheb_deg_A=1, cheb_deg_S=1, smooth_steps=2,

@@ -206,6 +206,25 @@ smg_status smg_solve(smg_ctx *ctx, double *x, const double *b, double rtol, int 
  * mean reduction of the last three iterations. */
 smg_status smg_solve_stationary(smg_ctx *ctx, double *x, const double *b, double rtol, int maxit, smg_solve_info *info);
 
+/* Batched solves of independent instances (the generalized Stokes problem on
+ * meshes of different sizes and with different gamma; Sec. 1 and Sec. 4.3
+ * motivate one smoother parameter set for all gamma).  Each context must have
+ * its own stream (smg_desc.stream or smg_set_stream); the instances are
+ * distributed over `nthreads` host threads, longest first by DoF count, each
+ * thread solving its share one after the other with smg_solve, so kernels of
+ * different instances overlap on the GPU.  ctxs, x, b, infos: HOST arrays of
+ * n entries (x[i], b[i] DEVICE FP64 of instance i; infos may be NULL).
+ * Returns the first failing instance's status (all instances are attempted). */
+smg_status smg_batch_solve(smg_ctx *const *ctxs, int n, double *const *x, const double *const *b, double rtol,
+                           int maxit, int nthreads, smg_solve_info *infos);
+
+/* Autotuner for smg_batch_solve: times `probe_iterations` FGMRES iterations
+ * of every instance for each thread count in candidates[0..ncand) and returns
+ * the fastest in *best (wall times in times_ms[c] if not NULL).  Overwrites
+ * x[i]. */
+smg_status smg_batch_autotune(smg_ctx *const *ctxs, int n, double *const *x, const double *const *b,
+                              const int *candidates, int ncand, int probe_iterations, int *best, double *times_ms);
+
 /* HOST array xyz (Nv x d, node-major) <- physical coordinates of the velocity
  * lattice nodes of level l (for evaluating nodal data such as f). */
 smg_status smg_node_coordinates(const smg_ctx *ctx, int level, double *xyz);

@@ -15,7 +15,7 @@ from . import _lib
 from ._lib import (SMG_F64, SMG_F32, SMG_BLOCK_K, SMG_BLOCK_A, SMG_BLOCK_BT, SMG_BLOCK_B,
                    SMG_BLOCK_MASS, SMG_BLOCK_MP, SMG_SCHUR_D, SMG_SCHUR_LOC, SMG_SCHUR_P, SmgError)
 
-__all__ = ["StokesMG", "SmgError", "SMG_BLOCK_K", "SMG_BLOCK_A", "SMG_BLOCK_BT", "SMG_BLOCK_B",
+__all__ = ["StokesMG", "StokesBatch", "SmgError", "SMG_BLOCK_K", "SMG_BLOCK_A", "SMG_BLOCK_BT", "SMG_BLOCK_B",
            "SMG_BLOCK_MASS", "SMG_BLOCK_MP"]
 
 _SCHUR = {"d": SMG_SCHUR_D, "loc": SMG_SCHUR_LOC, "p": SMG_SCHUR_P}
@@ -269,3 +269,70 @@ class StokesMG:
         xyz = np.zeros((nv, self.dim))
         _lib.check(self.lib.smg_node_coordinates(self._h, level, xyz.ctypes.data_as(ctypes.c_void_p)))
         return xyz
+
+
+class StokesBatch:
+    """Independent instances solved together (smg_batch_solve): one StokesMG
+    per instance, each on its own torch stream (default priority), solved by
+    several host threads so that the instances' kernels overlap."""
+
+    def __init__(self, problems):
+        import torch
+        self.streams = [torch.cuda.Stream() for _ in problems]
+        self.solvers = [StokesMG(stream=st.cuda_stream, **p) for st, p in zip(self.streams, problems)]
+        self.lib = self.solvers[0].lib
+        self.nthreads = None
+
+    def __len__(self):
+        return len(self.solvers)
+
+    def _arrays(self, xs, bs):
+        n = len(self.solvers)
+        P = ctypes.c_void_p
+        ctxs = (P * n)(*[s._h.value for s in self.solvers])
+        xa = (P * n)(*[x.data_ptr() for x in xs])
+        ba = (P * n)(*[b.data_ptr() for b in bs])
+        return ctxs, xa, ba
+
+    def _check(self, xs, bs):
+        import torch
+        for s, x, b in zip(self.solvers, xs, bs):
+            n = s.n_total(s.n_levels - 1)
+            for t, nm in ((x, "x"), (b, "b")):
+                s._check(t, n, nm)
+                if t.dtype != torch.float64:
+                    raise TypeError("batch solves work on float64 vectors")
+
+    def autotune(self, xs, bs, candidates=(1, 2, 4, 8, 16), probe_iterations=2):
+        """Fastest host-thread count for this batch (smg_batch_autotune);
+        overwrites xs.  Returns (best, {candidate: ms})."""
+        import torch
+        self._check(xs, bs)
+        torch.cuda.synchronize()
+        ctxs, xa, ba = self._arrays(xs, bs)
+        cand = (ctypes.c_int * len(candidates))(*candidates)
+        best = ctypes.c_int()
+        times = (ctypes.c_double * len(candidates))()
+        _lib.check(self.lib.smg_batch_autotune(ctxs, len(self.solvers), xa, ba, cand, len(candidates),
+                                               int(probe_iterations), ctypes.byref(best), times))
+        self.nthreads = best.value
+        return best.value, {c: times[i] for i, c in enumerate(candidates)}
+
+    def solve(self, xs, bs, rtol=1e-8, maxit=300, nthreads=None, raise_on_failure=True):
+        """Solve every instance; returns the per-instance info dicts."""
+        import torch
+        self._check(xs, bs)
+        torch.cuda.synchronize()
+        n = len(self.solvers)
+        nthreads = nthreads or self.nthreads or min(8, n)
+        infos = (_lib.SmgSolveInfo * n)()
+        ctxs, xa, ba = self._arrays(xs, bs)
+        st = self.lib.smg_batch_solve(ctxs, n, xa, ba, float(rtol), int(maxit), int(nthreads), infos)
+        if st != _lib.SMG_OK and raise_on_failure:
+            _lib.check(st)
+        return [{"iterations": i.iterations, "rel_residual": i.rel_residual, "t_solve_ms": i.t_solve_ms}
+                for i in infos]
+
+    def close(self):
+        for s in self.solvers:
+            s.close()

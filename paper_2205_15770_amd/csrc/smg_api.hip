@@ -4,7 +4,10 @@
 #include <cstring>
 #include <string>
 
+#include <chrono>
 #include <map>
+#include <thread>
+#include <vector>
 
 #include "engine.hpp"
 
@@ -375,6 +378,90 @@ smg_status smg_node_coordinates(const smg_ctx *ctx, int level, double *xyz) {
   if (s == SMG_OK) s = check_ptrs({xyz});
   if (s != SMG_OK) return s;
   SMG_TRY(ctx->eng->node_coordinates(level, xyz));
+}
+
+namespace {
+// Instances -> host threads, longest-processing-time first by finest-level DoFs.
+std::vector<std::vector<int>> lpt_groups(smg_ctx *const *ctxs, int n, int nthreads) {
+  std::vector<int> order(n);
+  for (int i = 0; i < n; ++i) order[i] = i;
+  auto size = [&](int i) { return ctxs[i]->eng->lv.back().N; };
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return size(a) > size(b); });
+  std::vector<std::vector<int>> groups(nthreads);
+  std::vector<int64_t> load(nthreads, 0);
+  for (int i : order) {
+    const int t = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+    groups[t].push_back(i);
+    load[t] += size(i);
+  }
+  return groups;
+}
+}  // namespace
+
+smg_status smg_batch_solve(smg_ctx *const *ctxs, int n, double *const *x, const double *const *b, double rtol,
+                           int maxit, int nthreads, smg_solve_info *infos) {
+  if (!ctxs || !x || !b || n < 1) return fail(SMG_EINVAL, "need n >= 1 contexts and vectors");
+  for (int i = 0; i < n; ++i) {
+    smg_status s = check_ctx(ctxs[i]);
+    if (s == SMG_OK) s = check_ptrs({x[i], b[i]});
+    if (s != SMG_OK) return s;
+    for (int j = 0; j < i; ++j)
+      if (ctxs[j] == ctxs[i]) return fail(SMG_EINVAL, "a context appears twice in the batch");
+  }
+  if (!(rtol > 0) || maxit < 0) return fail(SMG_EINVAL, "need rtol > 0 and maxit >= 0");
+  nthreads = std::max(1, std::min(nthreads, n));
+  const std::vector<std::vector<int>> groups = lpt_groups(ctxs, n, nthreads);
+  std::vector<smg_status> st(n, SMG_OK);
+  std::vector<std::string> err(n);
+  auto work = [&](int t) {
+    for (int i : groups[t]) {
+      try {
+        if (hipSetDevice(ctxs[i]->device) != hipSuccess) {
+          st[i] = SMG_EDEVICE;
+          err[i] = "hipSetDevice failed";
+          continue;
+        }
+        st[i] = smg_solve(ctxs[i], x[i], b[i], rtol, maxit, infos ? &infos[i] : nullptr);
+        if (st[i] != SMG_OK) err[i] = g_last_error;
+      } catch (const std::exception &e) {
+        st[i] = SMG_EDEVICE;
+        err[i] = std::string("exception: ") + e.what();
+      }
+    }
+  };
+  std::vector<std::thread> th;
+  for (int t = 1; t < nthreads; ++t) th.emplace_back(work, t);
+  work(0);
+  for (auto &h : th) h.join();
+  for (int i = 0; i < n; ++i)
+    if (st[i] != SMG_OK) return fail(st[i], "instance " + std::to_string(i) + ": " + err[i]);
+  g_last_error.clear();
+  return SMG_OK;
+}
+
+smg_status smg_batch_autotune(smg_ctx *const *ctxs, int n, double *const *x, const double *const *b,
+                              const int *candidates, int ncand, int probe_iterations, int *best, double *times_ms) {
+  if (!candidates || ncand < 1 || !best || probe_iterations < 1) return fail(SMG_EINVAL, "bad autotune arguments");
+  double tbest = 1e300;
+  for (int c = 0; c < ncand; ++c) {
+    if (candidates[c] < 1) return fail(SMG_EINVAL, "thread counts must be >= 1");
+    for (int i = 0; i < n; ++i) {
+      smg_status s = check_ctx(ctxs ? ctxs[i] : nullptr);
+      if (s != SMG_OK) return s;
+    }
+    const auto t0 = std::chrono::steady_clock::now();
+    // a fixed amount of work: probe_iterations FGMRES iterations per instance
+    smg_status s = smg_batch_solve(ctxs, n, x, b, 1e-300, probe_iterations, candidates[c], nullptr);
+    const double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    if (s != SMG_OK && s != SMG_ENOTCONV) return s;
+    if (times_ms) times_ms[c] = ms;
+    if (ms < tbest) {
+      tbest = ms;
+      *best = candidates[c];
+    }
+  }
+  g_last_error.clear();
+  return SMG_OK;
 }
 
 smg_status smg_gradient(smg_ctx *ctx, const double *x, const double *lam, double *g_logmu, double *g_f) {

@@ -185,3 +185,21 @@ def smooth_random_field(X, seed=6, modes=6):
             out[:, c] += rng.standard_normal() * np.cos(2 * np.pi * X @ kv + ph)
         out[:, c] *= bubble
     return out
+
+
+# ---------------------------------------------------------------------------
+# batches of independent instances (2D generalized Stokes)
+# ---------------------------------------------------------------------------
+def batch_instances(count=64, n_min=32, n_max=512, gamma_max=1e4, seed=7):
+    """Side counts drawn log-uniformly in [n_min, n_max] and snapped to the
+    nearest c 2^j with c in {4, 5, 6, 7} (coarsest mesh c x c, j + 1 levels),
+    gamma ~ U[0, gamma_max]; returns a list of dicts (n, c, levels, gamma)."""
+    rng = np.random.default_rng(seed)
+    draws = np.exp(rng.uniform(np.log(n_min), np.log(n_max), size=count))
+    gammas = rng.uniform(0.0, gamma_max, size=count)
+    cands = sorted({(c * 2 ** j, c, j) for c in (4, 5, 6, 7) for j in range(0, 12)})
+    out = []
+    for v, g in zip(draws, gammas):
+        n, c, j = min(cands, key=lambda t: (abs(t[0] - v), t[0]))
+        out.append(dict(n=n, c=c, levels=j + 1, gamma=float(g)))
+    return out
