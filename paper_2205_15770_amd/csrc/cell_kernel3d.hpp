@@ -152,18 +152,60 @@ struct Sweep {
   bool last_x, last_y;
 };
 
-// ------------------------------------------------------------ velocity wave
-template <int K, typename T, int BLK, class Op, int COMP, int TX>
-__device__ __forceinline__ void vel_wave(const Geo3<T> &g, const Op &op, const Column3D<K, T> &col, const Sweep &s) {
+// Cell matrices of one velocity component on one box cell:
+//   y = (A u)_COMP (BLK_A) or (M u)_COMP (BLK_MASS), plus (B^T p)_COMP (BLK_BT).
+template <int K, typename T, int BLK, int COMP>
+__device__ __forceinline__ void vel_cell(const Geo3<T> &g, T mu, const T (&u)[K + 1][K + 1][K + 1],
+                                         const T (&p)[K][K][K], T (&y)[K + 1][K + 1][K + 1]) {
   constexpr int NV = K + 1, NP = K;
   constexpr cfe::TabT<K, T> R = cfe::make_tab_t<K, T>();
-  constexpr bool NEED_U = (BLK & (BLK_A | BLK_MASS)) != 0;
-  constexpr bool NEED_P = (BLK & BLK_BT) != 0;
   // B_c^T: Gr^T in direction COMP, Nr^T in the others
   const T(&Bx)[K][K + 1] = COMP == 0 ? R.Gr : R.Nr;
   const T(&By)[K][K + 1] = COMP == 1 ? R.Gr : R.Nr;
   const T(&Bz)[K][K + 1] = COMP == 2 ? R.Gr : R.Nr;
+  if constexpr ((BLK & BLK_A) != 0) {
+    T X[NV][NV];
+    const T ax = mu * g.sKx, bx = g.gr * g.sM;
+#pragma unroll
+    for (int i = 0; i < NV; ++i)
+#pragma unroll
+      for (int j = 0; j < NV; ++j) X[i][j] = ax * R.Kr[i][j] + bx * R.Mr[i][j];
+    T a[NV][NV][NV], t[NV][NV][NV];
+    pass_z<false, false>(R.Mr, u, a, T(1));
+    pass_y<false, false>(R.Mr, a, t, T(1));
+    pass_x<false, false>(X, t, y, T(1));
+    pass_y<false, false>(R.Kr, a, t, T(1));
+    pass_z<false, false>(R.Kr, u, a, T(1));
+    pass_y<false, true>(R.Mr, a, t, g.rz);
+    pass_x<false, true>(R.Mr, t, y, mu * g.sKy);
+  } else if constexpr ((BLK & BLK_MASS) != 0) {
+    T a[NV][NV][NV], t[NV][NV][NV];
+    pass_z<false, false>(R.Mr, u, a, T(1));
+    pass_y<false, false>(R.Mr, a, t, T(1));
+    pass_x<false, false>(R.Mr, t, y, g.sM);
+  }
+  if constexpr ((BLK & BLK_BT) != 0) {
+    constexpr bool ACC = (BLK & (BLK_A | BLK_MASS)) != 0;
+    T s1[NV][NP][NP], s2[NV][NV][NP];
+    pass_z<true, false>(Bz, p, s1, T(1));
+    pass_y<true, false>(By, s1, s2, T(1));
+    pass_x<true, ACC>(Bx, s2, y, -g.sB[COMP]);
+  } else if constexpr ((BLK & (BLK_A | BLK_MASS)) == 0) {
+#pragma unroll
+    for (int z = 0; z < NV; ++z)
+#pragma unroll
+      for (int j = 0; j < NV; ++j)
+#pragma unroll
+        for (int i = 0; i < NV; ++i) y[z][j][i] = 0;
+  }
+}
 
+// ------------------------------------------------------------ velocity wave
+template <int K, typename T, int BLK, class Op, int COMP, int TX>
+__device__ __forceinline__ void vel_wave(const Geo3<T> &g, const Op &op, const Column3D<K, T> &col, const Sweep &s) {
+  constexpr int NV = K + 1, NP = K;
+  constexpr bool NEED_U = (BLK & (BLK_A | BLK_MASS)) != 0;
+  constexpr bool NEED_P = (BLK & BLK_BT) != 0;
   T u[NV][NV][NV], un[K][NV][NV];
   T p[NP][NP][NP], pn[NP - 1][NP][NP];
   T carry[NV][NV];
@@ -210,34 +252,7 @@ __device__ __forceinline__ void vel_wave(const Geo3<T> &g, const Op &op, const C
     }
 
     T y[NV][NV][NV];
-    if constexpr ((BLK & BLK_A) != 0) {
-      T X[NV][NV];
-      const T ax = mu * g.sKx, bx = g.gr * g.sM;
-#pragma unroll
-      for (int i = 0; i < NV; ++i)
-#pragma unroll
-        for (int j = 0; j < NV; ++j) X[i][j] = ax * R.Kr[i][j] + bx * R.Mr[i][j];
-      T a[NV][NV][NV], t[NV][NV][NV];
-      pass_z<false, false>(R.Mr, u, a, T(1));
-      pass_y<false, false>(R.Mr, a, t, T(1));
-      pass_x<false, false>(X, t, y, T(1));
-      pass_y<false, false>(R.Kr, a, t, T(1));
-      pass_z<false, false>(R.Kr, u, a, T(1));
-      pass_y<false, true>(R.Mr, a, t, g.rz);
-      pass_x<false, true>(R.Mr, t, y, mu * g.sKy);
-    } else if constexpr ((BLK & BLK_MASS) != 0) {
-      T a[NV][NV][NV], t[NV][NV][NV];
-      pass_z<false, false>(R.Mr, u, a, T(1));
-      pass_y<false, false>(R.Mr, a, t, T(1));
-      pass_x<false, false>(R.Mr, t, y, g.sM);
-    }
-    if constexpr ((BLK & BLK_BT) != 0) {
-      constexpr bool ACC = (BLK & (BLK_A | BLK_MASS)) != 0;
-      T s1[NV][NP][NP], s2[NV][NV][NP];
-      pass_z<true, false>(Bz, p, s1, T(1));
-      pass_y<true, false>(By, s1, s2, T(1));
-      pass_x<true, ACC>(Bx, s2, y, -g.sB[COMP]);
-    }
+    vel_cell<K, T, BLK, COMP>(g, mu, u, p, y);
     hand_over_xy<TX>(y, s.lcx, s.lcy, s.last_x, s.last_y);
 #pragma unroll
     for (int j = 0; j < NV; ++j)
@@ -425,6 +440,244 @@ __device__ __forceinline__ void pres_wave(const Geo3<T> &g, const Op &op, const 
       }
     }
   }
+}
+
+// ---------------------------------------------------------------------------
+// Small levels: one wave per 4 x 4 x 4 cells (lane = x + 4 y + 16 z) and
+// output field, one cell per lane, no sweep; the tile owns 3 x 3 x 3 cells
+// (lane coordinate 0 is halo in each direction) and the z = K face moves to
+// lane + 16 by a shuffle like the x and y faces.  A wave's critical path is
+// one cell instead of a column, which is what the latency-bound small levels
+// need.
+// ---------------------------------------------------------------------------
+struct Block3D {
+  int lx, ly, lz;
+  int cz;             // cell layer (clamped into the mesh for addressing)
+  bool active, owner;
+  bool last_x, last_y, last_z;
+};
+
+template <int K, typename T, int BLK, class Op, int COMP>
+__device__ __forceinline__ void block_vel(const Geo3<T> &g, const Op &op, const Column3D<K, T> &col,
+                                          const Block3D &s) {
+  constexpr int NV = K + 1, NP = K;
+  constexpr bool NEED_U = (BLK & (BLK_A | BLK_MASS)) != 0;
+  constexpr bool NEED_P = (BLK & BLK_BT) != 0;
+  T u[NV][NV][NV], p[NP][NP][NP];
+  if constexpr (NEED_U) col.template load_u<0>(op, COMP, s.cz, u);
+  if constexpr (NEED_P) col.template load_p<0>(op, s.cz, p);
+  T mu = 0;
+  if constexpr ((BLK & BLK_A) != 0) mu = col.mu_at(s.cz);
+  typename Op::Pre pre[K][K][K];
+  if (s.owner) {
+#pragma unroll
+    for (int z = 0; z < K; ++z)
+#pragma unroll
+      for (int y = 0; y < K; ++y)
+#pragma unroll
+        for (int x = 0; x < K; ++x) pre[z][y][x] = op.fetch_u(col.u_at(COMP, s.cz, x, y, z));
+  }
+  // keep the requests above unconditional (see the 2D wave kernel)
+  __asm__ volatile("" ::: "memory");
+#pragma unroll
+  for (int z = 0; z < NV; ++z)
+#pragma unroll
+    for (int j = 0; j < NV; ++j)
+#pragma unroll
+      for (int i = 0; i < NV; ++i) {
+        if constexpr (NEED_U) {
+          const bool keep = s.active & !(Op::ZERO_BC & col.vbc(s.cz, i, j, z));
+          u[z][j][i] = keep ? u[z][j][i] : T(0);
+        } else {
+          u[z][j][i] = 0;
+        }
+      }
+  if constexpr (NEED_P) {
+#pragma unroll
+    for (int z = 0; z < NP; ++z)
+#pragma unroll
+      for (int j = 0; j < NP; ++j)
+#pragma unroll
+        for (int i = 0; i < NP; ++i) p[z][j][i] = s.active ? p[z][j][i] : T(0);
+  }
+  T y[NV][NV][NV];
+  vel_cell<K, T, BLK, COMP>(g, mu, u, p, y);
+  hand_over_xy<4>(y, s.lx, s.ly, s.last_x, s.last_y);
+#pragma unroll
+  for (int j = 0; j < NV; ++j)
+#pragma unroll
+    for (int i = 0; i < NV; ++i) {
+      const T r = __shfl_up(y[K][j][i], 16, 64);
+      if (s.lz > 0) y[0][j][i] += r;
+      if (!s.last_z) y[K][j][i] = 0;
+    }
+  if (!s.owner) return;
+#pragma unroll
+  for (int z = 0; z < K; ++z)
+#pragma unroll
+    for (int yy = 0; yy < K; ++yy)
+#pragma unroll
+      for (int x = 0; x < K; ++x)
+        op.store_u(col.u_at(COMP, s.cz, x, yy, z), y[z][yy][x], u[z][yy][x], false, pre[z][yy][x]);
+  if (col.bxl | col.byl | (s.cz == 0)) {
+#pragma unroll
+    for (int z = 0; z < K; ++z)
+#pragma unroll
+      for (int yy = 0; yy < K; ++yy)
+#pragma unroll
+        for (int x = 0; x < K; ++x) {
+          if (!col.vbc(s.cz, x, yy, z)) continue;
+          const BOff gi = col.u_at(COMP, s.cz, x, yy, z);
+          T rw = 0;
+          if constexpr ((BLK & BLK_A) != 0) rw = op.load_u(gi);
+          op.store_u(gi, rw, rw, true, pre[z][yy][x]);
+        }
+  }
+  if (s.last_x | s.last_y | s.last_z) {
+#pragma unroll
+    for (int z = 0; z < NV; ++z)
+#pragma unroll
+      for (int yy = 0; yy < NV; ++yy)
+#pragma unroll
+        for (int x = 0; x < NV; ++x) {
+          if (x < K && yy < K && z < K) continue;
+          if ((x == K && !s.last_x) || (yy == K && !s.last_y) || (z == K && !s.last_z)) continue;
+          const BOff gi = col.u_at(COMP, s.cz, x, yy, z);
+          T rw = 0;
+          if constexpr ((BLK & BLK_A) != 0) rw = op.load_u(gi);
+          op.store_u(gi, rw, rw, true, op.fetch_u(gi));
+        }
+  }
+}
+
+template <int K, typename T, int BLK, class Op>
+__device__ __forceinline__ void block_pres(const Geo3<T> &g, const Op &op, const Column3D<K, T> &col,
+                                           const Block3D &s) {
+  constexpr int NV = K + 1, NP = K;
+  constexpr cfe::TabT<K, T> R = cfe::make_tab_t<K, T>();
+  constexpr bool NEED_U = (BLK & BLK_B) != 0;
+  constexpr bool NEED_P = (BLK & BLK_C) != 0;
+  T ub[3][NV][NV][NV], p[NP][NP][NP];
+  if constexpr (NEED_U) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) col.template load_u<0>(op, c, s.cz, ub[c]);
+  }
+  if constexpr (NEED_P) col.template load_p<0>(op, s.cz, p);
+  typename Op::Pre pre[K - 1][K - 1][K - 1];
+  if (s.owner) {
+#pragma unroll
+    for (int z = 0; z < K - 1; ++z)
+#pragma unroll
+      for (int yy = 0; yy < K - 1; ++yy)
+#pragma unroll
+        for (int x = 0; x < K - 1; ++x) pre[z][yy][x] = op.fetch_p(col.p_at(s.cz, x, yy, z));
+  }
+  __asm__ volatile("" ::: "memory");
+  T yp[NP][NP][NP];
+#pragma unroll
+  for (int z = 0; z < NP; ++z)
+#pragma unroll
+    for (int j = 0; j < NP; ++j)
+#pragma unroll
+      for (int i = 0; i < NP; ++i) yp[z][j][i] = 0;
+  if constexpr (NEED_U) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+#pragma unroll
+      for (int z = 0; z < NV; ++z)
+#pragma unroll
+        for (int j = 0; j < NV; ++j)
+#pragma unroll
+          for (int i = 0; i < NV; ++i) {
+            const bool keep = s.active & !(Op::ZERO_BC & col.vbc(s.cz, i, j, z));
+            ub[c][z][j][i] = keep ? ub[c][z][j][i] : T(0);
+          }
+      T w1[NV][NV][NP], w2[NV][NP][NP];
+      pass_x<false, false>(c == 0 ? R.Gr : R.Nr, ub[c], w1, T(1));
+      pass_y<false, false>(c == 1 ? R.Gr : R.Nr, w1, w2, T(1));
+      pass_z<false, true>(c == 2 ? R.Gr : R.Nr, w2, yp, -g.sB[c]);
+    }
+  }
+  if constexpr (NEED_P) {
+#pragma unroll
+    for (int z = 0; z < NP; ++z)
+#pragma unroll
+      for (int j = 0; j < NP; ++j)
+#pragma unroll
+        for (int i = 0; i < NP; ++i) p[z][j][i] = s.active ? p[z][j][i] : T(0);
+    const T sc = ((BLK & BLK_CPLUS) ? g.cp : -g.cp) * g.sM;
+    T q1[NP][NP][NP], q2[NP][NP][NP];
+    pass_x<false, false>(R.Mpr, p, q1, T(1));
+    pass_y<false, false>(R.Mpr, q1, q2, T(1));
+    pass_z<false, true>(R.Mpr, q2, yp, sc);
+  } else {
+#pragma unroll
+    for (int z = 0; z < NP; ++z)
+#pragma unroll
+      for (int j = 0; j < NP; ++j)
+#pragma unroll
+        for (int i = 0; i < NP; ++i) p[z][j][i] = 0;
+  }
+  hand_over_xy<4>(yp, s.lx, s.ly, s.last_x, s.last_y);
+#pragma unroll
+  for (int j = 0; j < NP; ++j)
+#pragma unroll
+    for (int i = 0; i < NP; ++i) {
+      const T r = __shfl_up(yp[NP - 1][j][i], 16, 64);
+      if (s.lz > 0) yp[0][j][i] += r;
+      if (!s.last_z) yp[NP - 1][j][i] = 0;
+    }
+  if (!s.owner) return;
+#pragma unroll
+  for (int z = 0; z < NP; ++z)
+#pragma unroll
+    for (int yy = 0; yy < NP; ++yy)
+#pragma unroll
+      for (int x = 0; x < NP; ++x) {
+        const bool main = x < K - 1 && yy < K - 1 && z < K - 1;
+        if (main) {
+          op.store_p(col.p_at(s.cz, x, yy, z), yp[z][yy][x], p[z][yy][x], pre[main ? z : 0][main ? yy : 0][main ? x : 0]);
+        } else if (((x < K - 1) | s.last_x) & ((yy < K - 1) | s.last_y) & ((z < K - 1) | s.last_z)) {
+          const BOff gi = col.p_at(s.cz, x, yy, z);
+          op.store_p(gi, yp[z][yy][x], p[z][yy][x], op.fetch_p(gi));
+        }
+      }
+}
+
+template <int K, typename T, int BLK, class Op>
+__global__ void __launch_bounds__(64)
+block3d_kernel(const Geo3<T> g, const Op op) {
+  constexpr bool OUT_U = (BLK & (BLK_A | BLK_MASS | BLK_BT)) != 0;
+  constexpr bool OUT_P = (BLK & (BLK_B | BLK_C)) != 0;
+  constexpr int NFIELD = (OUT_U ? 3 : 0) + (OUT_P ? 1 : 0);
+  const int b = xcd_contiguous_tile(blockIdx.x, gridDim.x);
+  const int field = b % NFIELD;
+  int rest = b / NFIELD;
+  const int tx = rest % g.tiles[0];
+  rest /= g.tiles[0];
+  const int ty = rest % g.tiles[1];
+  const int tz = rest / g.tiles[1];
+  Block3D s;
+  s.lx = threadIdx.x % 4;
+  s.ly = (threadIdx.x / 4) % 4;
+  s.lz = threadIdx.x / 16;
+  const Column3D<K, T> col(g, tx * 3 - 1 + s.lx, ty * 3 - 1 + s.ly);
+  const int cz = tz * 3 - 1 + s.lz;
+  s.cz = cz < 0 ? 0 : (cz >= g.n[2] ? g.n[2] - 1 : cz);
+  s.active = col.active && cz >= 0 && cz < g.n[2];
+  s.owner = s.active && s.lx > 0 && s.ly > 0 && s.lz > 0;
+  s.last_x = col.bxh;
+  s.last_y = col.byh;
+  s.last_z = cz == g.n[2] - 1;
+  if constexpr (OUT_U) {
+    switch (field) {
+      case 0: block_vel<K, T, BLK, Op, 0>(g, op, col, s); return;
+      case 1: block_vel<K, T, BLK, Op, 1>(g, op, col, s); return;
+      case 2: block_vel<K, T, BLK, Op, 2>(g, op, col, s); return;
+      default: break;
+    }
+  }
+  if constexpr (OUT_P) block_pres<K, T, BLK, Op>(g, op, col, s);
 }
 
 template <int K, typename T, int BLK, class Op, int TX, int TY>

@@ -4,6 +4,7 @@
 #include <algorithm>
 #include <chrono>
 #include <cstdio>
+#include <cstdlib>
 
 #include "cell_kernel2d.hpp"
 #include "gen_kernel.hpp"
@@ -15,6 +16,15 @@
 #include "vec_kernels.hpp"
 
 namespace smg {
+
+// Largest 3D Q2 level (cells per direction, all three directions) that runs
+// the one-cell-per-lane block kernel instead of the column sweep.  The
+// environment variable SMG_BLOCK3D_MAX_N, read when a solver is set up,
+// overrides it (0: sweep everywhere).
+inline int block3d_max_n_from_env() {
+  const char *e = std::getenv("SMG_BLOCK3D_MAX_N");
+  return e != nullptr ? std::atoi(e) : 32;
+}
 
 // Lanczos (Algorithm 2 asks for a close approximation of lambda_max): steps,
 // safety factor and SplitMix64 seeds of the start vectors.
@@ -57,6 +67,7 @@ class EngineT : public EngineBase {
   Ref1D ref;
   TransferTables ttab;
   bool general = false;                      // cells given by vertices
+  int block3d_max_n = block3d_max_n_from_env();
   std::vector<std::vector<double>> hverts;   // per level, host copy (node coordinates)
   double *Kinv = nullptr;
   int n0 = 0;
@@ -234,16 +245,23 @@ class EngineT : public EngineBase {
       g3.sB[0] = (T)(hy * hz);
       g3.sB[1] = (T)(hx * hz);
       g3.sB[2] = (T)(hx * hy);
-      g3.tiles[0] = (g.n[0] + 6) / 7;
-      g3.tiles[1] = (g.n[1] + 6) / 7;
-      const int cols = g3.tiles[0] * g3.tiles[1] * NF;
-      int nzc = (2048 + cols - 1) / cols;
-      const int zmax = (g.n[2] + 1) / 2;
-      nzc = nzc < 1 ? 1 : (nzc > zmax ? zmax : nzc);
-      const int zlen = (g.n[2] + nzc - 1) / nzc;
-      g3.tiles[2] = (g.n[2] + zlen - 1) / zlen;
-      const unsigned nb3 = (unsigned)(cols * g3.tiles[2]);
-      hipLaunchKernelGGL((tile3d_kernel<K, T, BLK, Op, 8, 8>), dim3(nb3), dim3(64), 0, stream, g3, op);
+      if (std::max(g.n[0], std::max(g.n[1], g.n[2])) <= block3d_max_n) {
+        // small level: 4 x 4 x 4 cells per wave, one cell per lane, no sweep
+        for (int a = 0; a < 3; ++a) g3.tiles[a] = (g.n[a] + 2) / 3;
+        const unsigned nbb = (unsigned)(g3.tiles[0] * g3.tiles[1] * g3.tiles[2] * NF);
+        hipLaunchKernelGGL((block3d_kernel<K, T, BLK, Op>), dim3(nbb), dim3(64), 0, stream, g3, op);
+      } else {
+        g3.tiles[0] = (g.n[0] + 6) / 7;
+        g3.tiles[1] = (g.n[1] + 6) / 7;
+        const int cols = g3.tiles[0] * g3.tiles[1] * NF;
+        int nzc = (2048 + cols - 1) / cols;
+        const int zmax = (g.n[2] + 1) / 2;
+        nzc = nzc < 1 ? 1 : (nzc > zmax ? zmax : nzc);
+        const int zlen = (g.n[2] + nzc - 1) / nzc;
+        g3.tiles[2] = (g.n[2] + zlen - 1) / zlen;
+        const unsigned nb3 = (unsigned)(cols * g3.tiles[2]);
+        hipLaunchKernelGGL((tile3d_kernel<K, T, BLK, Op, 8, 8>), dim3(nb3), dim3(64), 0, stream, g3, op);
+      }
     }
     check_launch();
     if (profiling) {

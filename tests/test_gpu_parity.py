@@ -10,6 +10,8 @@ tiles 3 x 3 x 3 (k = 2) / 2 x 2 x 2 (k = 3) cells).  Tolerances:
     maps composed; rounding differences grow by the iteration's norm);
   * FP32: <= 2e-5 relative (single-precision roundings, same count).
 """
+import os
+
 import numpy as np
 import pytest
 
@@ -27,6 +29,9 @@ CONFIGS = {
     "2d_k2": dict(dim=2, k=2, n_coarse=(5, 3), levels=4),
     "2d_k3": dict(dim=2, k=3, n_coarse=(3, 2), levels=4),
     "3d_k2": dict(dim=3, k=2, n_coarse=(2, 3, 2), levels=3),
+    # the same levels through the column-sweep kernel (by default levels of at
+    # most 32 cells per direction take the one-cell-per-lane block kernel)
+    "3d_k2_sweep": dict(dim=3, k=2, n_coarse=(2, 3, 2), levels=3, sweep=True),
     "3d_k3": dict(dim=3, k=3, n_coarse=(2, 2, 3), levels=2),
     # vertex-given (multilinear) cells: interior vertices of the finest mesh
     # moved by up to 0.2 h, coarse levels take the finest vertices
@@ -52,9 +57,18 @@ def _setup(name, c_p=0.0, kA=1, kS=1, schur="d", m=2, cycle=1, percell=True):
     meshes = make_hierarchy(dim, cfg["n_coarse"], L, k, fine_mu=mu_cell, fine_vertices=verts)
     ora = Multigrid(meshes, mu=1.0, gamma=PHYS["gamma"], rho=PHYS["rho"], c_p=c_p, k_A=kA, k_S=kS,
                     schur=schur, smooth_steps=m, cycle_index=cycle)
-    gpu = StokesMG(dim=dim, fe_degree=k, n_coarse=cfg["n_coarse"], n_levels=L, mu=1.0, mu_cell=mu_cell,
-                   gamma=PHYS["gamma"], rho=PHYS["rho"], c_pressure=c_p, cheb_deg_A=kA, cheb_deg_S=kS,
-                   smooth_steps=m, cycle_index=cycle, schur_diag=schur, fine_vertices=verts)
+    saved = os.environ.get("SMG_BLOCK3D_MAX_N")
+    if cfg.get("sweep"):
+        os.environ["SMG_BLOCK3D_MAX_N"] = "0"
+    try:
+        gpu = StokesMG(dim=dim, fe_degree=k, n_coarse=cfg["n_coarse"], n_levels=L, mu=1.0, mu_cell=mu_cell,
+                       gamma=PHYS["gamma"], rho=PHYS["rho"], c_pressure=c_p, cheb_deg_A=kA, cheb_deg_S=kS,
+                       smooth_steps=m, cycle_index=cycle, schur_diag=schur, fine_vertices=verts)
+    finally:
+        if saved is None:
+            os.environ.pop("SMG_BLOCK3D_MAX_N", None)
+        else:
+            os.environ["SMG_BLOCK3D_MAX_N"] = saved
     _cache[key] = (ora, gpu)
     return ora, gpu
 
@@ -214,7 +228,7 @@ def test_cycle(name, cycle):
     assert _rel(x32, ora.cycle(L, x0.copy(), b)) < 1e-4
 
 
-@pytest.mark.parametrize("name", ["2d_k2", "3d_k2", "2d_k3", "3d_k3_pert"])
+@pytest.mark.parametrize("name", ["2d_k2", "3d_k2", "3d_k2_sweep", "2d_k3", "3d_k3_pert"])
 @pytest.mark.parametrize("precision", ["f64", "f32"])
 def test_fgmres_solve(name, precision):
     from paper_2205_15770_amd import StokesMG
