@@ -26,8 +26,9 @@
  * the (k n_x + 1) x (k n_y + 1) [x (k n_z + 1)] node lattice, the pressure on
  * the ((k-1) n_x + 1) x ... lattice, lexicographic with x fastest.  Length
  * N = d * Nv + Np (see smg_sizes).  Every velocity node on the box boundary
- * carries the homogeneous Dirichlet condition: operators act as the identity
- * on those entries and ignore them as inputs of the free rows.
+ * carries a Dirichlet condition, homogeneous for the operators: they act as
+ * the identity on those entries and ignore them as inputs of the free rows
+ * (non-zero boundary values are lifted, smg_lift_dirichlet).
  *
  * Memory: every vector argument is a DEVICE pointer owned by the caller, on
  * the device that was current at smg_create, of the element type `dtype`
@@ -71,8 +72,12 @@ typedef enum { SMG_F64 = 0, SMG_F32 = 1 } smg_dtype;
  *   SMG_SCHUR_D   diag(B diag(A)^-1 B^T)                     (assembled B entries)
  *   SMG_SCHUR_LOC sum_tau diag(B_tau diag(A_tau)^-1 B_tau^T) (cell-local)
  *   SMG_SCHUR_P   diag(M_p)                                  (pressure mass)
+ *   SMG_SCHUR_EXACT diag(B A_hat^-1 B^T), A_hat^-1 = sigma Cheb(A, D_A, k_A):
+ *                 the diagonal the three choices above approximate; built
+ *                 at set-up by probing (about ((k-1)(k_A+3)+1)^d applications
+ *                 of A_hat^-1 per level), for comparisons on small meshes
  * With c_pressure != 0 the diagonal of C = c_pressure M_p is added.        */
-typedef enum { SMG_SCHUR_D = 0, SMG_SCHUR_LOC = 1, SMG_SCHUR_P = 2 } smg_schur_diag;
+typedef enum { SMG_SCHUR_D = 0, SMG_SCHUR_LOC = 1, SMG_SCHUR_P = 2, SMG_SCHUR_EXACT = 3 } smg_schur_diag;
 
 /* Blocks of K = [A B^T; B -C] for smg_apply_block (Sec. 1, saddle-point
  * system; Sec. 2, forms a and b):
@@ -156,6 +161,24 @@ smg_status smg_residual(smg_ctx *ctx, int level, int dtype, const void *x, const
 
 /* One block of K (see smg_block).  x and y distinct. */
 smg_status smg_apply_block(smg_ctx *ctx, int level, int dtype, int block, const void *x, void *y);
+
+/* Non-homogeneous Dirichlet data (Sec. 2: u = u_D on the boundary; the
+ * paper's driven-cavity examples) by lifting.  u_d is a velocity vector of
+ * length d*Nv whose entries on the Dirichlet nodes (every node on the box
+ * boundary) are the prescribed values; its other entries are not used.
+ * smg_lift_dirichlet updates the right-hand side b (length N) in place:
+ *   b_u <- b_u - (A u~ + 0) on free rows,  b_u <- 0 on Dirichlet rows,
+ *   b_p <- b_p - B u~,
+ * where u~ = u_d on the Dirichlet nodes, 0 elsewhere, and A, B keep their
+ * Dirichlet columns (the operator before constraints).  The solution x0 of
+ * K x0 = b (homogeneous on the boundary, e.g. by smg_solve) then gives the
+ * solution of the problem with data u_D as x0 + u~, which
+ * smg_insert_dirichlet forms by writing u_d into the Dirichlet entries of x.
+ * b (resp. x) and u_d must be distinct device arrays of the level's dtype.
+ * Uses the level's internal work vectors (not concurrently with a solve on
+ * the same handle).  Errors: EINVAL (level, dtype, NULL or aliasing). */
+smg_status smg_lift_dirichlet(smg_ctx *ctx, int level, int dtype, const void *u_d, void *b);
+smg_status smg_insert_dirichlet(smg_ctx *ctx, int level, int dtype, const void *u_d, void *x);
 
 /* Copy the FP64 diagonal D_A (which = 0, length d*Nv; 1 on Dirichlet rows) or
  * D~_S (which = 1, length Np) of level l into the device array out. */

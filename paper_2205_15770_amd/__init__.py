@@ -13,12 +13,12 @@ import numpy as np
 
 from . import _lib
 from ._lib import (SMG_F64, SMG_F32, SMG_BLOCK_K, SMG_BLOCK_A, SMG_BLOCK_BT, SMG_BLOCK_B,
-                   SMG_BLOCK_MASS, SMG_BLOCK_MP, SMG_SCHUR_D, SMG_SCHUR_LOC, SMG_SCHUR_P, SmgError)
+                   SMG_BLOCK_MASS, SMG_BLOCK_MP, SMG_SCHUR_D, SMG_SCHUR_LOC, SMG_SCHUR_P, SMG_SCHUR_EXACT, SmgError)
 
 __all__ = ["StokesMG", "StokesBatch", "SmgError", "SMG_BLOCK_K", "SMG_BLOCK_A", "SMG_BLOCK_BT", "SMG_BLOCK_B",
            "SMG_BLOCK_MASS", "SMG_BLOCK_MP"]
 
-_SCHUR = {"d": SMG_SCHUR_D, "loc": SMG_SCHUR_LOC, "p": SMG_SCHUR_P}
+_SCHUR = {"d": SMG_SCHUR_D, "loc": SMG_SCHUR_LOC, "p": SMG_SCHUR_P, "exact": SMG_SCHUR_EXACT}
 
 
 def _dtype_code(t):
@@ -137,6 +137,27 @@ class StokesMG:
         self._check(y, n_out, "y")
         _lib.check(self.lib.smg_apply_block(self._h, level, _dtype_code(x), block, _ptr(x), _ptr(y)))
         return y
+
+    def lift_dirichlet(self, level, u_d, b):
+        """b <- b - K u~ on free rows, 0 on Dirichlet rows (u~ = u_d on the
+        boundary nodes, 0 elsewhere); b updated in place and returned."""
+        nu, np_ = self.sizes(level)
+        self._check(u_d, nu, "u_d")
+        self._check(b, nu + np_, "b")
+        if u_d.dtype != b.dtype:
+            raise ValueError("u_d and b must have the same dtype")
+        _lib.check(self.lib.smg_lift_dirichlet(self._h, level, _dtype_code(b), _ptr(u_d), _ptr(b)))
+        return b
+
+    def insert_dirichlet(self, level, u_d, x):
+        """x_D <- u_d on the Dirichlet velocity entries; x updated in place."""
+        nu, np_ = self.sizes(level)
+        self._check(u_d, nu, "u_d")
+        self._check(x, nu + np_, "x")
+        if u_d.dtype != x.dtype:
+            raise ValueError("u_d and x must have the same dtype")
+        _lib.check(self.lib.smg_insert_dirichlet(self._h, level, _dtype_code(x), _ptr(u_d), _ptr(x)))
+        return x
 
     def diagonal(self, level, which):
         import torch

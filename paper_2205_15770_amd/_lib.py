@@ -11,7 +11,7 @@ LIB_PATH = os.path.join(HERE, "libsmg.so")
 
 SMG_OK, SMG_EINVAL, SMG_ENOMEM, SMG_EDEVICE, SMG_ENOTCONV, SMG_EBREAKDOWN, SMG_EUNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
 SMG_F64, SMG_F32 = 0, 1
-SMG_SCHUR_D, SMG_SCHUR_LOC, SMG_SCHUR_P = 0, 1, 2
+SMG_SCHUR_D, SMG_SCHUR_LOC, SMG_SCHUR_P, SMG_SCHUR_EXACT = 0, 1, 2, 3
 SMG_BLOCK_K, SMG_BLOCK_A, SMG_BLOCK_BT, SMG_BLOCK_B, SMG_BLOCK_MASS, SMG_BLOCK_MP = 0, 1, 2, 3, 4, 5
 SMG_PRECOND_F64, SMG_PRECOND_F32 = 0, 1
 
@@ -19,7 +19,7 @@ STATUS_NAMES = {0: "SMG_OK", -1: "SMG_EINVAL", -2: "SMG_ENOMEM", -3: "SMG_EDEVIC
                 -4: "SMG_ENOTCONV", -5: "SMG_EBREAKDOWN", -6: "SMG_EUNSUPPORTED"}
 
 EXPORTS = ["smg_desc_default", "smg_create", "smg_destroy", "smg_sizes", "smg_set_stream",
-           "smg_vmult", "smg_residual", "smg_apply_block", "smg_get_diagonal", "smg_get_eigs",
+           "smg_vmult", "smg_residual", "smg_apply_block", "smg_lift_dirichlet", "smg_insert_dirichlet", "smg_get_diagonal", "smg_get_eigs",
            "smg_set_eigs", "smg_chebyshev", "smg_smooth", "smg_restrict", "smg_prolongate_add",
            "smg_coarse_solve", "smg_vcycle", "smg_solve", "smg_solve_stationary", "smg_batch_solve",
            "smg_batch_autotune",
@@ -75,6 +75,8 @@ def load(path=LIB_PATH):
         "smg_vmult": (I, [P, I, I, P, P]),
         "smg_residual": (I, [P, I, I, P, P, P]),
         "smg_apply_block": (I, [P, I, I, I, P, P]),
+        "smg_lift_dirichlet": (I, [P, I, I, P, P]),
+        "smg_insert_dirichlet": (I, [P, I, I, P, P]),
         "smg_get_diagonal": (I, [P, I, I, P]),
         "smg_get_eigs": (I, [P, I, dp, dp]),
         "smg_set_eigs": (I, [P, I, D, D]),

@@ -65,6 +65,8 @@ class EngineBase {
   virtual void vmult(int l, int dt, const void *x, void *y) = 0;
   virtual void residual(int l, int dt, const void *x, const void *b, void *r) = 0;
   virtual void apply_block(int l, int dt, int blk, const void *x, void *y) = 0;
+  virtual void lift_dirichlet(int l, int dt, const void *ud, void *b) = 0;
+  virtual void insert_dirichlet(int l, int dt, const void *ud, void *x) = 0;
   virtual void chebyshev(int l, int dt, int which, const void *r, void *out) = 0;
   virtual void smooth(int l, int dt, void *x, const void *b, int steps) = 0;
   virtual void restrict_(int lf, int dt, const void *rf, void *rc) = 0;

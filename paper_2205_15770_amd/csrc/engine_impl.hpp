@@ -429,6 +429,42 @@ class EngineT : public EngineBase {
     }
   }
 
+  // D_S~ = diag(B A_hat^-1 B^T) (+ c_p diag(M_p)), A_hat^-1 = sigma Cheb(A, D_A, k_A)
+  // (Sec. 3.3.1, the diagonal the cheaper choices approximate), by probing:
+  // B^T e_j lives on the cells around pressure node j, each of the k_A
+  // applications of A inside Cheb widens that by one cell layer, and B e_i
+  // reads the cells around node i; pressure nodes of one class are
+  // (k - 1)(k_A + 3) + 1 lattice steps apart in some direction, which is more
+  // than that reach, so the probe returns the diagonal entry on its class.
+  // Needs D_A, beta_A and the level's FP64 work vectors.
+  void exact_schur_diagonal(int l) {
+    LevelInfo &I = lv[l];
+    Work<double> &W = work<double>(l);
+    auto g = geom<double>(l);
+    auto gu = geom<double>(l, true);
+    double *e = lz[0], *s = lz[2], *mpe = lz[3];
+    const int mp = (K - 1) * (desc.cheb_deg_A + 3) + 1;
+    const int ncp = DIM == 3 ? mp * mp * mp : mp * mp;
+    for (int col = 0; col < ncp; ++col) {
+      const int c0 = col % mp, c1 = (col / mp) % mp, c2 = DIM == 3 ? col / (mp * mp) : 0;
+      hipLaunchKernelGGL((k_probe_fill<DIM>), dim3(grid_for(I.N)), dim3(VB), 0, stream, e, I.Nv, I.Np, 1, mp, c0, c1,
+                         c2, I.vd[0], I.vd[1], I.pd[0], I.pd[1]);
+      check_launch();
+      const double *ep = e + I.Nu;
+      tile<double, BLK_C | BLK_CPLUS>(gu, OpApply<double>{nullptr, ep, nullptr, mpe});
+      tile<double, BLK_BT>(g, OpApply<double>{nullptr, ep, W.q, nullptr});
+      cheb_A<double>(l, W.q, nullptr, W.w, sigma);
+      tile<double, BLK_B>(g, OpApply<double>{W.w, nullptr, nullptr, s});
+      hipLaunchKernelGGL((k_probe_take<DIM>), dim3(grid_for(I.Np)), dim3(VB), 0, stream, I.DS, (const double *)s,
+                         (const double *)mpe, desc.c_pressure, I.Np, 1, mp, c0, c1, c2, I.pd[0], I.pd[1]);
+      check_launch();
+    }
+    hipLaunchKernelGGL((k_reciprocal<double>), dim3(grid_for(I.Np)), dim3(VB), 0, stream, W.dinvS, (const double *)I.DS, (i64)I.Np);
+    check_launch();
+    hipLaunchKernelGGL((k_reciprocal<float>), dim3(grid_for(I.Np)), dim3(VB), 0, stream, work<float>(l).dinvS, (const double *)I.DS, (i64)I.Np);
+    check_launch();
+  }
+
   bool has_c() const { return desc.c_pressure != 0.0; }
 
   template <typename T>
@@ -453,6 +489,29 @@ class EngineT : public EngineBase {
     OpResidual<T> op{x, x + nu, b, b + nu, r, r + nu};
     if (has_c()) tile<T, BLK_A | BLK_BT | BLK_B | BLK_C>(g, op);
     else tile<T, BLK_A | BLK_BT | BLK_B>(g, op);
+  }
+
+  // Non-homogeneous Dirichlet data by lifting: b <- b - K u~ (Dirichlet
+  // columns kept, u~ = u_d on the Dirichlet nodes, 0 elsewhere), Dirichlet
+  // rows of b set to 0; the solution of K x0 = b plus u~ solves the problem
+  // with x = u_d on the boundary.
+  template <typename T>
+  void lift_t(int l, const T *ud, T *b) {
+    const LevelInfo &I = lv[l];
+    Work<T> &W = work<T>(l);
+    hipLaunchKernelGGL((k_dirichlet_values<T, DIM>), dim3(grid_for(I.Nu)), dim3(VB), 0, stream, ud, W.ru, (i64)I.Nv,
+                       I.vd[0], I.vd[1], I.vd[2], 0);
+    check_launch();
+    auto g = geom<T>(l);
+    tile<T, BLK_A | BLK_B>(g, OpLift<T>{W.ru, b, b + I.Nu, b, b + I.Nu});
+  }
+
+  template <typename T>
+  void insert_dirichlet_t(int l, const T *ud, T *x) {
+    const LevelInfo &I = lv[l];
+    hipLaunchKernelGGL((k_dirichlet_values<T, DIM>), dim3(grid_for(I.Nu)), dim3(VB), 0, stream, ud, x, (i64)I.Nv,
+                       I.vd[0], I.vd[1], I.vd[2], 1);
+    check_launch();
   }
 
   template <typename T>
@@ -1057,7 +1116,8 @@ class EngineT : public EngineBase {
       } else {
         hipLaunchKernelGGL((k_diag_A<DIM, K>), dim3(grid_for(I.Nv)), dim3(VB), 0, stream, g, I.DA);
         check_launch();
-        const int kind = desc.schur_diag == SMG_SCHUR_D ? 0 : (desc.schur_diag == SMG_SCHUR_LOC ? 1 : 2);
+        // (the exact diagonal starts as the _d one and is replaced below)
+        const int kind = desc.schur_diag == SMG_SCHUR_LOC ? 1 : (desc.schur_diag == SMG_SCHUR_P ? 2 : 0);
         hipLaunchKernelGGL((k_diag_S<DIM, K>), dim3(grid_for(I.Np)), dim3(VB), 0, stream, g, kind, (const double *)I.DA, I.DS);
         check_launch();
       }
@@ -1076,6 +1136,7 @@ class EngineT : public EngineBase {
     // Chebyshev intervals (Algorithm 2); level 0 is solved directly
     for (int l = 1; l <= L; ++l) {
       lv[l].beta_A = lanczos(l, 0);
+      if (desc.schur_diag == SMG_SCHUR_EXACT) exact_schur_diagonal(l);
       lv[l].beta_S = lanczos(l, 1);
     }
     build_coarse();
@@ -1106,6 +1167,13 @@ class EngineT : public EngineBase {
   }
   void apply_block(int l, int dt, int blk, const void *x, void *y) override {
     SMG_DISPATCH(dt, block_t<double>(l, blk, (const double *)x, (double *)y), block_t<float>(l, blk, (const float *)x, (float *)y));
+  }
+  void lift_dirichlet(int l, int dt, const void *ud, void *b) override {
+    SMG_DISPATCH(dt, lift_t<double>(l, (const double *)ud, (double *)b), lift_t<float>(l, (const float *)ud, (float *)b));
+  }
+  void insert_dirichlet(int l, int dt, const void *ud, void *x) override {
+    SMG_DISPATCH(dt, insert_dirichlet_t<double>(l, (const double *)ud, (double *)x),
+                 insert_dirichlet_t<float>(l, (const float *)ud, (float *)x));
   }
   void chebyshev(int l, int dt, int which, const void *r, void *out) override {
     if (which == 0)

@@ -237,6 +237,37 @@ struct OpChebS {
   }
 };
 
+// Lifting of non-homogeneous Dirichlet data: with t = K u~ for the operator
+// with its Dirichlet columns kept (ZERO_BC off) and u~ the Dirichlet values
+// extended by zero,
+//   b_u <- b_u - t_u on free rows and 0 on Dirichlet rows,  b_p <- b_p - t_p.
+// b may be updated in place (each entry is read and written by one lane).
+template <typename T>
+struct OpLift {
+  static constexpr const char *NAME = "lift";
+  static constexpr int VARIANT = 0;
+  static constexpr bool ZERO_BC = false;
+  const T *ud;          // u~ (zero off the Dirichlet nodes)
+  const T *bu, *bp;
+  T *yu, *yp;
+  struct Pre {
+    T b;
+  };
+  template <class I>
+  __device__ T load_u(I i) const { return at(ud, i); }
+  template <class I>
+  __device__ T load_p(I) const { return 0; }
+  template <class I>
+  __device__ Pre fetch_u(I i) const { return Pre{at(bu, i)}; }
+  template <class I>
+  __device__ Pre fetch_p(I i) const { return Pre{at(bp, i)}; }
+  template <class I>
+  __device__ void store_u(I i, T t, T, bool bc, const Pre &q) const { at(yu, i) = bc ? T(0) : q.b - t; }
+  template <class I>
+  __device__ void store_p(I i, T t, T, const Pre &q) const { at(yp, i) = q.b - t; }
+  double algo_bytes(bool, bool, bool, bool, double nu, double np) const { return sizeof(T) * (3 * nu + 2 * np); }
+};
+
 // r_p = B u - C p - g, the argument of the second Uzawa update.
 template <typename T>
 struct OpDivResidual {

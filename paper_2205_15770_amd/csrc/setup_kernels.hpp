@@ -190,6 +190,23 @@ __global__ void k_probe_take(double *D, const double *y, const double *z, double
   }
 }
 
+// Velocity values on the Dirichlet nodes (every node on the boundary of the
+// box lattice): mode 0 writes out = u_d there and 0 elsewhere, mode 1 writes
+// out = u_d there and leaves the other entries.
+template <typename T, int DIM>
+__global__ void k_dirichlet_values(const T *ud, T *out, i64 Nv, int v0, int v1, int v2, int mode) {
+  SMG_GRID_LOOP(i, (i64)DIM * Nv) {
+    const i64 node = i % Nv;
+    const int x = (int)(node % v0);
+    const i64 r = node / v0;
+    const int y = (int)(r % v1);
+    const int z = (int)(r / v1);
+    const bool bc = x == 0 || x == v0 - 1 || y == 0 || y == v1 - 1 || (DIM == 3 && (z == 0 || z == v2 - 1));
+    if (bc) out[i] = ud[i];
+    else if (mode == 0) out[i] = T(0);
+  }
+}
+
 template <typename T>
 __global__ void k_div_by(T *q, const double *d, i64 n) {
   SMG_GRID_LOOP(i, n) q[i] = (T)((double)q[i] / d[i]);

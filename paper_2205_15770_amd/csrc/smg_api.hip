@@ -114,7 +114,7 @@ smg_status validate(const smg_desc *d) {
     return fail(SMG_EINVAL, "Chebyshev degrees must be in [0, 16]");
   if (d->smooth_steps < 1 || d->smooth_steps > 64) return fail(SMG_EINVAL, "smooth_steps must be in [1, 64]");
   if (d->cycle_index < 1 || d->cycle_index > 2) return fail(SMG_EINVAL, "cycle_index must be 1 (V) or 2 (W)");
-  if (d->schur_diag < 0 || d->schur_diag > 2) return fail(SMG_EINVAL, "schur_diag must be 0, 1 or 2");
+  if (d->schur_diag < 0 || d->schur_diag > 3) return fail(SMG_EINVAL, "schur_diag must be 0, 1, 2 or 3");
   if (d->precision != SMG_PRECOND_F64 && d->precision != SMG_PRECOND_F32) return fail(SMG_EINVAL, "precision must be 0 or 1");
   if (d->fgmres_restart < 1 || d->fgmres_restart > 200) return fail(SMG_EINVAL, "fgmres_restart must be in [1, 200]");
   if (d->fine_vertices && d->schur_diag == SMG_SCHUR_LOC)
@@ -251,6 +251,24 @@ smg_status smg_apply_block(smg_ctx *ctx, int level, int dtype, int block, const 
   if (block < SMG_BLOCK_K || block > SMG_BLOCK_MP) return fail(SMG_EINVAL, "unknown block");
   if (x == y) return fail(SMG_EINVAL, "x and y must be distinct");
   SMG_TRY(ctx->eng->apply_block(level, dtype, block, x, y));
+}
+
+smg_status smg_lift_dirichlet(smg_ctx *ctx, int level, int dtype, const void *u_d, void *b) {
+  smg_status s = check_level(ctx, level);
+  if (s == SMG_OK) s = check_dtype(dtype);
+  if (s == SMG_OK) s = check_ptrs({u_d, b});
+  if (s != SMG_OK) return s;
+  if (u_d == b) return fail(SMG_EINVAL, "u_d and b must be distinct");
+  SMG_TRY(ctx->eng->lift_dirichlet(level, dtype, u_d, b));
+}
+
+smg_status smg_insert_dirichlet(smg_ctx *ctx, int level, int dtype, const void *u_d, void *x) {
+  smg_status s = check_level(ctx, level);
+  if (s == SMG_OK) s = check_dtype(dtype);
+  if (s == SMG_OK) s = check_ptrs({u_d, x});
+  if (s != SMG_OK) return s;
+  if (u_d == x) return fail(SMG_EINVAL, "u_d and x must be distinct");
+  SMG_TRY(ctx->eng->insert_dirichlet(level, dtype, u_d, x));
 }
 
 smg_status smg_get_diagonal(const smg_ctx *ctx, int level, int which, double *out) {

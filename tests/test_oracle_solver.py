@@ -87,6 +87,33 @@ def test_damped_jacobi_case():
     assert np.allclose(out, r / D / beta, rtol=1e-15)
 
 
+@pytest.mark.parametrize("kA", [0, 1, 3])
+def test_exact_schur_diagonal_from_the_spectral_form(kA):
+    """D_S~ = diag(B A_hat^-1 B^T) (+ diag C) of Sec. 3.3.1, with A_hat^-1 =
+    sigma D^-1/2 Q s_k(Lambda) Q^T D^-1/2 built from the eigen-decomposition of
+    D^-1/2 A D^-1/2 and the closed-form residual polynomial of the Chebyshev
+    iteration, against the oracle's probing with unit vectors."""
+    mesh = BoxMesh(2, (3, 4), 2, vertices=si.perturbed_box_vertices((3, 4), dim=2, amplitude=0.15, seed=3),
+                   mu_cell=si.uniform(12, 4, 0.5, 2.0))
+    asm = Assembled(mesh, gamma=2.0, rho=1.0, c_p=0.3)
+    sm = LevelSmoother(asm, k_A=kA, k_S=1, schur="exact")
+    A = asm.A.toarray()
+    dh = 1.0 / np.sqrt(np.diag(A))
+    lam, Q = np.linalg.eigh(dh[:, None] * A * dh[None, :])
+    beta = sm.beta_A
+    alpha = beta / 2
+    T = _cheb_T_closed(kA + 1, (beta + alpha - 2 * lam) / (beta - alpha)) / \
+        _cheb_T_closed(kA + 1, np.array([(beta + alpha) / (beta - alpha)]))[0]
+    Ahat_inv = scaling_constant(kA) * (dh[:, None] * (Q * ((1.0 - T) / lam)) @ Q.T * dh[None, :])
+    B = asm.B.toarray()
+    ref = np.einsum("ij,jk,ik->i", B, Ahat_inv, B) + 0.3 * asm.Mp.diagonal()
+    assert np.allclose(sm.D_S, ref, rtol=1e-10, atol=0)
+    if kA == 0:
+        # damped Jacobi: A_hat^-1 = D_A^-1 / beta_A, so D_S~ = D~_S_d / beta_A on the B part
+        d = schur_diagonal(asm, "d") - 0.3 * asm.Mp.diagonal()
+        assert np.allclose(sm.D_S - 0.3 * asm.Mp.diagonal(), d / beta, rtol=1e-12)
+
+
 def test_splitmix64_published_vector():
     # published SplitMix64 reference outputs for seed 0
     assert [hex(z) for z in splitmix64_u64(0, 3)] == ["0xe220a8397b1dcdaf", "0x6e789e6aa1b965f4", "0x6c45d188009454f"]
