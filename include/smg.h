@@ -96,6 +96,16 @@ typedef enum {
 
 typedef enum { SMG_PRECOND_F64 = 0, SMG_PRECOND_F32 = 1 } smg_precision;
 
+/* Viscous term of the bilinear form a (Sec. 2):
+ *   SMG_FORM_GRAD  a(u,v) = int mu grad u : grad v + gamma rho u.v
+ *   SMG_FORM_EPS   a(u,v) = int mu eps(u) : eps(v) + gamma rho u.v,
+ *                  eps(u) = (grad u + grad u^T) / 2 (as printed, no factor 2);
+ *                  couples the velocity components.  Runs on every mesh
+ *                  through the quadrature-point kernel of vertex-given cells
+ *                  (a box mesh is passed to it as its vertex lattice);
+ *                  SMG_SCHUR_LOC is not available with it.               */
+typedef enum { SMG_FORM_GRAD = 0, SMG_FORM_EPS = 1 } smg_form;
+
 typedef struct {
   int dim;                 /* 2 or 3                                                  */
   int fe_degree;           /* k: velocity Q_k, pressure Q_{k-1}; k = 2 or 3            */
@@ -119,6 +129,7 @@ typedef struct {
   int precision;           /* smg_precision: the multigrid preconditioner in smg_solve */
   int fgmres_restart;      /* Krylov basis size of smg_solve, 1..200                   */
   void *stream;            /* hipStream_t, or NULL                                     */
+  int form;                /* smg_form: the viscous term of the form a (Sec. 2)        */
 } smg_desc;
 
 typedef struct {
@@ -256,8 +267,10 @@ smg_status smg_node_coordinates(const smg_ctx *ctx, int level, double *xyz);
  * K(mu) x = [Z M_v f; 0] (Z zeroes the Dirichlet rows; f a nodal velocity
  * field) and an objective J(x), let lam solve K lam = dJ/dx (K = K^T, so
  * smg_solve with that right-hand side).  K depends on the per-cell viscosity
- * only through mu_tau int_tau grad u : grad v (Sec. 2, form a), hence
- *   g_logmu[tau] = dJ/d log mu_tau = -mu_tau int_tau grad lam_u : grad u,
+ * only through mu_tau int_tau grad u : grad v (Sec. 2, form a; with
+ * SMG_FORM_EPS mu_tau int_tau eps(u) : eps(v)), hence
+ *   g_logmu[tau] = dJ/d log mu_tau = -mu_tau int_tau grad lam_u : grad u
+ *                  (-mu_tau int_tau eps(lam_u) : eps(u) with SMG_FORM_EPS),
  *   g_f          = dJ/df          = M_v Z lam_u   (every velocity node),
  * with the Dirichlet entries of x and lam taken as zero (cell integrals by
  * the operator's quadrature, on box or vertex-given cells).

@@ -5,7 +5,9 @@ b = [Z M_v f; 0] (nodal force field f, Z zeroing the constrained velocity
 rows), is symmetric (K = K^T; the Dirichlet rows and columns are the
 identity).  For an objective J(x) the adjoint state lam solves K lam = dJ/dx
 and, since K depends on the per-cell viscosity only through the first term of
-the form a of Section 2 (mu_tau int_tau grad u : grad v),
+the form a of Section 2 (mu_tau int_tau grad u : grad v, or mu_tau int_tau
+eps(u) : eps(v) for the deformation-rate form, where A_tau^grad below is that
+form's cell matrix at unit viscosity),
 
   dJ/d log mu_tau = - mu_tau  lam_u^T A_tau^grad u     (constrained entries zeroed),
   dJ/df           = M_v^T Z lam_u = M_v (Z lam_u)      (per component, every node),
@@ -19,7 +21,7 @@ import numpy as np
 import scipy.sparse as sp
 import scipy.sparse.linalg as spla
 
-from .assemble import element_matrices
+from .assemble import element_matrices, symmetric_gradient_blocks
 
 
 def bordered_solve(asm, rhs):
@@ -58,13 +60,20 @@ def gradients(asm, x, lam):
     lu = lam[:d * Nv] * free
     mu = mesh.mu(1.0)
     cells = np.arange(mesh.ncell)
-    stiff, _, _, _ = element_matrices(mesh, cells, np.ones(mesh.ncell), 0.0, 1.0)
     vn = mesh.cell_velocity_nodes(cells)
     g_mu = np.zeros(mesh.ncell)
-    for c in range(d):
-        uc = u[c * Nv:(c + 1) * Nv][vn]           # (nc, nv)
-        lc = lu[c * Nv:(c + 1) * Nv][vn]
-        g_mu -= np.einsum("ci,cij,cj->c", lc, stiff, uc)
+    if asm.form == "sym":
+        # the viscous part of the deformation-rate form at unit viscosity
+        blk = symmetric_gradient_blocks(mesh, cells, np.ones(mesh.ncell), 0.0, 1.0)   # (nc, d, nv, d, nv)
+        U = np.stack([u[c * Nv:(c + 1) * Nv][vn] for c in range(d)], axis=1)        # (nc, d, nv)
+        Lm = np.stack([lu[c * Nv:(c + 1) * Nv][vn] for c in range(d)], axis=1)
+        g_mu -= np.einsum("cdi,cdiej,cej->c", Lm, blk, U)
+    else:
+        stiff, _, _, _ = element_matrices(mesh, cells, np.ones(mesh.ncell), 0.0, 1.0)
+        for c in range(d):
+            uc = u[c * Nv:(c + 1) * Nv][vn]           # (nc, nv)
+            lc = lu[c * Nv:(c + 1) * Nv][vn]
+            g_mu -= np.einsum("ci,cij,cj->c", lc, stiff, uc)
     g_mu *= mu
     g_f = np.concatenate([asm.Mv @ lu[c * Nv:(c + 1) * Nv] for c in range(d)])
     return g_mu, g_f

@@ -16,6 +16,12 @@ equation of the mixed problem is -mu Laplace u + grad p = f, i.e. the strong
 form (1)-(2) with the physical pressure, so B = -div is used.  The velocity
 solution does not depend on this choice.
 
+Deformation-rate form (Sec. 2, used in some applications in place of a):
+  a_eps(u,v) = int mu eps(u) : eps(v) + gamma rho u.v,  eps(u) = (grad u + grad u^T) / 2,
+as printed (no factor 2 in front of mu).  For the test function phi_i e_d and
+the trial function phi_j e_c, eps(u):eps(v) = (delta_cd grad phi_i . grad phi_j
++ d_c phi_i d_d phi_j) / 2, so the velocity block couples the components.
+
 Dirichlet reading: every velocity node on the box boundary is constrained;
 the constrained matrix has those rows and columns zeroed and a unit diagonal,
 so K acts as the identity on constrained entries.
@@ -78,6 +84,27 @@ def element_matrices(mesh, cells, mu, gamma, rho):
     return A, B, Mp, mass_v
 
 
+def symmetric_gradient_blocks(mesh, cells, mu, gamma, rho):
+    """Per-cell velocity blocks of a_eps: out[c, d, i, e, j] = a_eps(phi_j e_e, phi_i e_d)
+      = mu/2 (delta_de int grad phi_i . grad phi_j + int d_e phi_i d_d phi_j)
+        + gamma rho delta_de int phi_i phi_j."""
+    cd = CellData(mesh, cells)
+    d = mesh.dim
+    mu = np.asarray(mu, dtype=np.float64)
+    G = np.einsum("ciqa,cjqb,cq->ciajb", cd.grad, cd.grad, cd.JxW)       # int d_a phi_i d_b phi_j
+    stiff = np.einsum("ciaja->cij", G)
+    mass_v = np.einsum("iq,jq,cq->cij", cd.phi, cd.phi, cd.JxW)
+    nc, nv = stiff.shape[0], stiff.shape[1]
+    out = np.zeros((nc, d, nv, d, nv))
+    for dt in range(d):
+        for ct in range(d):
+            blk = 0.5 * G[:, :, ct, :, dt]
+            if dt == ct:
+                blk = blk + 0.5 * stiff
+            out[:, dt, :, ct, :] = mu[:, None, None] * blk + (gamma * rho * mass_v if dt == ct else 0.0)
+    return out
+
+
 class Assembled:
     """The constrained sparse system of one level.
 
@@ -86,7 +113,10 @@ class Assembled:
     matrix), constrained (global indices), plus the per-cell matrices needed by
     the local Schur diagonal."""
 
-    def __init__(self, mesh, mu=1.0, gamma=0.0, rho=1.0, c_p=0.0, chunk=4096, keep_local=True):
+    def __init__(self, mesh, mu=1.0, gamma=0.0, rho=1.0, c_p=0.0, chunk=4096, keep_local=True, form="grad"):
+        if form not in ("grad", "sym"):
+            raise ValueError(form)
+        self.form = form
         d = mesh.dim
         Nv, Np = mesh.n_vnode, mesh.n_pnode
         self.mesh = mesh
@@ -103,11 +133,19 @@ class Assembled:
             vn = mesh.cell_velocity_nodes(cells)                  # (nc, nv)
             pn = mesh.cell_pressure_nodes(cells)                  # (nc, np)
             nv, npl = vn.shape[1], pn.shape[1]
+            if form == "sym":
+                Ablk = symmetric_gradient_blocks(mesh, cells, mu_cell[cells], gamma, rho)   # (nc, d, nv, d, nv)
+                for dt in range(d):          # test component
+                    for ct in range(d):      # trial component
+                        rA.append(np.repeat(vn + dt * Nv, nv, axis=1).ravel())
+                        cA.append(np.tile(vn + ct * Nv, (1, nv)).ravel())
+                        vA.append(Ablk[:, dt, :, ct, :].ravel())
             for comp in range(d):
                 g = vn + comp * Nv
-                rA.append(np.repeat(g, nv, axis=1).ravel())
-                cA.append(np.tile(g, (1, nv)).ravel())
-                vA.append(A_t.ravel())
+                if form == "grad":
+                    rA.append(np.repeat(g, nv, axis=1).ravel())
+                    cA.append(np.tile(g, (1, nv)).ravel())
+                    vA.append(A_t.ravel())
                 rB.append(np.repeat(pn, nv, axis=1).ravel())
                 cB.append(np.tile(g, (1, npl)).ravel())
                 vB.append(B_t[:, :, comp, :].ravel())
@@ -117,7 +155,7 @@ class Assembled:
             rV.append(np.repeat(vn, nv, axis=1).ravel())
             cV.append(np.tile(vn, (1, nv)).ravel())
             vV.append(Mv_t.ravel())
-            if keep_local:
+            if keep_local and form == "grad":
                 local_Adiag.append(np.einsum("cii->ci", A_t))
                 local_B.append(B_t)
         cat = np.concatenate
@@ -138,7 +176,7 @@ class Assembled:
         self.free_u = free
         self.C = (c_p * self.Mp).tocsr()
         self.K = sp.bmat([[self.A, self.B.T], [self.B, -self.C]]).tocsr()
-        if keep_local:
+        if keep_local and form == "grad":
             self.local_Adiag = cat(local_Adiag)                   # (ncell, nv)
             self.local_B = cat(local_B, axis=0)                   # (ncell, np, d, nv)
 

@@ -20,12 +20,12 @@ from .transfer import prolongation
 
 class Multigrid:
     def __init__(self, meshes, mu=1.0, gamma=0.0, rho=1.0, c_p=0.0,
-                 k_A=1, k_S=1, schur="d", smooth_steps=2, cycle_index=1, betas=None):
+                 k_A=1, k_S=1, schur="d", smooth_steps=2, cycle_index=1, betas=None, form="grad"):
         self.meshes = meshes
         self.L = len(meshes) - 1
         self.m = smooth_steps
         self.cycle_index = cycle_index
-        self.levels = [Assembled(me, mu, gamma, rho, c_p) for me in meshes]
+        self.levels = [Assembled(me, mu, gamma, rho, c_p, form=form) for me in meshes]
         self.P = [None] + [prolongation(meshes[l - 1], meshes[l]) for l in range(1, self.L + 1)]
         self.smoothers = [None]
         for l in range(1, self.L + 1):

@@ -170,6 +170,8 @@ def schur_diagonal(asm, kind, smoother=None):
     elif kind == "p":
         D = asm.Mp.diagonal().copy()
     elif kind == "loc":
+        if asm.form != "grad":
+            raise ValueError("the local Schur diagonal is defined here for the gradient form only")
         mesh = asm.mesh
         cells = np.arange(mesh.ncell)
         vn = mesh.cell_velocity_nodes(cells)

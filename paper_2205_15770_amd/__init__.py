@@ -40,7 +40,7 @@ class StokesMG:
     def __init__(self, dim=2, fe_degree=2, n_coarse=(4, 4, 4), n_levels=3, box_lo=(0.0, 0.0, 0.0),
                  box_hi=(1.0, 1.0, 1.0), mu=1.0, mu_cell=None, gamma=0.0, rho=1.0, c_pressure=0.0,
                  cheb_deg_A=1, cheb_deg_S=1, smooth_steps=2, cycle_index=1, schur_diag="d",
-                 precision="f64", fgmres_restart=30, stream=None, fine_vertices=None):
+                 precision="f64", fgmres_restart=30, stream=None, fine_vertices=None, form="grad"):
         import torch
         self.lib = _lib.load()
         d = _lib.SmgDesc()
@@ -66,6 +66,7 @@ class StokesMG:
         d.schur_diag = _SCHUR[schur_diag] if isinstance(schur_diag, str) else int(schur_diag)
         d.precision = {"f64": 0, "f32": 1}[precision] if isinstance(precision, str) else int(precision)
         d.fgmres_restart = int(fgmres_restart)
+        d.form = {"grad": _lib.SMG_FORM_GRAD, "eps": _lib.SMG_FORM_EPS}[form] if isinstance(form, str) else int(form)
         if stream is None:
             stream = torch.cuda.current_stream().cuda_stream
         d.stream = ctypes.c_void_p(stream)

@@ -12,6 +12,7 @@ LIB_PATH = os.path.join(HERE, "libsmg.so")
 SMG_OK, SMG_EINVAL, SMG_ENOMEM, SMG_EDEVICE, SMG_ENOTCONV, SMG_EBREAKDOWN, SMG_EUNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
 SMG_F64, SMG_F32 = 0, 1
 SMG_SCHUR_D, SMG_SCHUR_LOC, SMG_SCHUR_P, SMG_SCHUR_EXACT = 0, 1, 2, 3
+SMG_FORM_GRAD, SMG_FORM_EPS = 0, 1
 SMG_BLOCK_K, SMG_BLOCK_A, SMG_BLOCK_BT, SMG_BLOCK_B, SMG_BLOCK_MASS, SMG_BLOCK_MP = 0, 1, 2, 3, 4, 5
 SMG_PRECOND_F64, SMG_PRECOND_F32 = 0, 1
 
@@ -36,7 +37,7 @@ class SmgDesc(ctypes.Structure):
                 ("cheb_deg_A", ctypes.c_int), ("cheb_deg_S", ctypes.c_int),
                 ("smooth_steps", ctypes.c_int), ("cycle_index", ctypes.c_int),
                 ("schur_diag", ctypes.c_int), ("precision", ctypes.c_int),
-                ("fgmres_restart", ctypes.c_int), ("stream", ctypes.c_void_p)]
+                ("fgmres_restart", ctypes.c_int), ("stream", ctypes.c_void_p), ("form", ctypes.c_int)]
 
 
 class SmgSolveInfo(ctypes.Structure):

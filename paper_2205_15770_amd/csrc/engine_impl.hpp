@@ -295,6 +295,7 @@ class EngineT : public EngineBase {
     gg.cp = g.cp;
     gg.mu_cell = g.mu_cell;
     gg.verts = g.verts;
+    gg.sym = desc.form == SMG_FORM_EPS ? 1 : 0;
     gg.tu = g.gs;
     gg.tp = g.gs + (int64_t)DIM * g.Nv;
     const int64_t n_all = (int64_t)DIM * g.Nv + g.Np;
@@ -359,6 +360,7 @@ class EngineT : public EngineBase {
     gg.mu = g.mu;
     gg.mu_cell = g.mu_cell;
     gg.verts = lv[L].w64.verts;
+    gg.sym = desc.form == SMG_FORM_EPS ? 1 : 0;
     gg.tu = g.gs;
     gg.tp = g.gs + (int64_t)DIM * g.Nv;
     if (g_logmu) {
@@ -391,16 +393,22 @@ class EngineT : public EngineBase {
     double *e = lz[0], *q = lz[1], *s = lz[2], *mpe = lz[3];
     const int mv = K + 1;
     const int ncv = DIM == 3 ? mv * mv * mv : mv * mv;
-    for (int col = 0; col < ncv; ++col) {
-      const int c0 = col % mv, c1 = (col / mv) % mv, c2 = DIM == 3 ? col / (mv * mv) : 0;
-      hipLaunchKernelGGL((k_probe_fill<DIM>), dim3(grid_for(I.N)), dim3(VB), 0, stream, e, I.Nv, I.Np, 0, mv, c0, c1,
-                         c2, I.vd[0], I.vd[1], I.pd[0], I.pd[1]);
-      check_launch();
-      tile<double, BLK_A>(g, OpApply<double>{e, nullptr, q, nullptr});
-      hipLaunchKernelGGL((k_probe_take<DIM>), dim3(grid_for(I.Nu)), dim3(VB), 0, stream, I.DA, (const double *)q,
-                         (const double *)nullptr, 0.0, I.Nv, DIM, mv, c0, c1, c2, I.vd[0], I.vd[1]);
-      check_launch();
-    }
+    // the deformation-rate form couples the components at a node: probe one
+    // component at a time there
+    const bool per_comp = desc.form == SMG_FORM_EPS;
+    for (int comp = 0; comp < (per_comp ? DIM : 1); ++comp)
+      for (int col = 0; col < ncv; ++col) {
+        const int c0 = col % mv, c1 = (col / mv) % mv, c2 = DIM == 3 ? col / (mv * mv) : 0;
+        hipLaunchKernelGGL((k_probe_fill<DIM>), dim3(grid_for(I.N)), dim3(VB), 0, stream, e, I.Nv, I.Np,
+                           per_comp ? 2 + comp : 0, mv, c0, c1, c2, I.vd[0], I.vd[1], I.pd[0], I.pd[1]);
+        check_launch();
+        tile<double, BLK_A>(g, OpApply<double>{e, nullptr, q, nullptr});
+        const int64_t o = per_comp ? comp * I.Nv : 0;
+        hipLaunchKernelGGL((k_probe_take<DIM>), dim3(grid_for(I.Nu)), dim3(VB), 0, stream, I.DA + o,
+                           (const double *)(q + o), (const double *)nullptr, 0.0, I.Nv, per_comp ? 1 : DIM, mv, c0, c1,
+                           c2, I.vd[0], I.vd[1]);
+        check_launch();
+      }
     const int mp = K == 2 ? 3 : 5;
     const int ncp = DIM == 3 ? mp * mp * mp : mp * mp;
     const bool schur_p = desc.schur_diag == SMG_SCHUR_P;
@@ -1076,7 +1084,25 @@ class EngineT : public EngineBase {
     dvec = dalloc<double>(1024);
     // general cells: vertex coordinates of every level (level l takes the
     // finest-level vertex at the same lattice point)
-    if (desc.fine_vertices) {
+    // the deformation-rate form runs on the vertex-given cell kernel: a box
+    // mesh is handed to it as its vertex lattice
+    std::vector<double> lattice;
+    const double *fverts = desc.fine_vertices;
+    if (!fverts && desc.form == SMG_FORM_EPS) {
+      const LevelInfo &F = lv[L];
+      const int nz = DIM == 3 ? F.n[2] + 1 : 1;
+      lattice.resize((size_t)(F.n[0] + 1) * (F.n[1] + 1) * nz * DIM);
+      size_t o = 0;
+      for (int k = 0; k < nz; ++k)
+        for (int j = 0; j <= F.n[1]; ++j)
+          for (int i = 0; i <= F.n[0]; ++i) {
+            const int ijk[3] = {i, j, k};
+            for (int a = 0; a < DIM; ++a)
+              lattice[o++] = desc.box_lo[a] + (desc.box_hi[a] - desc.box_lo[a]) * ijk[a] / (double)F.n[a];
+          }
+      fverts = lattice.data();
+    }
+    if (fverts) {
       general = true;
       hverts.resize(L + 1);
       const LevelInfo &F = lv[L];
@@ -1092,7 +1118,7 @@ class EngineT : public EngineBase {
           for (int j = 0; j <= I.n[1]; ++j)
             for (int i = 0; i <= I.n[0]; ++i) {
               const int64_t fv = (int64_t)i * s + fx * ((int64_t)j * s + fy * (int64_t)k * s);
-              for (int a = 0; a < DIM; ++a) hv[o++] = desc.fine_vertices[fv * DIM + a];
+              for (int a = 0; a < DIM; ++a) hv[o++] = fverts[fv * DIM + a];
             }
         lv[l].w64.verts = dalloc<double>((int64_t)hv.size());
         lv[l].w32.verts = dalloc<float>((int64_t)hv.size());

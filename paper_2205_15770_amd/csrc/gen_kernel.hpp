@@ -6,7 +6,8 @@
 //
 // At each quadrature point: J = sum_v x_v (x) grad N_v, JxW = det J w_q, the
 // physical gradients grad u_c = J^-T grad^ u_c, and the integrands of
-//   a(u, v) = int mu grad u_c . grad v_c + gamma rho u_c v_c,
+//   a(u, v) = int mu grad u_c . grad v_c + gamma rho u_c v_c
+//             (or int mu eps(u) : eps(v) + gamma rho u.v, Sec. 2),
 //   b(v, q) = -int q div v,   (C p, q) = c_p int p q.
 //
 // Work decomposition: one wave64 per 64 / (k+1)^d cells, one lane per node /
@@ -32,6 +33,7 @@ struct GenGeo {
   const T *mu_cell;
   const T *verts;   // (n+1)^d vertices x d coordinates, x fastest
   T *tu, *tp;       // accumulated cell sums (velocity [u_1|..|u_d], pressure)
+  int sym;          // viscous term mu eps(u):eps(v) instead of mu grad u : grad v
 };
 
 // a[i] for a lane-dependent i without dynamic indexing into private memory
@@ -282,7 +284,9 @@ __global__ void __launch_bounds__(64) gen_apply_kernel(const GenGeo<T> g, const 
       T G[3] = {0, 0, 0};
 #pragma unroll
       for (int a = 0; a < DIM; ++a) {
-        if constexpr ((BLK & BLK_A) != 0) G[a] += mu * gphys[c][a];
+        // test function of component c: mu grad u_c, or mu eps(u)_{c.} (eps:eps = eps:grad)
+        if constexpr ((BLK & BLK_A) != 0)
+          G[a] += mu * (g.sym ? T(0.5) * (gphys[c][a] + gphys[a][c]) : gphys[c][a]);
         if constexpr ((BLK & BLK_BT) != 0)
           if (a == c) G[a] -= pq;
       }
@@ -423,6 +427,7 @@ __global__ void gen_epilogue_kernel(const GenGeo<T> g, const Op op) {
 
 // Adjoint-state gradient with respect to the per-cell log-viscosity:
 //   out[tau] = - mu_tau int_tau sum_c grad lam_c . grad u_c
+//   (- mu_tau int_tau eps(lam) : eps(u) for the deformation-rate form)
 // (constrained velocity entries of u and lam taken as zero), every cell of
 // the level in one launch; one lane per quadrature point, LDS passes as in
 // gen_apply_kernel, then a sum over the cell's lanes.  FP64.
@@ -562,15 +567,20 @@ __global__ void __launch_bounds__(64) gen_grad_logmu_kernel(const GenGeo<double>
       gp[a] = s;
     }
   };
-  T acc = 0;
+  T gu[DIM][3], gl[DIM][3];
 #pragma unroll
   for (int c = 0; c < DIM; ++c) {
-    T gu[3], gl[3];
-    grad_at(x, c, gu);
-    grad_at(lam, c, gl);
-#pragma unroll
-    for (int a = 0; a < DIM; ++a) acc += gu[a] * gl[a];
+    grad_at(x, c, gu[c]);
+    grad_at(lam, c, gl[c]);
   }
+  T acc = 0;
+#pragma unroll
+  for (int c = 0; c < DIM; ++c)
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) {
+      if (g.sym) acc += T(0.25) * (gu[c][a] + gu[a][c]) * (gl[c][a] + gl[a][c]);
+      else acc += gu[c][a] * gl[c][a];
+    }
   acc *= JxW;
   if (in_slot) A[q] = acc;
   __syncthreads();

@@ -162,8 +162,9 @@ __device__ __forceinline__ bool in_class(i64 node, int d0, int d1, int m, int c0
   return x % m == c0 && y % m == c1 && (DIM == 2 || z % m == c2);
 }
 
-// e = 1 on the nodes of `field` (0: every velocity component, 1: pressure)
-// whose lattice coordinates are congruent to (c0, c1, c2) modulo m, else 0.
+// e = 1 on the nodes of `field` (0: every velocity component, 1: pressure,
+// 2 + c: velocity component c only) whose lattice coordinates are congruent
+// to (c0, c1, c2) modulo m, else 0.
 template <int DIM>
 __global__ void k_probe_fill(double *e, i64 Nv, i64 Np, int field, int m, int c0, int c1, int c2, int v0, int v1,
                              int p0, int p1) {
@@ -171,7 +172,7 @@ __global__ void k_probe_fill(double *e, i64 Nv, i64 Np, int field, int m, int c0
   SMG_GRID_LOOP(i, nu + Np) {
     bool on = false;
     if (i < nu) {
-      if (field == 0) on = in_class<DIM>(i % Nv, v0, v1, m, c0, c1, c2);
+      if (field == 0 || (field >= 2 && i / Nv == field - 2)) on = in_class<DIM>(i % Nv, v0, v1, m, c0, c1, c2);
     } else if (field == 1) {
       on = in_class<DIM>(i - nu, p0, p1, m, c0, c1, c2);
     }
