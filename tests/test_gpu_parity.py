@@ -353,6 +353,62 @@ def test_full_size_2d_512_sampled_rows(dtype, tol):
     gpu.close()
 
 
+def _sampled_dofs(n, nu, lat_v, extra, seed):
+    rng = np.random.default_rng(seed)
+    return np.unique(np.concatenate([rng.integers(0, n, 400), np.arange(0, 40), np.arange(n - 40, n),
+                                     np.arange(nu - 20, nu + 20), extra]))
+
+
+@pytest.mark.parametrize("dtype,tol", [(torch.float64, 1e-12), (torch.float32, 2e-5)])
+def test_full_size_3d_64_sampled_rows(dtype, tol):
+    """The 64^3 Q2-Q1 workload (6 levels) at full size: sampled rows of K x on
+    the finest level (column-sweep kernel) and on the 32^3 level (cell-block
+    kernel) against the oracle's row-by-row definition."""
+    from paper_2205_15770_amd import StokesMG
+    from oracle.mesh import BoxMesh
+    gpu = StokesMG(dim=3, fe_degree=2, n_coarse=(2, 2, 2), n_levels=6, mu=1.0, gamma=0.0)
+    for L, nc in ((5, 64), (4, 32)):
+        n = gpu.n_total(L)
+        nu, _ = gpu.sizes(L)
+        x = si.uniform(n, 98 + L)
+        y = gpu.vmult(L, _dev(x, dtype)).cpu().numpy().astype(np.float64)
+        mesh = BoxMesh(3, (nc, nc, nc), 2)
+        vd = 2 * nc + 1
+        # nodes on tile and chunk boundaries of both kernels, and on the faces
+        extra = [vd * vd * z + vd * y_ + x_ for (x_, y_, z) in
+                 [(14, 14, 14), (15, 7, 30), (6, 6, 6), (7, 13, 2 * nc - 1), (1, 1, 1), (vd - 2, vd - 2, vd - 2)]]
+        dofs = _sampled_dofs(n, nu, vd, extra + [nu // 3 + e for e in extra], 6 + L)
+        xin = x if dtype == torch.float64 else x.astype(np.float32).astype(np.float64)
+        ref = sample_Kx(mesh, xin, dofs)
+        assert np.linalg.norm(y[dofs] - ref) / np.linalg.norm(ref) < tol, L
+    gpu.close()
+
+
+@pytest.mark.parametrize("dtype,tol", [(torch.float64, 1e-12), (torch.float32, 2e-5)])
+def test_full_size_3d_q3_32_perturbed_sampled_rows(dtype, tol):
+    """The 32^3 Q3-Q2 workload with perturbed vertices (seed 4) and Fourier
+    viscosity in [1, 100] (seed 5), 5 levels, at full size: sampled rows of
+    K x on the finest level (quadrature-point kernel)."""
+    from paper_2205_15770_amd import StokesMG
+    from oracle.mesh import BoxMesh
+    V = si.perturbed_box_vertices(32, dim=3, amplitude=0.2, seed=4)
+    mu = si.fourier_log_viscosity(32, dim=3, seed=5)
+    gpu = StokesMG(dim=3, fe_degree=3, n_coarse=(2, 2, 2), n_levels=5, mu_cell=mu, gamma=0.0, fine_vertices=V)
+    L = 4
+    n = gpu.n_total(L)
+    nu, _ = gpu.sizes(L)
+    x = si.uniform(n, 97)
+    y = gpu.vmult(L, _dev(x, dtype)).cpu().numpy().astype(np.float64)
+    mesh = BoxMesh(3, (32, 32, 32), 3, vertices=V, mu_cell=mu)
+    vd = 97
+    extra = [vd * vd * z + vd * y_ + x_ for (x_, y_, z) in [(3, 3, 3), (4, 50, 61), (95, 95, 95), (48, 1, 2)]]
+    dofs = _sampled_dofs(n, nu, vd, extra, 16)
+    xin = x if dtype == torch.float64 else x.astype(np.float32).astype(np.float64)
+    ref = sample_Kx(mesh, xin, dofs)
+    assert np.linalg.norm(y[dofs] - ref) / np.linalg.norm(ref) < tol
+    gpu.close()
+
+
 @pytest.mark.parametrize("precision", ["f32", "f64"])
 def test_graph_replayed_cycle_matches_eager(precision):
     """The preconditioning cycle inside smg_solve is captured into a HIP graph
