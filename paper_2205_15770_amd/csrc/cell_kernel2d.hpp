@@ -36,18 +36,24 @@ struct Geo2 {
   T sB[2];
 };
 
-template <int K, typename T, int BLK, class Op>
-__global__ void __launch_bounds__(64)
-wave2d_kernel(const Geo2<T> g, const Op op) {
+// One tile; FIELD = -1: every output field of the block, 0 / 1: velocity
+// component 0 / 1 only, 2: pressure only (the split form for small levels,
+// where a wave's instruction count is its latency).
+template <int K, typename T, int BLK, class Op, int FIELD>
+__device__ __forceinline__ void wave2d_tile(const Geo2<T> &g, const Op &op, int b) {
   constexpr int NV = K + 1, NP = K, TX = 8;
   constexpr uint32_t ST = sizeof(T);
   constexpr cfe::TabT<K, T> R = cfe::make_tab_t<K, T>();
-  constexpr bool OUT_U = (BLK & (BLK_A | BLK_MASS | BLK_BT)) != 0;
-  constexpr bool OUT_P = (BLK & (BLK_B | BLK_C)) != 0;
-  constexpr bool NEED_U = (BLK & (BLK_A | BLK_MASS | BLK_B)) != 0;
-  constexpr bool NEED_P = (BLK & (BLK_BT | BLK_C)) != 0;
+  constexpr bool ALL_U = (BLK & (BLK_A | BLK_MASS | BLK_BT)) != 0;
+  constexpr bool OUT_P = (BLK & (BLK_B | BLK_C)) != 0 && (FIELD == -1 || FIELD == 2);
+  // per velocity component: computed here?
+  constexpr bool DU[2] = {ALL_U && (FIELD == -1 || FIELD == 0), ALL_U && (FIELD == -1 || FIELD == 1)};
+  constexpr bool OUT_U = DU[0] || DU[1];
+  // inputs: u_c for A / M of component c and for B; p for B^T and C
+  constexpr bool LU[2] = {(DU[0] && (BLK & (BLK_A | BLK_MASS)) != 0) || (OUT_P && (BLK & BLK_B) != 0),
+                          (DU[1] && (BLK & (BLK_A | BLK_MASS)) != 0) || (OUT_P && (BLK & BLK_B) != 0)};
+  constexpr bool NEED_P = (OUT_U && (BLK & BLK_BT) != 0) || (OUT_P && (BLK & BLK_C) != 0);
 
-  const int b = xcd_contiguous_tile(blockIdx.x, gridDim.x);
   const int tx = b % g.tiles[0], ty = b / g.tiles[0];
   const int lcx = threadIdx.x % TX, lcy = threadIdx.x / TX;
   const int gcx = tx * (TX - 1) - 1 + lcx, gcy = ty * (TX - 1) - 1 + lcy;
@@ -66,13 +72,13 @@ wave2d_kernel(const Geo2<T> g, const Op op) {
 
   // 1. requests: cell DoFs, viscosity, epilogue inputs of the owned nodes
   T u[2][1][NV][NV], p[1][NP][NP];
-  if constexpr (NEED_U) {
 #pragma unroll
-    for (int c = 0; c < 2; ++c)
+  for (int c = 0; c < 2; ++c) {
+    if (!LU[c]) continue;
 #pragma unroll
-      for (int y = 0; y < NV; ++y)
+    for (int y = 0; y < NV; ++y)
 #pragma unroll
-        for (int x = 0; x < NV; ++x) u[c][0][y][x] = op.load_u(u_at(c, x, y));
+      for (int x = 0; x < NV; ++x) u[c][0][y][x] = op.load_u(u_at(c, x, y));
   }
   if constexpr (NEED_P) {
 #pragma unroll
@@ -86,13 +92,13 @@ wave2d_kernel(const Geo2<T> g, const Op op) {
   typename Op::Pre pre_u[2][K][K];
   typename Op::Pre pre_p[K - 1][K - 1];
   if (owner) {
-    if constexpr (OUT_U) {
 #pragma unroll
-      for (int c = 0; c < 2; ++c)
+    for (int c = 0; c < 2; ++c) {
+      if (!DU[c]) continue;
 #pragma unroll
-        for (int y = 0; y < K; ++y)
+      for (int y = 0; y < K; ++y)
 #pragma unroll
-          for (int x = 0; x < K; ++x) pre_u[c][y][x] = op.fetch_u(u_at(c, x, y));
+        for (int x = 0; x < K; ++x) pre_u[c][y][x] = op.fetch_u(u_at(c, x, y));
     }
     if constexpr (OUT_P) {
 #pragma unroll
@@ -106,24 +112,15 @@ wave2d_kernel(const Geo2<T> g, const Op op) {
   __asm__ volatile("" ::: "memory");
 
   // 2. mask: inactive cells, Dirichlet inputs (ZERO_BC)
-  if constexpr (NEED_U) {
 #pragma unroll
-    for (int c = 0; c < 2; ++c)
+  for (int c = 0; c < 2; ++c)
 #pragma unroll
-      for (int y = 0; y < NV; ++y)
+    for (int y = 0; y < NV; ++y)
 #pragma unroll
-        for (int x = 0; x < NV; ++x) {
-          const bool keep = active & !(Op::ZERO_BC & vbc(x, y));
-          u[c][0][y][x] = keep ? u[c][0][y][x] : T(0);
-        }
-  } else {
-#pragma unroll
-    for (int c = 0; c < 2; ++c)
-#pragma unroll
-      for (int y = 0; y < NV; ++y)
-#pragma unroll
-        for (int x = 0; x < NV; ++x) u[c][0][y][x] = 0;
-  }
+      for (int x = 0; x < NV; ++x) {
+        const bool keep = LU[c] & active & !(Op::ZERO_BC & vbc(x, y));
+        u[c][0][y][x] = keep ? u[c][0][y][x] : T(0);
+      }
   if constexpr (NEED_P) {
 #pragma unroll
     for (int y = 0; y < NP; ++y)
@@ -148,6 +145,7 @@ wave2d_kernel(const Geo2<T> g, const Op op) {
     const T sy = mu * g.sKy;
 #pragma unroll
     for (int c = 0; c < 2; ++c) {
+      if (!DU[c]) continue;
       T t[1][NV][NV];
       pass_y<false, false>(R.Mr, u[c], t, T(1));
       pass_x<false, false>(X, t, yu[c], T(1));
@@ -157,6 +155,7 @@ wave2d_kernel(const Geo2<T> g, const Op op) {
   } else if constexpr ((BLK & BLK_MASS) != 0) {
 #pragma unroll
     for (int c = 0; c < 2; ++c) {
+      if (!DU[c]) continue;
       T t[1][NV][NV];
       pass_y<false, false>(R.Mr, u[c], t, T(1));
       pass_x<false, false>(R.Mr, t, yu[c], g.sM);
@@ -164,13 +163,17 @@ wave2d_kernel(const Geo2<T> g, const Op op) {
   }
   if constexpr ((BLK & BLK_BT) != 0) {
     constexpr bool ACC = (BLK & (BLK_A | BLK_MASS)) != 0;
-    T s[1][NV][NP];
-    pass_y<true, false>(R.Nr, p, s, T(1));
-    pass_x<true, ACC>(R.Gr, s, yu[0], -g.sB[0]);
-    T s2[1][NP][NV];
-    pass_x<true, false>(R.Nr, p, s2, T(1));
-    pass_y<true, ACC>(R.Gr, s2, yu[1], -g.sB[1]);
-  } else if constexpr (!OUT_U) {
+    if constexpr (DU[0]) {
+      T s[1][NV][NP];
+      pass_y<true, false>(R.Nr, p, s, T(1));
+      pass_x<true, ACC>(R.Gr, s, yu[0], -g.sB[0]);
+    }
+    if constexpr (DU[1]) {
+      T s2[1][NP][NV];
+      pass_x<true, false>(R.Nr, p, s2, T(1));
+      pass_y<true, ACC>(R.Gr, s2, yu[1], -g.sB[1]);
+    }
+  } else if constexpr (!ALL_U) {
 #pragma unroll
     for (int c = 0; c < 2; ++c)
 #pragma unroll
@@ -196,25 +199,27 @@ wave2d_kernel(const Geo2<T> g, const Op op) {
   }
 
   // 4. hand-over to the right (lane + 1) and upper (lane + 8) neighbours
-  if constexpr (OUT_U) {
 #pragma unroll
-    for (int c = 0; c < 2; ++c) hand_over_xy<TX>(yu[c], lcx, lcy, bxh, byh);
-  }
+  for (int c = 0; c < 2; ++c)
+    if (DU[c]) hand_over_xy<TX>(yu[c], lcx, lcy, bxh, byh);
   if constexpr (OUT_P) hand_over_xy<TX>(yp, lcx, lcy, bxh, byh);
 
   // 5. owned nodes
   if (!owner) return;
   if constexpr (OUT_U) {
 #pragma unroll
-    for (int c = 0; c < 2; ++c)
+    for (int c = 0; c < 2; ++c) {
+      if (!DU[c]) continue;
 #pragma unroll
       for (int y = 0; y < K; ++y)
 #pragma unroll
         for (int x = 0; x < K; ++x) op.store_u(u_at(c, x, y), yu[c][0][y][x], u[c][0][y][x], false, pre_u[c][y][x]);
+    }
     if (bxl | byl) {
       // Dirichlet rows on the low faces (rewritten: same lane, program order)
 #pragma unroll
       for (int c = 0; c < 2; ++c)
+        if (DU[c])
 #pragma unroll
         for (int y = 0; y < K; ++y)
 #pragma unroll
@@ -230,6 +235,7 @@ wave2d_kernel(const Geo2<T> g, const Op op) {
       // nodes on the domain's high faces: Dirichlet rows
 #pragma unroll
       for (int c = 0; c < 2; ++c)
+        if (DU[c])
 #pragma unroll
         for (int y = 0; y < NV; ++y)
 #pragma unroll
@@ -257,6 +263,29 @@ wave2d_kernel(const Geo2<T> g, const Op op) {
         }
       }
   }
+}
+
+template <int K, typename T, int BLK, class Op>
+__global__ void __launch_bounds__(64)
+wave2d_kernel(const Geo2<T> g, const Op op) {
+  wave2d_tile<K, T, BLK, Op, -1>(g, op, xcd_contiguous_tile(blockIdx.x, gridDim.x));
+}
+
+// Split form: one wave per (tile, output field); the fields of a tile are
+// consecutive blocks (same XCD).
+template <int K, typename T, int BLK, class Op>
+__global__ void __launch_bounds__(64)
+wave2d_split_kernel(const Geo2<T> g, const Op op) {
+  constexpr bool OUT_U = (BLK & (BLK_A | BLK_MASS | BLK_BT)) != 0;
+  constexpr bool OUT_P = (BLK & (BLK_B | BLK_C)) != 0;
+  constexpr int NF = (OUT_U ? 2 : 0) + (OUT_P ? 1 : 0);
+  const int bb = xcd_contiguous_tile(blockIdx.x, gridDim.x);
+  const int f = bb % NF, b = bb / NF;
+  if constexpr (OUT_U) {
+    if (f == 0) { wave2d_tile<K, T, BLK, Op, 0>(g, op, b); return; }
+    if (f == 1) { wave2d_tile<K, T, BLK, Op, 1>(g, op, b); return; }
+  }
+  if constexpr (OUT_P) wave2d_tile<K, T, BLK, Op, 2>(g, op, b);
 }
 
 }  // namespace smg

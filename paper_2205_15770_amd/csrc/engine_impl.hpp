@@ -26,6 +26,15 @@ inline int block3d_max_n_from_env() {
   return e != nullptr ? std::atoi(e) : 32;
 }
 
+// Largest 2D level (cells per direction) whose operator launches with a
+// pressure output use one wave per (tile, output field) instead of one wave
+// per tile for all fields (launches with velocity outputs only always do);
+// SMG_SPLIT2D_MAX_N overrides it (0: one wave per tile everywhere).
+inline int split2d_max_n_from_env() {
+  const char *e = std::getenv("SMG_SPLIT2D_MAX_N");
+  return e != nullptr ? std::atoi(e) : 256;
+}
+
 // Lanczos (Algorithm 2 asks for a close approximation of lambda_max): steps,
 // safety factor and SplitMix64 seeds of the start vectors.
 constexpr int LANCZOS_STEPS = 30;
@@ -68,6 +77,7 @@ class EngineT : public EngineBase {
   TransferTables ttab;
   bool general = false;                      // cells given by vertices
   int block3d_max_n = block3d_max_n_from_env();
+  int split2d_max_n = split2d_max_n_from_env();
   std::vector<std::vector<double>> hverts;   // per level, host copy (node coordinates)
   double *Kinv = nullptr;
   int n0 = 0;
@@ -214,7 +224,16 @@ class EngineT : public EngineBase {
       g2.sB[0] = (T)hy;
       g2.sB[1] = (T)hx;
       const unsigned nb2 = (unsigned)(g2.tiles[0] * g2.tiles[1]);
-      hipLaunchKernelGGL((wave2d_kernel<K, T, BLK, Op>), dim3(nb2), dim3(64), 0, stream, g2, op);
+      constexpr unsigned NF2 = ((BLK & (BLK_A | BLK_MASS | BLK_BT)) ? 2 : 0) + ((BLK & (BLK_B | BLK_C)) ? 1 : 0);
+      constexpr bool VEL_ONLY = (BLK & (BLK_B | BLK_C)) == 0;
+      if (NF2 > 1 && split2d_max_n > 0 && (VEL_ONLY || std::max(g.n[0], g.n[1]) <= split2d_max_n)) {
+        // one wave per (tile, output field): fewer instructions per wave.
+        // Blocks with only velocity outputs read nothing twice this way; the
+        // others read p (and u) once per field, which pays on small levels.
+        hipLaunchKernelGGL((wave2d_split_kernel<K, T, BLK, Op>), dim3(nb2 * NF2), dim3(64), 0, stream, g2, op);
+      } else {
+        hipLaunchKernelGGL((wave2d_kernel<K, T, BLK, Op>), dim3(nb2), dim3(64), 0, stream, g2, op);
+      }
     } else if constexpr (K != 2) {
       // Q3-Q2 in 3D: colour-phase tile kernel (the column sweep is built for
       // Q2-Q1 only; its Q3 variants spill to scratch and are switched off)

@@ -23,7 +23,8 @@ CASES = {
     "2d_k2": dict(dim=2, k=2, n_coarse=(5, 3), levels=3),
     "2d_k3": dict(dim=2, k=3, n_coarse=(3, 2), levels=3),
     "3d_k2": dict(dim=3, k=2, n_coarse=(2, 3, 2), levels=3),
-    "3d_k2_sweep": dict(dim=3, k=2, n_coarse=(2, 3, 2), levels=3, sweep=True),
+    "2d_k2_fused": dict(dim=2, k=2, n_coarse=(5, 3), levels=3, env={"SMG_SPLIT2D_MAX_N": "0"}),
+    "3d_k2_sweep": dict(dim=3, k=2, n_coarse=(2, 3, 2), levels=3, env={"SMG_BLOCK3D_MAX_N": "0"}),
     "3d_k3": dict(dim=3, k=3, n_coarse=(2, 2, 3), levels=2),
     "2d_k2_pert": dict(dim=2, k=2, n_coarse=(3, 2), levels=3, pert=True),
     "3d_k3_pert": dict(dim=3, k=3, n_coarse=(2, 2, 2), levels=2, pert=True),
@@ -47,8 +48,8 @@ def _pair(name, monkeypatch):
     n_f = [v * 2 ** (L - 1) for v in c["n_coarse"]]
     mu_cell = si.uniform(int(np.prod(n_f)), 23, 0.5, 3.0)
     V = si.perturbed_box_vertices(n_f, dim=dim, amplitude=0.2, seed=29) if c.get("pert") else None
-    if c.get("sweep"):
-        monkeypatch.setenv("SMG_BLOCK3D_MAX_N", "0")
+    for k_, v_ in c.get("env", {}).items():
+        monkeypatch.setenv(k_, v_)
     gpu = StokesMG(dim=dim, fe_degree=k, n_coarse=c["n_coarse"], n_levels=L, mu_cell=mu_cell, gamma=GAMMA,
                    rho=RHO, c_pressure=CP, fine_vertices=V)
     mesh = make_hierarchy(dim, c["n_coarse"], L, k, fine_mu=mu_cell, fine_vertices=V)[-1]

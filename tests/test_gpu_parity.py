@@ -10,6 +10,7 @@ tiles 3 x 3 x 3 (k = 2) / 2 x 2 x 2 (k = 3) cells).  Tolerances:
     maps composed; rounding differences grow by the iteration's norm);
   * FP32: <= 2e-5 relative (single-precision roundings, same count).
 """
+import contextlib
 import os
 
 import numpy as np
@@ -31,7 +32,11 @@ CONFIGS = {
     "3d_k2": dict(dim=3, k=2, n_coarse=(2, 3, 2), levels=3),
     # the same levels through the column-sweep kernel (by default levels of at
     # most 32 cells per direction take the one-cell-per-lane block kernel)
-    "3d_k2_sweep": dict(dim=3, k=2, n_coarse=(2, 3, 2), levels=3, sweep=True),
+    "3d_k2_sweep": dict(dim=3, k=2, n_coarse=(2, 3, 2), levels=3, env={"SMG_BLOCK3D_MAX_N": "0"}),
+    # 2D levels of at most 128 cells per direction take one wave per output
+    # field by default; the same levels with one wave for all fields:
+    "2d_k2_fused": dict(dim=2, k=2, n_coarse=(5, 3), levels=4, env={"SMG_SPLIT2D_MAX_N": "0"}),
+    "2d_k3_fused": dict(dim=2, k=3, n_coarse=(3, 2), levels=4, env={"SMG_SPLIT2D_MAX_N": "0"}),
     "3d_k3": dict(dim=3, k=3, n_coarse=(2, 2, 3), levels=2),
     # vertex-given (multilinear) cells: interior vertices of the finest mesh
     # moved by up to 0.2 h, coarse levels take the finest vertices
@@ -57,20 +62,28 @@ def _setup(name, c_p=0.0, kA=1, kS=1, schur="d", m=2, cycle=1, percell=True):
     meshes = make_hierarchy(dim, cfg["n_coarse"], L, k, fine_mu=mu_cell, fine_vertices=verts)
     ora = Multigrid(meshes, mu=1.0, gamma=PHYS["gamma"], rho=PHYS["rho"], c_p=c_p, k_A=kA, k_S=kS,
                     schur=schur, smooth_steps=m, cycle_index=cycle)
-    saved = os.environ.get("SMG_BLOCK3D_MAX_N")
-    if cfg.get("sweep"):
-        os.environ["SMG_BLOCK3D_MAX_N"] = "0"
-    try:
+    with _env(cfg):
         gpu = StokesMG(dim=dim, fe_degree=k, n_coarse=cfg["n_coarse"], n_levels=L, mu=1.0, mu_cell=mu_cell,
                        gamma=PHYS["gamma"], rho=PHYS["rho"], c_pressure=c_p, cheb_deg_A=kA, cheb_deg_S=kS,
                        smooth_steps=m, cycle_index=cycle, schur_diag=schur, fine_vertices=verts)
-    finally:
-        if saved is None:
-            os.environ.pop("SMG_BLOCK3D_MAX_N", None)
-        else:
-            os.environ["SMG_BLOCK3D_MAX_N"] = saved
     _cache[key] = (ora, gpu)
     return ora, gpu
+
+
+@contextlib.contextmanager
+def _env(cfg):
+    """Kernel-choice variables (read when a solver is set up) of a config."""
+    env = cfg.get("env", {})
+    saved = {k: os.environ.get(k) for k in env}
+    os.environ.update(env)
+    try:
+        yield
+    finally:
+        for k, v in saved.items():
+            if v is None:
+                os.environ.pop(k, None)
+            else:
+                os.environ[k] = v
 
 
 def _vertices(name):
@@ -231,7 +244,7 @@ def test_cycle(name, cycle):
     assert _rel(x32, ora.cycle(L, x0.copy(), b)) < 1e-4
 
 
-@pytest.mark.parametrize("name", ["2d_k2", "3d_k2", "3d_k2_sweep", "2d_k3", "3d_k3_pert"])
+@pytest.mark.parametrize("name", ["2d_k2", "2d_k2_fused", "3d_k2", "3d_k2_sweep", "2d_k3", "3d_k3_pert"])
 @pytest.mark.parametrize("precision", ["f64", "f32"])
 def test_fgmres_solve(name, precision):
     from paper_2205_15770_amd import StokesMG
@@ -242,9 +255,10 @@ def test_fgmres_solve(name, precision):
     L = ora.L
     n_f = [c * 2 ** (cfg["levels"] - 1) for c in cfg["n_coarse"]]
     mu_cell = si.uniform(int(np.prod(n_f)), 17, 0.5, 3.0)
-    gpu = StokesMG(dim=cfg["dim"], fe_degree=cfg["k"], n_coarse=cfg["n_coarse"], n_levels=cfg["levels"],
-                   mu_cell=mu_cell, gamma=PHYS["gamma"], rho=PHYS["rho"], precision=precision,
-                   fine_vertices=_vertices(name))
+    with _env(cfg):
+        gpu = StokesMG(dim=cfg["dim"], fe_degree=cfg["k"], n_coarse=cfg["n_coarse"], n_levels=cfg["levels"],
+                       mu_cell=mu_cell, gamma=PHYS["gamma"], rho=PHYS["rho"], precision=precision,
+                       fine_vertices=_vertices(name))
     asm = ora.levels[L]
     f = si.nodal_random_f(cfg["dim"], ora.meshes[L].n_vnode, seed=2)
     b = asm.rhs_from_nodal_f(f)
@@ -334,22 +348,25 @@ def test_vmult_is_deterministic():
 @pytest.mark.parametrize("dtype,tol", [(torch.float64, 1e-12), (torch.float32, 2e-5)])
 def test_full_size_2d_512_sampled_rows(dtype, tol):
     """The 512^2, 7-level generalized Stokes workload at full size: sampled rows
-    of K x against the oracle's row-by-row definition."""
+    of K x against the oracle's row-by-row definition, on the finest level (one
+    wave per tile for all fields) and on the 128^2 level (one wave per tile
+    and field)."""
     from paper_2205_15770_amd import StokesMG
     from oracle.mesh import BoxMesh
     gpu = StokesMG(dim=2, fe_degree=2, n_coarse=(8, 8), n_levels=7, gamma=1e3, rho=1.0)
-    L = 6
-    n = gpu.n_total(L)
-    x = si.uniform(n, 99)
-    y = gpu.vmult(L, _dev(x, dtype)).cpu().numpy().astype(np.float64)
-    mesh = BoxMesh(2, (512, 512), 2)
-    rng = np.random.default_rng(5)
-    dofs = np.unique(np.concatenate([rng.integers(0, n, 400), np.arange(0, 40), np.arange(n - 40, n),
-                                     [1025 * 30 + 30, 1025 * 60 + 61, 2 * 1025 * 1025 + 513 * 15 + 15]]))
-    xin = x if dtype == torch.float64 else x.astype(np.float32).astype(np.float64)
-    ref = sample_Kx(mesh, xin, dofs, gamma=1e3, rho=1.0)
-    err = np.linalg.norm(y[dofs] - ref) / np.linalg.norm(ref)
-    assert err < tol
+    for L, nc in ((6, 512), (4, 128)):
+        n = gpu.n_total(L)
+        x = si.uniform(n, 99 + L)
+        y = gpu.vmult(L, _dev(x, dtype)).cpu().numpy().astype(np.float64)
+        mesh = BoxMesh(2, (nc, nc), 2)
+        vd = 2 * nc + 1
+        rng = np.random.default_rng(5)
+        dofs = np.unique(np.concatenate([rng.integers(0, n, 400), np.arange(0, 40), np.arange(n - 40, n),
+                                         [vd * 30 + 30, vd * 60 + 61, 2 * vd * vd + (nc + 1) * 15 + 15]]))
+        xin = x if dtype == torch.float64 else x.astype(np.float32).astype(np.float64)
+        ref = sample_Kx(mesh, xin, dofs, gamma=1e3, rho=1.0)
+        err = np.linalg.norm(y[dofs] - ref) / np.linalg.norm(ref)
+        assert err < tol, L
     gpu.close()
 
 
