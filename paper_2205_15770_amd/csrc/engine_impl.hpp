@@ -26,6 +26,15 @@ inline int block3d_max_n_from_env() {
   return e != nullptr ? std::atoi(e) : 32;
 }
 
+// Waves a 3D column-sweep launch aims at (the z extent is cut into chunks
+// of >= 2 cells until the launch has about this many); SMG_SWEEP_WAVES
+// overrides it.
+inline int sweep_waves_from_env() {
+  const char *e = std::getenv("SMG_SWEEP_WAVES");
+  const int v = e != nullptr ? std::atoi(e) : 4096;
+  return v > 0 ? v : 4096;
+}
+
 // Largest 2D level (cells per direction) whose operator launches with a
 // pressure output use one wave per (tile, output field) instead of one wave
 // per tile for all fields (launches with velocity outputs only always do);
@@ -78,6 +87,7 @@ class EngineT : public EngineBase {
   bool general = false;                      // cells given by vertices
   int block3d_max_n = block3d_max_n_from_env();
   int split2d_max_n = split2d_max_n_from_env();
+  int sweep_waves = sweep_waves_from_env();
   std::vector<std::vector<double>> hverts;   // per level, host copy (node coordinates)
   double *Kinv = nullptr;
   int n0 = 0;
@@ -241,8 +251,9 @@ class EngineT : public EngineBase {
                          g, op);
     } else {
       // 8 x 8 cell columns per wave, one wave per output field; the z extent
-      // is cut into chunks so that the launch has >= ~2048 waves when the
-      // level is large enough (two per SIMD), chunks of >= 2 cells.
+      // is cut into chunks so that the launch has about sweep_waves waves
+      // (4096: four per SIMD) when the level is large enough, chunks of >= 2
+      // cells.
       constexpr int NF = ((BLK & (BLK_A | BLK_MASS | BLK_BT)) ? 3 : 0) + ((BLK & (BLK_B | BLK_C)) ? 1 : 0);
       Geo3<T> g3;
       std::memset(&g3, 0, sizeof(g3));
@@ -273,7 +284,7 @@ class EngineT : public EngineBase {
         g3.tiles[0] = (g.n[0] + 6) / 7;
         g3.tiles[1] = (g.n[1] + 6) / 7;
         const int cols = g3.tiles[0] * g3.tiles[1] * NF;
-        int nzc = (2048 + cols - 1) / cols;
+        int nzc = (sweep_waves + cols - 1) / cols;
         const int zmax = (g.n[2] + 1) / 2;
         nzc = nzc < 1 ? 1 : (nzc > zmax ? zmax : nzc);
         const int zlen = (g.n[2] + nzc - 1) / nzc;
