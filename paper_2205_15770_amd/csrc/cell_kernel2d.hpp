@@ -18,8 +18,11 @@
 //   B_c    = -sB_c (Gr in direction c, Nr in the other),  C = cp sM Mpr(x)Mpr,
 // with sKx = h_y / h_x, sKy = h_x / h_y, sM = h_x h_y, sB_x = h_y, sB_y = h_x.
 #pragma once
+#include <type_traits>
+
 #include "cell_kernel.hpp"
 #include "fe1d_const.hpp"
+#include "ops.hpp"
 
 namespace smg {
 
@@ -286,6 +289,210 @@ wave2d_split_kernel(const Geo2<T> g, const Op op) {
     if (f == 1) { wave2d_tile<K, T, BLK, Op, 1>(g, op, b); return; }
   }
   if constexpr (OUT_P) wave2d_tile<K, T, BLK, Op, 2>(g, op, b);
+}
+
+
+// ---------------------------------------------------------------------------
+// Two operator applications in one launch (small levels, where a launch costs
+// more than its arithmetic): a velocity field v is formed by a first
+// application -- q = B^T d (OpGrad) or the residual r = f - A u - B^T p
+// (OpResidual) -- and fed directly into the first step of the Chebyshev
+// recurrence for A (OpChebA with FIRST).  v never goes to memory.  After the
+// first hand-over, lanes 1..7 hold the complete sums of their owned nodes;
+// the values on a cell's right / upper faces and corner come back from lanes
+// + 1, + 8, + 9 (or stay local on the domain's high faces), so lanes 1..6 in
+// each direction hold v on their whole cell.  The second application runs on
+// those lanes only; after its hand-over, lanes 2..6 hold complete sums: the
+// tile owns 5 x 5 cells (halo: two cell rings below, one above).  Dirichlet
+// rows of v take the values the separate launches would store (r = f - u for
+// the residual, 0 for q), so the result equals the two-launch sequence.
+// One wave per (tile, velocity component).
+template <class Op>
+struct is_residual_op : std::false_type {};
+template <typename T>
+struct is_residual_op<OpResidual<T>> : std::true_type {};
+
+template <int K, typename T, class Op1, bool LAST>
+__global__ void __launch_bounds__(64)
+wave2d_fused_kernel(const Geo2<T> g, const Op1 op1, const OpChebA<T, true, LAST> op2) {
+  constexpr int NV = K + 1, NP = K, TX = 8, OWN = TX - 3;
+  constexpr uint32_t ST = sizeof(T);
+  constexpr cfe::TabT<K, T> R = cfe::make_tab_t<K, T>();
+  constexpr bool RESID = is_residual_op<Op1>::value;
+
+  const int bb = xcd_contiguous_tile(blockIdx.x, gridDim.x);
+  const int c = bb % 2, b = bb / 2;
+  const int tx = b % g.tiles[0], ty = b / g.tiles[0];
+  const int lcx = threadIdx.x % TX, lcy = threadIdx.x / TX;
+  const int gcx = tx * OWN - 2 + lcx, gcy = ty * OWN - 2 + lcy;
+  const bool active = gcx >= 0 && gcx < g.n[0] && gcy >= 0 && gcy < g.n[1];
+  const bool valid2 = active && lcx >= 1 && lcx <= TX - 2 && lcy >= 1 && lcy <= TX - 2;
+  const bool owner = active && lcx >= 2 && lcx <= TX - 2 && lcy >= 2 && lcy <= TX - 2;
+  const bool bxl = gcx == 0, bxh = gcx == g.n[0] - 1, byl = gcy == 0, byh = gcy == g.n[1] - 1;
+  const int ax = gcx < 0 ? 0 : (gcx >= g.n[0] ? g.n[0] - 1 : gcx);
+  const int ay = gcy < 0 ? 0 : (gcy >= g.n[1] ? g.n[1] - 1 : gcy);
+  const uint32_t suy = ST * (uint32_t)g.vd[0], spy = ST * (uint32_t)g.pd[0];
+  const uint32_t base_u = (uint32_t)c * g.nv_bytes + ST * (uint32_t)(K * ax) + suy * (uint32_t)(K * ay);
+  const uint32_t base_p = ST * (uint32_t)((K - 1) * ax) + spy * (uint32_t)((K - 1) * ay);
+  auto u_at = [&](int x, int y) { return BOff{base_u + suy * (uint32_t)y, ST * (uint32_t)x}; };
+  auto p_at = [&](int x, int y) { return BOff{base_p + spy * (uint32_t)y, ST * (uint32_t)x}; };
+  auto vbc = [&](int x, int y) { return ((x == 0) & bxl) | ((x == K) & bxh) | ((y == 0) & byl) | ((y == K) & byh); };
+
+  // 1. requests: first-stage inputs, the second stage's D^-1 on the whole
+  //    cell, its base vector on the owned nodes
+  T u[1][NV][NV], f[NV][NV], p[1][NP][NP], dv[NV][NV], bs[K][K];
+  if constexpr (RESID) {
+#pragma unroll
+    for (int y = 0; y < NV; ++y)
+#pragma unroll
+      for (int x = 0; x < NV; ++x) {
+        u[0][y][x] = op1.load_u(u_at(x, y));
+        f[y][x] = op1.fetch_u(u_at(x, y)).b;
+      }
+  }
+#pragma unroll
+  for (int y = 0; y < NP; ++y)
+#pragma unroll
+    for (int x = 0; x < NP; ++x) p[0][y][x] = op1.load_p(p_at(x, y));
+#pragma unroll
+  for (int y = 0; y < NV; ++y)
+#pragma unroll
+    for (int x = 0; x < NV; ++x) dv[y][x] = at(op2.dinv, u_at(x, y));
+  T mu = g.mu;
+  if constexpr (RESID)
+    if (g.mu_cell != nullptr) mu = g.mu_cell[(uint32_t)ax + (uint32_t)g.n[0] * (uint32_t)ay];
+  if (owner) {
+#pragma unroll
+    for (int y = 0; y < K; ++y)
+#pragma unroll
+      for (int x = 0; x < K; ++x) bs[y][x] = (LAST && op2.base) ? at(op2.base, u_at(x, y)) : T(0);
+  }
+  if constexpr (!RESID) {
+    if (g.mu_cell != nullptr) mu = g.mu_cell[(uint32_t)ax + (uint32_t)g.n[0] * (uint32_t)ay];
+  }
+  __asm__ volatile("" ::: "memory");
+
+  const T axk = mu * g.sKx, bxm = g.gr * g.sM, sy = mu * g.sKy;
+  T X[NV][NV];
+#pragma unroll
+  for (int i = 0; i < NV; ++i)
+#pragma unroll
+    for (int j = 0; j < NV; ++j) X[i][j] = axk * R.Kr[i][j] + bxm * R.Mr[i][j];
+  // A of one component on this cell: out = A in
+  auto apply_A = [&](const T (&in)[1][NV][NV], T (&out)[1][NV][NV]) {
+    T t[1][NV][NV];
+    pass_y<false, false>(R.Mr, in, t, T(1));
+    pass_x<false, false>(X, t, out, T(1));
+    pass_y<false, false>(R.Kr, in, t, T(1));
+    pass_x<false, true>(R.Mr, t, out, sy);
+  };
+
+  // 2. first stage
+  T um[1][NV][NV], t1[1][NV][NV];
+#pragma unroll
+  for (int y = 0; y < NV; ++y)
+#pragma unroll
+    for (int x = 0; x < NV; ++x) um[0][y][x] = (RESID && active && !vbc(x, y)) ? u[0][y][x] : T(0);
+#pragma unroll
+  for (int y = 0; y < NP; ++y)
+#pragma unroll
+    for (int x = 0; x < NP; ++x) p[0][y][x] = active ? p[0][y][x] : T(0);
+  if constexpr (RESID) apply_A(um, t1);
+  {
+    // B^T_c p
+    constexpr bool ACC = RESID;
+    if (c == 0) {
+      T s1[1][NV][NP];
+      pass_y<true, false>(R.Nr, p, s1, T(1));
+      pass_x<true, ACC>(R.Gr, s1, t1, -g.sB[0]);
+    } else {
+      T s2[1][NP][NV];
+      pass_x<true, false>(R.Nr, p, s2, T(1));
+      pass_y<true, ACC>(R.Gr, s2, t1, -g.sB[1]);
+    }
+  }
+  hand_over_xy<TX>(t1, lcx, lcy, bxh, byh);
+  // v on the nodes this lane holds completely
+  T v[NV][NV];
+#pragma unroll
+  for (int y = 0; y < NV; ++y)
+#pragma unroll
+    for (int x = 0; x < NV; ++x) {
+      const T free_v = RESID ? f[y][x] - t1[0][y][x] : t1[0][y][x];
+      const T bc_v = RESID ? f[y][x] - u[0][y][x] : T(0);
+      v[y][x] = vbc(x, y) ? bc_v : free_v;
+    }
+  // 3. right / upper faces and corner from the owners (lane + 1, + 8, + 9)
+  {
+    T colK[K], rowK[K];
+#pragma unroll
+    for (int j = 0; j < K; ++j) colK[j] = __shfl_down(v[j][0], 1, 64);
+#pragma unroll
+    for (int i = 0; i < K; ++i) rowK[i] = __shfl_down(v[0][i], TX, 64);
+    const T c9 = __shfl_down(v[0][0], TX + 1, 64);   // (0, 0) of the upper-right cell
+    const T c8 = __shfl_down(v[0][K], TX, 64);       // (K, 0) of the upper cell (its right face is local)
+    const T c1 = __shfl_down(v[K][0], 1, 64);        // (0, K) of the right cell (its upper face is local)
+    if (!bxh) {
+#pragma unroll
+      for (int j = 0; j < K; ++j) v[j][K] = colK[j];
+    }
+    if (!byh) {
+#pragma unroll
+      for (int i = 0; i < K; ++i) v[K][i] = rowK[i];
+    }
+    if (!bxh && !byh) v[K][K] = c9;
+    else if (bxh && !byh) v[K][K] = c8;
+    else if (!bxh && byh) v[K][K] = c1;
+  }
+  // 4. second stage: t2 = A d0, d0 = D^-1 v / theta (inputs of the valid lanes only)
+  T d0[1][NV][NV], t2[1][NV][NV];
+#pragma unroll
+  for (int y = 0; y < NV; ++y)
+#pragma unroll
+    for (int x = 0; x < NV; ++x) {
+      const T d = dv[y][x] * v[y][x] * op2.inv_theta;
+      d0[0][y][x] = (valid2 && !vbc(x, y)) ? d : T(0);
+    }
+  apply_A(d0, t2);
+  hand_over_xy<TX>(t2, lcx, lcy, bxh, byh);
+
+  // 5. owned nodes through the Chebyshev epilogue
+  if (!owner) return;
+  using Pre2 = typename OpChebA<T, true, LAST>::Pre;
+  auto pre_at = [&](int x, int y, T base) {
+    Pre2 q;
+    q.r = v[y][x];
+    q.x = T(0);
+    q.dinv = dv[y][x];
+    q.base = base;
+    return q;
+  };
+#pragma unroll
+  for (int y = 0; y < K; ++y)
+#pragma unroll
+    for (int x = 0; x < K; ++x) op2.store_u(u_at(x, y), t2[0][y][x], d0[0][y][x], false, pre_at(x, y, bs[y][x]));
+  if (bxl | byl) {
+#pragma unroll
+    for (int y = 0; y < K; ++y)
+#pragma unroll
+      for (int x = 0; x < K; ++x) {
+        if (!vbc(x, y)) continue;
+        const T rw = dv[y][x] * v[y][x] * op2.inv_theta;
+        op2.store_u(u_at(x, y), rw, rw, true, pre_at(x, y, bs[y][x]));
+      }
+  }
+  if (bxh | byh) {
+#pragma unroll
+    for (int y = 0; y < NV; ++y)
+#pragma unroll
+      for (int x = 0; x < NV; ++x) {
+        if (x < K && y < K) continue;
+        if ((x == K && !bxh) || (y == K && !byh)) continue;
+        const BOff gi = u_at(x, y);
+        const T rw = dv[y][x] * v[y][x] * op2.inv_theta;
+        op2.store_u(gi, rw, rw, true, pre_at(x, y, (LAST && op2.base) ? at(op2.base, gi) : T(0)));
+      }
+  }
 }
 
 }  // namespace smg

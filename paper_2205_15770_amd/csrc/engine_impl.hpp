@@ -26,6 +26,17 @@ inline int block3d_max_n_from_env() {
   return e != nullptr ? std::atoi(e) : 32;
 }
 
+// Largest 2D level (cells per direction) on which the smoother fuses the
+// operator application producing a Chebyshev right-hand side with the first
+// Chebyshev step (one launch instead of two).  Measured on the 512^2 solve:
+// the fused launch pays on every level in FP32 and up to 256^2 in FP64 (its
+// 8 x 8 tile owns 5 x 5 cells, so it recomputes more).  SMG_FUSE2D_MAX_N
+// overrides both (0: never); unset (-1): every FP32 level, FP64 up to 256.
+inline int fuse2d_max_n_from_env() {
+  const char *e = std::getenv("SMG_FUSE2D_MAX_N");
+  return e != nullptr ? std::atoi(e) : -1;
+}
+
 // Waves a 3D column-sweep launch aims at (the z extent is cut into chunks
 // of >= 2 cells until the launch has about this many); SMG_SWEEP_WAVES
 // overrides it.
@@ -88,6 +99,7 @@ class EngineT : public EngineBase {
   int block3d_max_n = block3d_max_n_from_env();
   int split2d_max_n = split2d_max_n_from_env();
   int sweep_waves = sweep_waves_from_env();
+  int fuse2d_max_n = fuse2d_max_n_from_env();
   std::vector<std::vector<double>> hverts;   // per level, host copy (node coordinates)
   double *Kinv = nullptr;
   int n0 = 0;
@@ -201,6 +213,31 @@ class EngineT : public EngineBase {
 
   void check_launch() { SMG_HIP(hipGetLastError()); }
 
+  // 2D box-cell geometry of the wave-tile kernels; `own` cells per tile and direction
+  template <typename T>
+  Geo2<T> geo2(const LevelGeom<T, DIM, K> &g, int own) const {
+    Geo2<T> g2;
+    std::memset(&g2, 0, sizeof(g2));
+    for (int a = 0; a < 2; ++a) {
+      g2.n[a] = g.n[a];
+      g2.vd[a] = g.vd[a];
+      g2.pd[a] = g.pd[a];
+      g2.tiles[a] = (g.n[a] + own - 1) / own;
+    }
+    g2.nv_bytes = (uint32_t)(g.Nv * (int64_t)sizeof(T));
+    g2.mu = g.mu;
+    g2.gr = g.gr;
+    g2.cp = g.cp;
+    g2.mu_cell = g.mu_cell;
+    const double hx = g.h[0], hy = g.h[1];
+    g2.sKx = (T)(hy / hx);
+    g2.sKy = (T)(hx / hy);
+    g2.sM = (T)(hx * hy);
+    g2.sB[0] = (T)hy;
+    g2.sB[1] = (T)hx;
+    return g2;
+  }
+
   template <typename T, int BLK, class Op>
   void tile(const LevelGeom<T, DIM, K> &g, const Op &op) {
     const unsigned nblk = (unsigned)(g.tiles[0] * g.tiles[1] * g.tiles[2]);
@@ -214,25 +251,7 @@ class EngineT : public EngineBase {
       gen_tile<T, BLK, Op>(g, op);
     } else if constexpr (DIM == 2) {
       // 8 x 8 cells per wave, one cell per lane
-      Geo2<T> g2;
-      std::memset(&g2, 0, sizeof(g2));
-      for (int a = 0; a < 2; ++a) {
-        g2.n[a] = g.n[a];
-        g2.vd[a] = g.vd[a];
-        g2.pd[a] = g.pd[a];
-        g2.tiles[a] = (g.n[a] + 6) / 7;
-      }
-      g2.nv_bytes = (uint32_t)(g.Nv * (int64_t)sizeof(T));
-      g2.mu = g.mu;
-      g2.gr = g.gr;
-      g2.cp = g.cp;
-      g2.mu_cell = g.mu_cell;
-      const double hx = g.h[0], hy = g.h[1];
-      g2.sKx = (T)(hy / hx);
-      g2.sKy = (T)(hx / hy);
-      g2.sM = (T)(hx * hy);
-      g2.sB[0] = (T)hy;
-      g2.sB[1] = (T)hx;
+      const Geo2<T> g2 = geo2<T>(g, 7);
       const unsigned nb2 = (unsigned)(g2.tiles[0] * g2.tiles[1]);
       constexpr unsigned NF2 = ((BLK & (BLK_A | BLK_MASS | BLK_BT)) ? 2 : 0) + ((BLK & (BLK_B | BLK_C)) ? 1 : 0);
       constexpr bool VEL_ONLY = (BLK & (BLK_B | BLK_C)) == 0;
@@ -574,8 +593,10 @@ class EngineT : public EngineBase {
 
   // --------------------------------------------------------- Chebyshev (A)
   // out = base + s * Cheb(A, D_A, k_A) r   (Sec. 3.3.1; three-term recurrence)
+  // i0 > 0: continue after a first step done elsewhere (its r, x, d in the
+  // level's Chebyshev state vectors)
   template <typename T>
-  void cheb_A(int l, const T *r, const T *base, T *out, double s) {
+  void cheb_A(int l, const T *r, const T *base, T *out, double s, int i0 = 0) {
     Work<T> &W = work<T>(l);
     const int64_t nu = lv[l].Nu;
     const double beta = lv[l].beta_A, theta = 0.75 * beta, delta = 0.25 * beta, s1 = theta / delta;
@@ -587,7 +608,8 @@ class EngineT : public EngineBase {
     }
     auto g = geom<T>(l);
     double rho = 1.0 / s1;
-    for (int i = 0; i < k; ++i) {
+    for (int i = 0; i < i0; ++i) rho = 1.0 / (2.0 * s1 - rho);
+    for (int i = i0; i < k; ++i) {
       const double rn = 1.0 / (2.0 * s1 - rho);
       OpChebA<T, true, true> o;  // field holder; copied into the right instantiation below
       std::memset(&o, 0, sizeof(o));
@@ -610,6 +632,65 @@ class EngineT : public EngineBase {
       else if (last) tile<T, BLK_A>(g, cast_op<OpChebA<T, false, true>>(o));
       else tile<T, BLK_A>(g, cast_op<OpChebA<T, false, false>>(o));
       rho = rn;
+    }
+  }
+
+  // out = base + s * Cheb(A, D_A, k_A) r where r comes from op1 (q = B^T d
+  // of OpGrad, or the residual of OpResidual), the application of op1 and the
+  // first Chebyshev step in one launch (2D box levels of at most
+  // fuse2d_max_n cells per direction).  Returns false, launching nothing,
+  // where the fused kernel does not apply; the caller then runs op1 and
+  // cheb_A separately.
+  template <typename T, class Op1>
+  bool cheb_A_fused(int l, const Op1 &op1, const T *base, T *out, double s) {
+    if constexpr (DIM != 2) {
+      return false;
+    } else {
+      const int k = desc.cheb_deg_A;
+      const int lim = fuse2d_max_n >= 0 ? fuse2d_max_n : (sizeof(T) == 4 ? 1 << 30 : 256);
+      if (general || k < 1 || lim <= 0 || std::max(lv[l].n[0], lv[l].n[1]) > lim) return false;
+      Work<T> &W = work<T>(l);
+      const double beta = lv[l].beta_A, theta = 0.75 * beta, delta = 0.25 * beta, s1 = theta / delta;
+      const double rho = 1.0 / s1, rn = 1.0 / (2.0 * s1 - rho);
+      OpChebA<T, true, true> o;
+      std::memset(&o, 0, sizeof(o));
+      o.dinv = W.dinvA;
+      o.r_out = W.cr;
+      o.x_out = W.cx;
+      o.d_out = W.cd[1];
+      o.base = base;
+      o.out = out;
+      o.inv_theta = (T)(1.0 / theta);
+      o.c1 = (T)(rn * rho);
+      o.c2 = (T)(2.0 * rn / delta);
+      o.s = (T)s;
+      auto g = geom<T>(l);
+      const Geo2<T> g2 = geo2<T>(g, 5);
+      const unsigned nb = (unsigned)(g2.tiles[0] * g2.tiles[1] * 2);
+      hipEvent_t ea = nullptr, eb = nullptr;
+      if (profiling) {
+        ea = next_event();
+        eb = next_event();
+        SMG_HIP(hipEventRecord(ea, stream));
+      }
+      if (k == 1)
+        hipLaunchKernelGGL((wave2d_fused_kernel<K, T, Op1, true>), dim3(nb), dim3(64), 0, stream, g2, op1, o);
+      else
+        hipLaunchKernelGGL((wave2d_fused_kernel<K, T, Op1, false>), dim3(nb), dim3(64), 0, stream, g2, op1,
+                           cast_op<OpChebA<T, true, false>>(o));
+      check_launch();
+      if (profiling) {
+        SMG_HIP(hipEventRecord(eb, stream));
+        char key[160];
+        std::snprintf(key, sizeof(key), "%s+cheb_A/v%d/fused/%s/%dx%dx%d", Op1::NAME, k == 1 ? 3 : 1,
+                      std::is_same<T, double>::value ? "f64" : "f32", g.n[0], g.n[1], g.n[2]);
+        const double nu = (double)(DIM * g.Nv), np = (double)g.Np;
+        const double bytes = sizeof(T) * ((std::is_same<Op1, OpResidual<T>>::value ? 3 * nu + np : np) +
+                                          nu * (k == 1 ? (base ? 3 : 2) : 4));
+        prof.push_back(ProfRec{key, ea, eb, bytes});
+      }
+      if (k > 1) cheb_A<T>(l, nullptr, base, out, s, 1);
+      return true;
     }
   }
 
@@ -642,11 +723,20 @@ class EngineT : public EngineBase {
     for (int i = 0; i < k; ++i) {
       const double rn = 1.0 / (2.0 * s1 - rho);
       const bool first = i == 0, last = i == k - 1;
-      // q = B^T d_i
-      if (first) tile<T, BLK_BT>(g, OpGrad<T, true>{rp, W.dinvS, nullptr, (T)(1.0 / theta), W.q});
-      else tile<T, BLK_BT>(g, OpGrad<T, false>{nullptr, nullptr, W.sd[i % 2], (T)0, W.q});
-      // w = A_hat^-1 q
-      cheb_A<T>(l, W.q, nullptr, W.w, sigma);
+      // q = B^T d_i, w = A_hat^-1 q
+      if (first) {
+        const OpGrad<T, true> og{rp, W.dinvS, nullptr, (T)(1.0 / theta), W.q};
+        if (!cheb_A_fused<T>(l, og, (const T *)nullptr, W.w, sigma)) {
+          tile<T, BLK_BT>(g, og);
+          cheb_A<T>(l, W.q, nullptr, W.w, sigma);
+        }
+      } else {
+        const OpGrad<T, false> og{nullptr, nullptr, W.sd[i % 2], (T)0, W.q};
+        if (!cheb_A_fused<T>(l, og, (const T *)nullptr, W.w, sigma)) {
+          tile<T, BLK_BT>(g, og);
+          cheb_A<T>(l, W.q, nullptr, W.w, sigma);
+        }
+      }
       // t = B w + C d_i and the recurrence
       OpChebS<T, true, true> o;
       std::memset(&o, 0, sizeof(o));
@@ -703,19 +793,24 @@ class EngineT : public EngineBase {
     T *u = x, *p = x + nu;
     const T *f = b, *gp = b + nu;
     auto g = geom<T>(l);
-    const T *ru = f;
-    if (!zero_init) {
-      OpResidual<T> op{u, p, f, nullptr, W.ru, nullptr};
-      tile<T, BLK_A | BLK_BT>(g, op);
-      ru = W.ru;
+    if (zero_init) {
+      cheb_A<T>(l, f, nullptr, W.uhat, sigma);
+    } else {
+      const OpResidual<T> op{u, p, f, nullptr, W.ru, nullptr};
+      if (!cheb_A_fused<T>(l, op, u, W.uhat, sigma)) {
+        tile<T, BLK_A | BLK_BT>(g, op);
+        cheb_A<T>(l, W.ru, u, W.uhat, sigma);
+      }
     }
-    cheb_A<T>(l, ru, zero_init ? nullptr : u, W.uhat, sigma);
     OpDivResidual<T> od{W.uhat, p, gp, W.rp};
     if (has_c()) tile<T, BLK_B | BLK_C>(g, od);
     else tile<T, BLK_B>(g, od);
     cheb_S<T>(l, W.rp, W.dp, p);
-    tile<T, BLK_BT>(g, OpGrad<T, false>{nullptr, nullptr, W.dp, (T)0, W.q});
-    cheb_A<T>(l, W.q, W.uhat, u, -sigma);
+    const OpGrad<T, false> og{nullptr, nullptr, W.dp, (T)0, W.q};
+    if (!cheb_A_fused<T>(l, og, (const T *)W.uhat, u, -sigma)) {
+      tile<T, BLK_BT>(g, og);
+      cheb_A<T>(l, W.q, W.uhat, u, -sigma);
+    }
   }
 
   template <typename T>

@@ -33,10 +33,14 @@ CONFIGS = {
     # the same levels through the column-sweep kernel (by default levels of at
     # most 32 cells per direction take the one-cell-per-lane block kernel)
     "3d_k2_sweep": dict(dim=3, k=2, n_coarse=(2, 3, 2), levels=3, env={"SMG_BLOCK3D_MAX_N": "0"}),
-    # 2D levels of at most 128 cells per direction take one wave per output
-    # field by default; the same levels with one wave for all fields:
-    "2d_k2_fused": dict(dim=2, k=2, n_coarse=(5, 3), levels=4, env={"SMG_SPLIT2D_MAX_N": "0"}),
-    "2d_k3_fused": dict(dim=2, k=3, n_coarse=(3, 2), levels=4, env={"SMG_SPLIT2D_MAX_N": "0"}),
+    # small 2D levels take one wave per output field and fuse the producer of
+    # each Chebyshev right-hand side with the first Chebyshev step by
+    # default; the same levels with one wave per tile for all fields and
+    # separate launches:
+    "2d_k2_plain": dict(dim=2, k=2, n_coarse=(5, 3), levels=4,
+                        env={"SMG_SPLIT2D_MAX_N": "0", "SMG_FUSE2D_MAX_N": "0"}),
+    "2d_k3_plain": dict(dim=2, k=3, n_coarse=(3, 2), levels=4,
+                        env={"SMG_SPLIT2D_MAX_N": "0", "SMG_FUSE2D_MAX_N": "0"}),
     "3d_k3": dict(dim=3, k=3, n_coarse=(2, 2, 3), levels=2),
     # vertex-given (multilinear) cells: interior vertices of the finest mesh
     # moved by up to 0.2 h, coarse levels take the finest vertices
@@ -244,7 +248,7 @@ def test_cycle(name, cycle):
     assert _rel(x32, ora.cycle(L, x0.copy(), b)) < 1e-4
 
 
-@pytest.mark.parametrize("name", ["2d_k2", "2d_k2_fused", "3d_k2", "3d_k2_sweep", "2d_k3", "3d_k3_pert"])
+@pytest.mark.parametrize("name", ["2d_k2", "2d_k2_plain", "3d_k2", "3d_k2_sweep", "2d_k3", "3d_k3_pert"])
 @pytest.mark.parametrize("precision", ["f64", "f32"])
 def test_fgmres_solve(name, precision):
     from paper_2205_15770_amd import StokesMG
@@ -334,6 +338,35 @@ def test_c1_protocol_16x16_stationary():
     assert abs(info["rate_q"] - rate_q(hist)) < 1e-2 * rate_q(hist)
     assert _rel(x, pressure_mean_free(asm, xo)) < 1e-8
     gpu.close()
+
+
+@pytest.mark.parametrize("kA,kS", [(1, 1), (2, 1), (3, 2), (0, 1)])
+def test_small_level_variants_equal_separate_launches(kA, kS):
+    """The small-level 2D kernels (one wave per field, operator application
+    fused with the first Chebyshev step) against one wave per tile and
+    separate launches, on every level of the same problem: the same
+    arithmetic in another launch order, so the results agree to rounding."""
+    from paper_2205_15770_amd import StokesMG
+    cfg = CONFIGS["2d_k2"]
+    mu_cell = si.uniform(40 * 24, 17, 0.5, 3.0)
+    kw = dict(dim=2, fe_degree=2, n_coarse=cfg["n_coarse"], n_levels=cfg["levels"], mu_cell=mu_cell,
+              gamma=PHYS["gamma"], rho=PHYS["rho"], c_pressure=0.2, cheb_deg_A=kA, cheb_deg_S=kS)
+    a = StokesMG(**kw)
+    with _env(CONFIGS["2d_k2_plain"]):
+        b = StokesMG(**kw)
+    for l in range(1, cfg["levels"]):
+        bA, bS = a.eigs(l)
+        b.set_eigs(l, bA, bS)
+        n = a.n_total(l)
+        for dtype, tol in ((torch.float64, 1e-13), (torch.float32, 1e-5)):
+            x0 = _dev(si.uniform(n, 60 + l), dtype)
+            rhs = _dev(si.uniform(n, 70 + l), dtype)
+            xa, xb = x0.clone(), x0.clone()
+            a.smooth(l, xa, rhs, 2)
+            b.smooth(l, xb, rhs, 2)
+            assert _rel(xa, xb.cpu().numpy().astype(np.float64)) < tol, (l, dtype)
+    a.close()
+    b.close()
 
 
 def test_vmult_is_deterministic():
