@@ -28,13 +28,12 @@ inline int block3d_max_n_from_env() {
 
 // Largest 2D level (cells per direction) on which the smoother fuses the
 // operator application producing a Chebyshev right-hand side with the first
-// Chebyshev step (one launch instead of two).  Measured on the 512^2 solve:
-// the fused launch pays on every level in FP32 and up to 256^2 in FP64 (its
-// 8 x 8 tile owns 5 x 5 cells, so it recomputes more).  SMG_FUSE2D_MAX_N
-// overrides both (0: never); unset (-1): every FP32 level, FP64 up to 256.
+// Chebyshev step (one launch instead of two; its 8 x 8 tile owns 5 x 5
+// cells, so it recomputes more, which pays where launches dominate: up to
+// 256^2 on the 512^2 solve).  SMG_FUSE2D_MAX_N overrides it (0: never).
 inline int fuse2d_max_n_from_env() {
   const char *e = std::getenv("SMG_FUSE2D_MAX_N");
-  return e != nullptr ? std::atoi(e) : -1;
+  return e != nullptr ? std::atoi(e) : 256;
 }
 
 // Waves a 3D column-sweep launch aims at (the z extent is cut into chunks
@@ -647,8 +646,7 @@ class EngineT : public EngineBase {
       return false;
     } else {
       const int k = desc.cheb_deg_A;
-      const int lim = fuse2d_max_n >= 0 ? fuse2d_max_n : (sizeof(T) == 4 ? 1 << 30 : 256);
-      if (general || k < 1 || lim <= 0 || std::max(lv[l].n[0], lv[l].n[1]) > lim) return false;
+      if (general || k < 1 || fuse2d_max_n <= 0 || std::max(lv[l].n[0], lv[l].n[1]) > fuse2d_max_n) return false;
       Work<T> &W = work<T>(l);
       const double beta = lv[l].beta_A, theta = 0.75 * beta, delta = 0.25 * beta, s1 = theta / delta;
       const double rho = 1.0 / s1, rn = 1.0 / (2.0 * s1 - rho);
