@@ -437,263 +437,4 @@ tile_apply_kernel(const LevelGeom<T, DIM, K> g, const Op op) {
   }
 }
 
-
-// ---------------------------------------------------------------------------
-// 2D variant without an LDS output patch.  After the cell matrices are
-// applied, the contributions of each cell to nodes it shares with its right
-// and upper neighbours are handed over: along x by lane shuffles (a tile row
-// of TX cells is TX consecutive lanes of one wave), along y through a small
-// LDS buffer.  Every cell then holds the complete sums of the nodes it owns
-// (local indices [0, K) in each direction, plus the high face at the domain
-// boundary) and writes them itself; the epilogue inputs of those nodes are
-// requested at kernel start together with the DoF patch.
-// ---------------------------------------------------------------------------
-template <int K, typename T, int BLK, class Op, int TX, int TY>
-__global__ void __launch_bounds__(TX * TY)
-tile2d_kernel(const LevelGeom<T, 2, K> g, const Op op) {
-  constexpr int DIM = 2, NT = TX * TY, NV = K + 1, NP = K;
-  static_assert(64 % TX == 0, "a tile row must not straddle waves");
-  constexpr int PVX = TX * K + 1, PVY = TY * K + 1;
-  constexpr int PPX = TX * (K - 1) + 1, PPY = TY * (K - 1) + 1;
-  constexpr int PV = PVX * PVY, PP = PPX * PPY;
-  constexpr bool NEED_U = (BLK & (BLK_A | BLK_MASS | BLK_B)) != 0;
-  constexpr bool NEED_P = (BLK & (BLK_BT | BLK_C)) != 0;
-  constexpr bool OUT_U = (BLK & (BLK_A | BLK_MASS | BLK_BT)) != 0;
-  constexpr bool OUT_P = (BLK & (BLK_B | BLK_C)) != 0;
-  constexpr int OWN_X = TX - 1, OWN_Y = TY - 1;
-  // y hand-over payload per cell: row y = K of each velocity component
-  // (K+1 values) and row y = K-1 of the pressure (K values)
-  constexpr int YS = (OUT_U ? DIM * (K + 1) : 0) + (OUT_P ? K : 0);
-  constexpr int LDS_IN = (NEED_U ? DIM * PV : 0) + (NEED_P ? PP : 0);
-  constexpr int LDS_N = (LDS_IN > YS * NT ? LDS_IN : YS * NT) > 0 ? (LDS_IN > YS * NT ? LDS_IN : YS * NT) : 1;
-  __shared__ T lds[LDS_N];
-  T *s_u = lds;
-  T *s_p = lds + (NEED_U ? DIM * PV : 0);
-  T *ysend = lds;  // reused once the patch has been read
-
-  const int bid = xcd_contiguous_tile(blockIdx.x, gridDim.x);
-  const int tx = bid % g.tiles[0];
-  const int ty = bid / g.tiles[0];
-  const TileAxis ax = tile_axis(tx, g.tiles[0], OWN_X, K, g.vd[0]);
-  const TileAxis ay = tile_axis(ty, g.tiles[1], OWN_Y, K, g.vd[1]);
-  const TileAxis px = tile_axis(tx, g.tiles[0], OWN_X, K - 1, g.pd[0]);
-  const TileAxis py = tile_axis(ty, g.tiles[1], OWN_Y, K - 1, g.pd[1]);
-  const int lcx = threadIdx.x % TX, lcy = threadIdx.x / TX;
-  const int gcx = ax.cell0 + lcx, gcy = ay.cell0 + lcy;
-  const bool active = gcx >= 0 && gcx < g.n[0] && gcy >= 0 && gcy < g.n[1];
-  const bool owner = active && lcx > 0 && lcy > 0;
-  const bool last_x = gcx == g.n[0] - 1, last_y = gcy == g.n[1] - 1;
-
-  // 0. epilogue inputs of the owned nodes [0,K)^2 (velocity) and [0,K-1)^2
-  //    (pressure); the high-face nodes at the domain end are handled late.
-  typename Op::Pre pre_u[DIM][K][K];
-  T raw_u[DIM][K][K];
-  typename Op::Pre pre_p[K - 1][K - 1];
-  if constexpr (OUT_U) {
-    if (owner) {
-#pragma unroll
-      for (int c = 0; c < DIM; ++c)
-#pragma unroll
-        for (int y = 0; y < K; ++y)
-#pragma unroll
-          for (int x = 0; x < K; ++x) {
-            const int gx = K * gcx + x, gy = K * gcy + y;
-            const i64 gi = (i64)c * g.Nv + gx + (i64)g.vd[0] * gy;
-            pre_u[c][y][x] = op.fetch_u(gi);
-            raw_u[c][y][x] = 0;
-            if constexpr ((BLK & BLK_A) != 0)
-              if (gx == 0 || gy == 0) raw_u[c][y][x] = op.load_u(gi);
-          }
-    }
-  }
-  if constexpr (OUT_P) {
-    if (owner) {
-#pragma unroll
-      for (int y = 0; y < K - 1; ++y)
-#pragma unroll
-        for (int x = 0; x < K - 1; ++x)
-          pre_p[y][x] = op.fetch_p(((K - 1) * gcx + x) + (i64)g.pd[0] * ((K - 1) * gcy + y));
-    }
-  }
-
-  // 1. DoF patch -> LDS (all loads of a thread in flight together)
-  if constexpr (NEED_U) {
-    constexpr int IT = (DIM * PV + NT - 1) / NT;
-    T vals[IT];
-#pragma unroll
-    for (int it = 0; it < IT; ++it) {
-      const int i = threadIdx.x + it * NT;
-      vals[it] = 0;
-      if (i < DIM * PV) {
-        const int c = i / PV;
-        const int r = i - c * PV;
-        const int gx = ax.node0 + r % PVX, gy = ay.node0 + r / PVX;
-        if (gx >= 0 && gx < g.vd[0] && gy >= 0 && gy < g.vd[1]) {
-          const bool bc = on_box_boundary(gx, g.vd[0]) || on_box_boundary(gy, g.vd[1]);
-          if (!(bc && Op::ZERO_BC)) vals[it] = op.load_u((i64)c * g.Nv + gx + (i64)g.vd[0] * gy);
-        }
-      }
-    }
-#pragma unroll
-    for (int it = 0; it < IT; ++it) {
-      const int i = threadIdx.x + it * NT;
-      if (i < DIM * PV) s_u[i] = vals[it];
-    }
-  }
-  if constexpr (NEED_P) {
-    constexpr int IT = (PP + NT - 1) / NT;
-    T vals[IT];
-#pragma unroll
-    for (int it = 0; it < IT; ++it) {
-      const int i = threadIdx.x + it * NT;
-      vals[it] = 0;
-      if (i < PP) {
-        const int gx = px.node0 + i % PPX, gy = py.node0 + i / PPX;
-        if (gx >= 0 && gx < g.pd[0] && gy >= 0 && gy < g.pd[1]) vals[it] = op.load_p(gx + (i64)g.pd[0] * gy);
-      }
-    }
-#pragma unroll
-    for (int it = 0; it < IT; ++it) {
-      const int i = threadIdx.x + it * NT;
-      if (i < PP) s_p[i] = vals[it];
-    }
-  }
-  __syncthreads();
-
-  // 2. cell matrices (sum factorisation in registers)
-  T u[DIM][1][NV][NV];
-  T p[1][NP][NP];
-  T yu[DIM][1][NV][NV];
-  T yp[1][NP][NP];
-#pragma unroll
-  for (int c = 0; c < DIM; ++c)
-#pragma unroll
-    for (int y = 0; y < NV; ++y)
-#pragma unroll
-      for (int x = 0; x < NV; ++x) {
-        u[c][0][y][x] = 0;
-        yu[c][0][y][x] = 0;
-      }
-#pragma unroll
-  for (int y = 0; y < NP; ++y)
-#pragma unroll
-    for (int x = 0; x < NP; ++x) {
-      p[0][y][x] = 0;
-      yp[0][y][x] = 0;
-    }
-  if (active) {
-    if constexpr (NEED_U) {
-#pragma unroll
-      for (int c = 0; c < DIM; ++c)
-#pragma unroll
-        for (int y = 0; y < NV; ++y)
-#pragma unroll
-          for (int x = 0; x < NV; ++x) u[c][0][y][x] = s_u[c * PV + (lcx * K + x) + PVX * (lcy * K + y)];
-    }
-    if constexpr (NEED_P) {
-#pragma unroll
-      for (int y = 0; y < NP; ++y)
-#pragma unroll
-        for (int x = 0; x < NP; ++x) p[0][y][x] = s_p[(lcx * (K - 1) + x) + PPX * (lcy * (K - 1) + y)];
-    }
-    T mu = g.mu;
-    if (g.mu_cell != nullptr) mu = g.mu_cell[gcx + (i64)g.n[0] * gcy];
-    cell_apply<DIM, K, T, BLK>(g, mu, u, p, yu, yp);
-  }
-
-  // 3a. hand the x = K column to the right neighbour (lane + 1)
-  if constexpr (OUT_U) {
-#pragma unroll
-    for (int c = 0; c < DIM; ++c)
-#pragma unroll
-      for (int y = 0; y < NV; ++y) {
-        const T r = __shfl_up(yu[c][0][y][K], 1, TX);
-        if (lcx > 0) yu[c][0][y][0] += r;
-        if (!last_x) yu[c][0][y][K] = 0;
-      }
-  }
-  if constexpr (OUT_P) {
-#pragma unroll
-    for (int y = 0; y < NP; ++y) {
-      const T r = __shfl_up(yp[0][y][K - 1], 1, TX);
-      if (lcx > 0) yp[0][y][0] += r;
-      if (!last_x) yp[0][y][K - 1] = 0;
-    }
-  }
-  // 3b. hand the y = K row to the upper neighbour (thread + TX) through LDS
-  __syncthreads();  // the patch is no longer read
-  if constexpr (YS > 0) {
-    int q = 0;
-    if constexpr (OUT_U) {
-#pragma unroll
-      for (int c = 0; c < DIM; ++c)
-#pragma unroll
-        for (int x = 0; x < NV; ++x) ysend[(q++) * NT + threadIdx.x] = yu[c][0][K][x];
-    }
-    if constexpr (OUT_P) {
-#pragma unroll
-      for (int x = 0; x < NP; ++x) ysend[(q++) * NT + threadIdx.x] = yp[0][K - 1][x];
-    }
-    __syncthreads();
-    if (lcy > 0) {
-      q = 0;
-      if constexpr (OUT_U) {
-#pragma unroll
-        for (int c = 0; c < DIM; ++c)
-#pragma unroll
-          for (int x = 0; x < NV; ++x) yu[c][0][0][x] += ysend[(q++) * NT + threadIdx.x - TX];
-      }
-      if constexpr (OUT_P) {
-#pragma unroll
-        for (int x = 0; x < NP; ++x) yp[0][0][x] += ysend[(q++) * NT + threadIdx.x - TX];
-      }
-    }
-  }
-
-  // 4. owned nodes
-  if (!owner) return;
-  if constexpr (OUT_U) {
-#pragma unroll
-    for (int c = 0; c < DIM; ++c)
-#pragma unroll
-      for (int y = 0; y < K; ++y)
-#pragma unroll
-        for (int x = 0; x < K; ++x) {
-          const int gx = K * gcx + x, gy = K * gcy + y;
-          const i64 gi = (i64)c * g.Nv + gx + (i64)g.vd[0] * gy;
-          if (gx == 0 || gy == 0) op.store_u(gi, raw_u[c][y][x], raw_u[c][y][x], true, pre_u[c][y][x]);
-          else op.store_u(gi, yu[c][0][y][x], u[c][0][y][x], false, pre_u[c][y][x]);
-        }
-    // high faces of the domain: Dirichlet nodes, handled with late loads
-    if (last_x || last_y) {
-#pragma unroll
-      for (int c = 0; c < DIM; ++c)
-#pragma unroll
-        for (int y = 0; y < NV; ++y)
-#pragma unroll
-          for (int x = 0; x < NV; ++x) {
-            const bool extra = (x == K && last_x && (y < K || last_y)) || (y == K && last_y && x < K);
-            if (!extra) continue;
-            const i64 gi = (i64)c * g.Nv + (K * gcx + x) + (i64)g.vd[0] * (K * gcy + y);
-            T raw = 0;
-            if constexpr ((BLK & BLK_A) != 0) raw = op.load_u(gi);
-            op.store_u(gi, raw, raw, true, op.fetch_u(gi));
-          }
-    }
-  }
-  if constexpr (OUT_P) {
-#pragma unroll
-    for (int y = 0; y < NP; ++y)
-#pragma unroll
-      for (int x = 0; x < NP; ++x) {
-        const bool main = x < K - 1 && y < K - 1;
-        const bool extra = (x == K - 1 && last_x && (y < K - 1 || last_y)) || (y == K - 1 && last_y && x < K - 1);
-        if (!main && !extra) continue;
-        const i64 gi = ((K - 1) * gcx + x) + (i64)g.pd[0] * ((K - 1) * gcy + y);
-        if (main) op.store_p(gi, yp[0][y][x], p[0][y][x], pre_p[main ? y : 0][main ? x : 0]);
-        else op.store_p(gi, yp[0][y][x], p[0][y][x], op.fetch_p(gi));
-      }
-  }
-}
-
 }  // namespace smg
