@@ -680,6 +680,320 @@ block3d_kernel(const Geo3<T> g, const Op op) {
   if constexpr (OUT_P) block_pres<K, T, BLK, Op>(g, op, col, s);
 }
 
+// ---------------------------------------------------------------------------
+// Smallest levels: the cell block of block3d_kernel with one wave per output
+// z-plane of the cell (three waves per block and output field for the
+// velocity, two for the pressure).  Each wave reads the whole cell but
+// contracts in z only for its own plane, so its instruction chain -- the run
+// time of a launch with a few dozen waves -- is about a third.  The z = k
+// plane moves to the cell above through LDS (the x and y faces still by
+// shuffles within the plane's wave).
+// ---------------------------------------------------------------------------
+// out = sum_z m[O][z] in[z] (TR: m[z][O]) for one output plane O
+template <int O, bool TR, int NI, int NY, int NX, typename T, int R, int C>
+__device__ __forceinline__ void plane_z(const T (&m)[R][C], const T (&in)[NI][NY][NX], T (&out)[1][NY][NX]) {
+#pragma unroll
+  for (int y = 0; y < NY; ++y)
+#pragma unroll
+    for (int x = 0; x < NX; ++x) {
+      T acc = 0;
+#pragma unroll
+      for (int i = 0; i < NI; ++i) acc += (TR ? m[i][O] : m[O][i]) * in[i][y][x];
+      out[0][y][x] = acc;
+    }
+}
+
+// plane O of (A u + B^T p)_COMP (or M u), as vel_cell
+template <int K, typename T, int BLK, int COMP, int O>
+__device__ __forceinline__ void vel_plane(const Geo3<T> &g, T mu, const T (&u)[K + 1][K + 1][K + 1],
+                                          const T (&p)[K][K][K], T (&y)[1][K + 1][K + 1]) {
+  constexpr int NV = K + 1, NP = K;
+  constexpr cfe::TabT<K, T> R = cfe::make_tab_t<K, T>();
+  const T(&Bx)[K][K + 1] = COMP == 0 ? R.Gr : R.Nr;
+  const T(&By)[K][K + 1] = COMP == 1 ? R.Gr : R.Nr;
+  const T(&Bz)[K][K + 1] = COMP == 2 ? R.Gr : R.Nr;
+  if constexpr ((BLK & BLK_A) != 0) {
+    T X[NV][NV];
+    const T ax = mu * g.sKx, bx = g.gr * g.sM;
+#pragma unroll
+    for (int i = 0; i < NV; ++i)
+#pragma unroll
+      for (int j = 0; j < NV; ++j) X[i][j] = ax * R.Kr[i][j] + bx * R.Mr[i][j];
+    T a[1][NV][NV], b[1][NV][NV], t[1][NV][NV];
+    plane_z<O, false>(R.Mr, u, a);
+    plane_z<O, false>(R.Kr, u, b);
+    pass_y<false, false>(R.Mr, a, t, T(1));
+    pass_x<false, false>(X, t, y, T(1));
+    pass_y<false, false>(R.Kr, a, t, T(1));
+    pass_y<false, true>(R.Mr, b, t, g.rz);
+    pass_x<false, true>(R.Mr, t, y, mu * g.sKy);
+  } else if constexpr ((BLK & BLK_MASS) != 0) {
+    T a[1][NV][NV], t[1][NV][NV];
+    plane_z<O, false>(R.Mr, u, a);
+    pass_y<false, false>(R.Mr, a, t, T(1));
+    pass_x<false, false>(R.Mr, t, y, g.sM);
+  }
+  if constexpr ((BLK & BLK_BT) != 0) {
+    constexpr bool ACC = (BLK & (BLK_A | BLK_MASS)) != 0;
+    T s1[1][NP][NP], s2[1][NV][NP];
+    plane_z<O, true>(Bz, p, s1);
+    pass_y<true, false>(By, s1, s2, T(1));
+    pass_x<true, ACC>(Bx, s2, y, -g.sB[COMP]);
+  } else if constexpr ((BLK & (BLK_A | BLK_MASS)) == 0) {
+#pragma unroll
+    for (int j = 0; j < NV; ++j)
+#pragma unroll
+      for (int i = 0; i < NV; ++i) y[0][j][i] = 0;
+  }
+}
+
+// plane O (< K) of B u -/+ C p
+template <int K, typename T, int BLK, int O>
+__device__ __forceinline__ void pres_plane(const Geo3<T> &g, const T (&ub)[3][K + 1][K + 1][K + 1],
+                                           const T (&p)[K][K][K], T (&yp)[1][K][K]) {
+  constexpr int NV = K + 1, NP = K;
+  constexpr cfe::TabT<K, T> R = cfe::make_tab_t<K, T>();
+#pragma unroll
+  for (int j = 0; j < NP; ++j)
+#pragma unroll
+    for (int i = 0; i < NP; ++i) yp[0][j][i] = 0;
+  if constexpr ((BLK & BLK_B) != 0) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      T w1[1][NV][NV], w2[1][NP][NV];
+      plane_z<O, false>(c == 2 ? R.Gr : R.Nr, ub[c], w1);
+      pass_y<false, false>(c == 1 ? R.Gr : R.Nr, w1, w2, T(1));
+      pass_x<false, true>(c == 0 ? R.Gr : R.Nr, w2, yp, -g.sB[c]);
+    }
+  }
+  if constexpr ((BLK & BLK_C) != 0) {
+    const T sc = ((BLK & BLK_CPLUS) ? g.cp : -g.cp) * g.sM;
+    T q1[1][NP][NP], q2[1][NP][NP];
+    plane_z<O, false>(R.Mpr, p, q1);
+    pass_y<false, false>(R.Mpr, q1, q2, T(1));
+    pass_x<false, true>(R.Mpr, q2, yp, sc);
+  }
+}
+
+template <int K, typename T, int BLK, class Op, int COMP>
+__device__ __forceinline__ void block_vel_planes(const Geo3<T> &g, const Op &op, const Column3D<K, T> &col,
+                                                 const Block3D &s, int o, T (*lds)[K + 1][K + 1]) {
+  constexpr int NV = K + 1, NP = K;
+  constexpr bool NEED_U = (BLK & (BLK_A | BLK_MASS)) != 0;
+  constexpr bool NEED_P = (BLK & BLK_BT) != 0;
+  T u[NV][NV][NV], p[NP][NP][NP];
+  if constexpr (NEED_U) col.template load_u<0>(op, COMP, s.cz, u);
+  if constexpr (NEED_P) col.template load_p<0>(op, s.cz, p);
+  T mu = 0;
+  if constexpr ((BLK & BLK_A) != 0) mu = col.mu_at(s.cz);
+  typename Op::Pre pre[K][K];
+  if (s.owner && o < K) {
+#pragma unroll
+    for (int yy = 0; yy < K; ++yy)
+#pragma unroll
+      for (int x = 0; x < K; ++x) pre[yy][x] = op.fetch_u(col.u_at(COMP, s.cz, x, yy, o));
+  }
+  __asm__ volatile("" ::: "memory");
+#pragma unroll
+  for (int z = 0; z < NV; ++z)
+#pragma unroll
+    for (int j = 0; j < NV; ++j)
+#pragma unroll
+      for (int i = 0; i < NV; ++i) {
+        if constexpr (NEED_U) {
+          const bool keep = s.active & !(Op::ZERO_BC & col.vbc(s.cz, i, j, z));
+          u[z][j][i] = keep ? u[z][j][i] : T(0);
+        } else {
+          u[z][j][i] = 0;
+        }
+      }
+  if constexpr (NEED_P) {
+#pragma unroll
+    for (int z = 0; z < NP; ++z)
+#pragma unroll
+      for (int j = 0; j < NP; ++j)
+#pragma unroll
+        for (int i = 0; i < NP; ++i) p[z][j][i] = s.active ? p[z][j][i] : T(0);
+  }
+  T y[1][NV][NV];
+  switch (o) {
+    case 0: vel_plane<K, T, BLK, COMP, 0>(g, mu, u, p, y); break;
+    case 1: vel_plane<K, T, BLK, COMP, 1>(g, mu, u, p, y); break;
+    default: vel_plane<K, T, BLK, COMP, 2>(g, mu, u, p, y); break;
+  }
+  hand_over_xy<4>(y, s.lx, s.ly, s.last_x, s.last_y);
+  // the z = K plane goes to plane 0 of the cell above (lane + 16)
+  if (o == K) {
+#pragma unroll
+    for (int j = 0; j < NV; ++j)
+#pragma unroll
+      for (int i = 0; i < NV; ++i) lds[threadIdx.x % 64][j][i] = y[0][j][i];
+  }
+  __syncthreads();
+  if (o == 0 && s.lz > 0) {
+#pragma unroll
+    for (int j = 0; j < NV; ++j)
+#pragma unroll
+      for (int i = 0; i < NV; ++i) y[0][j][i] += lds[threadIdx.x % 64 - 16][j][i];
+  }
+  if (!s.owner) return;
+  if (o < K) {
+#pragma unroll
+    for (int yy = 0; yy < K; ++yy)
+#pragma unroll
+      for (int x = 0; x < K; ++x) {
+        // u[o] without a dynamic index into registers (o is wave-uniform)
+        T uo = u[0][yy][x];
+#pragma unroll
+        for (int z = 1; z < K; ++z) uo = o == z ? u[z][yy][x] : uo;
+        op.store_u(col.u_at(COMP, s.cz, x, yy, o), y[0][yy][x], uo, false, pre[yy][x]);
+      }
+    if (col.bxl | col.byl | ((s.cz == 0) & (o == 0))) {
+#pragma unroll
+      for (int yy = 0; yy < K; ++yy)
+#pragma unroll
+        for (int x = 0; x < K; ++x) {
+          if (!col.vbc(s.cz, x, yy, o)) continue;
+          const BOff gi = col.u_at(COMP, s.cz, x, yy, o);
+          T rw = 0;
+          if constexpr ((BLK & BLK_A) != 0) rw = op.load_u(gi);
+          op.store_u(gi, rw, rw, true, pre[yy][x]);
+        }
+    }
+  }
+  // nodes on the domain's high faces in this plane: Dirichlet rows
+  if (s.last_x | s.last_y | ((o == K) & s.last_z)) {
+#pragma unroll
+    for (int yy = 0; yy < NV; ++yy)
+#pragma unroll
+      for (int x = 0; x < NV; ++x) {
+        if (x < K && yy < K && o < K) continue;
+        if ((x == K && !s.last_x) || (yy == K && !s.last_y) || (o == K && !s.last_z)) continue;
+        const BOff gi = col.u_at(COMP, s.cz, x, yy, o);
+        T rw = 0;
+        if constexpr ((BLK & BLK_A) != 0) rw = op.load_u(gi);
+        op.store_u(gi, rw, rw, true, op.fetch_u(gi));
+      }
+  }
+}
+
+template <int K, typename T, int BLK, class Op>
+__device__ __forceinline__ void block_pres_planes(const Geo3<T> &g, const Op &op, const Column3D<K, T> &col,
+                                                  const Block3D &s, int o, T (*lds)[K + 1][K + 1]) {
+  constexpr int NV = K + 1, NP = K;
+  constexpr bool NEED_U = (BLK & BLK_B) != 0;
+  constexpr bool NEED_P = (BLK & BLK_C) != 0;
+  const bool act = o < NP;   // the pressure has K planes; the last wave only joins the barrier
+  T ub[3][NV][NV][NV], p[NP][NP][NP];
+  if constexpr (NEED_U) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) col.template load_u<0>(op, c, s.cz, ub[c]);
+  }
+  if constexpr (NEED_P) col.template load_p<0>(op, s.cz, p);
+  typename Op::Pre pre[K - 1][K - 1];
+  if (s.owner && o < K - 1) {
+#pragma unroll
+    for (int yy = 0; yy < K - 1; ++yy)
+#pragma unroll
+      for (int x = 0; x < K - 1; ++x) pre[yy][x] = op.fetch_p(col.p_at(s.cz, x, yy, o));
+  }
+  __asm__ volatile("" ::: "memory");
+  if constexpr (NEED_U) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+#pragma unroll
+      for (int z = 0; z < NV; ++z)
+#pragma unroll
+        for (int j = 0; j < NV; ++j)
+#pragma unroll
+          for (int i = 0; i < NV; ++i) {
+            const bool keep = s.active & !(Op::ZERO_BC & col.vbc(s.cz, i, j, z));
+            ub[c][z][j][i] = keep ? ub[c][z][j][i] : T(0);
+          }
+  }
+#pragma unroll
+  for (int z = 0; z < NP; ++z)
+#pragma unroll
+    for (int j = 0; j < NP; ++j)
+#pragma unroll
+      for (int i = 0; i < NP; ++i) p[z][j][i] = (NEED_P && s.active) ? p[z][j][i] : T(0);
+  T yp[1][NP][NP];
+  switch (o) {
+    case 0: pres_plane<K, T, BLK, 0>(g, ub, p, yp); break;
+    default: pres_plane<K, T, BLK, K - 1>(g, ub, p, yp); break;
+  }
+  hand_over_xy<4>(yp, s.lx, s.ly, s.last_x, s.last_y);
+  if (o == NP - 1) {
+#pragma unroll
+    for (int j = 0; j < NP; ++j)
+#pragma unroll
+      for (int i = 0; i < NP; ++i) lds[threadIdx.x % 64][j][i] = yp[0][j][i];
+  }
+  __syncthreads();
+  if (o == 0 && s.lz > 0) {
+#pragma unroll
+    for (int j = 0; j < NP; ++j)
+#pragma unroll
+      for (int i = 0; i < NP; ++i) yp[0][j][i] += lds[threadIdx.x % 64 - 16][j][i];
+  }
+  if (!s.owner || !act) return;
+  // plane o: nodes [0, K-1)^2 owned; the high faces as in the column sweep
+#pragma unroll
+  for (int yy = 0; yy < NP; ++yy)
+#pragma unroll
+    for (int x = 0; x < NP; ++x) {
+      T po = p[0][yy][x];
+#pragma unroll
+      for (int z = 1; z < NP; ++z) po = o == z ? p[z][yy][x] : po;
+      const bool main = x < K - 1 && yy < K - 1 && o < K - 1;
+      if (main) {
+        op.store_p(col.p_at(s.cz, x, yy, o), yp[0][yy][x], po, pre[main ? yy : 0][main ? x : 0]);
+      } else if (((x < K - 1) | s.last_x) & ((yy < K - 1) | s.last_y) & ((o < K - 1) | s.last_z)) {
+        const BOff gi = col.p_at(s.cz, x, yy, o);
+        op.store_p(gi, yp[0][yy][x], po, op.fetch_p(gi));
+      }
+    }
+}
+
+template <int K, typename T, int BLK, class Op>
+__global__ void __launch_bounds__(64 * (K + 1))
+block3d_plane_kernel(const Geo3<T> g, const Op op) {
+  constexpr bool OUT_U = (BLK & (BLK_A | BLK_MASS | BLK_BT)) != 0;
+  constexpr bool OUT_P = (BLK & (BLK_B | BLK_C)) != 0;
+  constexpr int NFIELD = (OUT_U ? 3 : 0) + (OUT_P ? 1 : 0);
+  __shared__ T lds[64][K + 1][K + 1];
+  const int b = xcd_contiguous_tile(blockIdx.x, gridDim.x);
+  const int field = b % NFIELD;
+  int rest = b / NFIELD;
+  const int tx = rest % g.tiles[0];
+  rest /= g.tiles[0];
+  const int ty = rest % g.tiles[1];
+  const int tz = rest / g.tiles[1];
+  const int o = __builtin_amdgcn_readfirstlane((int)threadIdx.x / 64);
+  const int lane = threadIdx.x % 64;
+  Block3D s;
+  s.lx = lane % 4;
+  s.ly = (lane / 4) % 4;
+  s.lz = lane / 16;
+  const Column3D<K, T> col(g, tx * 3 - 1 + s.lx, ty * 3 - 1 + s.ly);
+  const int cz = tz * 3 - 1 + s.lz;
+  s.cz = cz < 0 ? 0 : (cz >= g.n[2] ? g.n[2] - 1 : cz);
+  s.active = col.active && cz >= 0 && cz < g.n[2];
+  s.owner = s.active && s.lx > 0 && s.ly > 0 && s.lz > 0;
+  s.last_x = col.bxh;
+  s.last_y = col.byh;
+  s.last_z = cz == g.n[2] - 1;
+  if constexpr (OUT_U) {
+    switch (field) {
+      case 0: block_vel_planes<K, T, BLK, Op, 0>(g, op, col, s, o, lds); return;
+      case 1: block_vel_planes<K, T, BLK, Op, 1>(g, op, col, s, o, lds); return;
+      case 2: block_vel_planes<K, T, BLK, Op, 2>(g, op, col, s, o, lds); return;
+      default: break;
+    }
+  }
+  if constexpr (OUT_P) block_pres_planes<K, T, BLK, Op>(g, op, col, s, o, lds);
+}
+
 template <int K, typename T, int BLK, class Op, int TX, int TY>
 __global__ void __launch_bounds__(64)
 tile3d_kernel(const Geo3<T> g, const Op op) {

@@ -36,6 +36,14 @@ inline int fuse2d_max_n_from_env() {
   return e != nullptr ? std::atoi(e) : 256;
 }
 
+// Largest 3D Q2 level (cells per direction) whose cell-block launches use
+// one wave per output plane of the cells; SMG_PLANE3D_MAX_N overrides it
+// (0: never).
+inline int plane3d_max_n_from_env() {
+  const char *e = std::getenv("SMG_PLANE3D_MAX_N");
+  return e != nullptr ? std::atoi(e) : 16;
+}
+
 // Waves a 3D column-sweep launch aims at (the z extent is cut into chunks
 // of >= 2 cells until the launch has about this many); SMG_SWEEP_WAVES
 // overrides it.
@@ -99,6 +107,7 @@ class EngineT : public EngineBase {
   int split2d_max_n = split2d_max_n_from_env();
   int sweep_waves = sweep_waves_from_env();
   int fuse2d_max_n = fuse2d_max_n_from_env();
+  int plane3d_max_n = plane3d_max_n_from_env();
   std::vector<std::vector<double>> hverts;   // per level, host copy (node coordinates)
   double *Kinv = nullptr;
   int n0 = 0;
@@ -297,7 +306,11 @@ class EngineT : public EngineBase {
         // small level: 4 x 4 x 4 cells per wave, one cell per lane, no sweep
         for (int a = 0; a < 3; ++a) g3.tiles[a] = (g.n[a] + 2) / 3;
         const unsigned nbb = (unsigned)(g3.tiles[0] * g3.tiles[1] * g3.tiles[2] * NF);
-        hipLaunchKernelGGL((block3d_kernel<K, T, BLK, Op>), dim3(nbb), dim3(64), 0, stream, g3, op);
+        if (std::max(g.n[0], std::max(g.n[1], g.n[2])) <= plane3d_max_n)
+          // smallest levels: one wave per output plane of the cells
+          hipLaunchKernelGGL((block3d_plane_kernel<K, T, BLK, Op>), dim3(nbb), dim3(64 * (K + 1)), 0, stream, g3, op);
+        else
+          hipLaunchKernelGGL((block3d_kernel<K, T, BLK, Op>), dim3(nbb), dim3(64), 0, stream, g3, op);
       } else {
         g3.tiles[0] = (g.n[0] + 6) / 7;
         g3.tiles[1] = (g.n[1] + 6) / 7;

@@ -25,6 +25,7 @@ CASES = {
     "3d_k2": dict(dim=3, k=2, n_coarse=(2, 3, 2), levels=3),
     "2d_k2_plain": dict(dim=2, k=2, n_coarse=(5, 3), levels=3, env={"SMG_SPLIT2D_MAX_N": "0", "SMG_FUSE2D_MAX_N": "0"}),
     "3d_k2_sweep": dict(dim=3, k=2, n_coarse=(2, 3, 2), levels=3, env={"SMG_BLOCK3D_MAX_N": "0"}),
+    "3d_k2_cellblock": dict(dim=3, k=2, n_coarse=(2, 3, 2), levels=3, env={"SMG_PLANE3D_MAX_N": "0"}),
     "3d_k3": dict(dim=3, k=3, n_coarse=(2, 2, 3), levels=2),
     "2d_k2_pert": dict(dim=2, k=2, n_coarse=(3, 2), levels=3, pert=True),
     "3d_k3_pert": dict(dim=3, k=3, n_coarse=(2, 2, 2), levels=2, pert=True),

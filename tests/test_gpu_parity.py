@@ -33,6 +33,9 @@ CONFIGS = {
     # the same levels through the column-sweep kernel (by default levels of at
     # most 32 cells per direction take the one-cell-per-lane block kernel)
     "3d_k2_sweep": dict(dim=3, k=2, n_coarse=(2, 3, 2), levels=3, env={"SMG_BLOCK3D_MAX_N": "0"}),
+    # levels of at most 16 cells per direction use one wave per output plane
+    # of the cell block by default; the same levels with one wave per block:
+    "3d_k2_cellblock": dict(dim=3, k=2, n_coarse=(2, 3, 2), levels=3, env={"SMG_PLANE3D_MAX_N": "0"}),
     # small 2D levels take one wave per output field and fuse the producer of
     # each Chebyshev right-hand side with the first Chebyshev step by
     # default; the same levels with one wave per tile for all fields and
@@ -248,7 +251,7 @@ def test_cycle(name, cycle):
     assert _rel(x32, ora.cycle(L, x0.copy(), b)) < 1e-4
 
 
-@pytest.mark.parametrize("name", ["2d_k2", "2d_k2_plain", "3d_k2", "3d_k2_sweep", "2d_k3", "3d_k3_pert"])
+@pytest.mark.parametrize("name", ["2d_k2", "2d_k2_plain", "3d_k2", "3d_k2_sweep", "3d_k2_cellblock", "2d_k3", "3d_k3_pert"])
 @pytest.mark.parametrize("precision", ["f64", "f32"])
 def test_fgmres_solve(name, precision):
     from paper_2205_15770_amd import StokesMG
