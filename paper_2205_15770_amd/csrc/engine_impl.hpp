@@ -854,11 +854,11 @@ class EngineT : public EngineBase {
       const bool vel = field == 0;
       const XferGeo<T> g = xfer_geo<T>(lf, vel);
       const unsigned nz = (unsigned)((DIM == 3 ? g.fdim[2] : 1) * (vel ? DIM : 1));
-      const dim3 grid((unsigned)((g.fdim[0] + 127) / 128), (unsigned)g.fdim[1], nz);
+      const dim3 grid((unsigned)(((int64_t)g.fdim[0] * g.fdim[1] + 255) / 256), nz);
       if (vel)
-        hipLaunchKernelGGL((k_prolong<T, DIM, K, true>), grid, dim3(128), 0, stream, wc, xf, g);
+        hipLaunchKernelGGL((k_prolong<T, DIM, K, true>), grid, dim3(256), 0, stream, wc, xf, g);
       else
-        hipLaunchKernelGGL((k_prolong<T, DIM, K - 1, false>), grid, dim3(128), 0, stream, wc, xf, g);
+        hipLaunchKernelGGL((k_prolong<T, DIM, K - 1, false>), grid, dim3(256), 0, stream, wc, xf, g);
       check_launch();
     }
   }

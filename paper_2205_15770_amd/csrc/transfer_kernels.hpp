@@ -6,13 +6,12 @@
 // the restriction is its transpose, R = P^T.  Velocity rows and columns of
 // Dirichlet nodes are zero.
 //
-// prolongation: one thread per fine node, x_f += P w_c.  A block covers a
-//   run of fine nodes along x with fixed (y, z), so the y and z weights are
-//   uniform across the block and only the x weights vary by lane.
+// prolongation: one thread per fine node, x_f += P w_c, every coarse value of
+//   the node's support requested at once.
 // restriction: one block per run of coarse nodes along x with fixed (y, z):
-//   the fine values in the (y, z) support are first summed with the uniform
-//   y/z weights into an LDS row (coalesced loads), then each coarse node
-//   applies its x weights to that row.  One pass over the fine vector, no
+//   the fine values in the (y, z) support are first summed with the y/z
+//   weights into an LDS row (coalesced loads), then each coarse node applies
+//   its x weights to that row.  One pass over the fine vector, no
 //   intermediate vectors.
 #pragma once
 #include "common.hpp"
@@ -38,15 +37,33 @@ __device__ __forceinline__ void fine_pos(int f, int nf_cells, int &cc, int &pos)
   pos = f - 2 * DEG * cc;
 }
 
-template <typename T, int DIM, int DEG, bool BC>
-__global__ void __launch_bounds__(128) k_prolong(const T *__restrict__ wc, T *__restrict__ xf, const XferGeo<T> g) {
+// 1D weight W[pos][j] for a lane-dependent position (the table is a kernel
+// argument; the select chain keeps it out of scratch memory)
+template <int DEG, typename T>
+__device__ __forceinline__ T weight_at(const T *W, int pos, int j) {
   constexpr int ND = DEG + 1;
-  const int fx = blockIdx.x * 128 + threadIdx.x;
-  const int fy = blockIdx.y;
+  T w = W[j];
+#pragma unroll
+  for (int p = 1; p <= 2 * DEG; ++p) w = pos == p ? W[p * ND + j] : w;
+  return w;
+}
+
+// Prolongation x_f += P w_c: one thread per fine node; blocks of 256 threads
+// run over the flattened (x, y) plane of one z position and component, so no
+// block is left mostly empty by lattice extents of the form 2^j + 1.  All
+// (deg+1)^d coarse values of the node's support are requested at once (zero
+// weights included; coarse Dirichlet nodes get weight 0).
+template <typename T, int DIM, int DEG, bool BC>
+__global__ void __launch_bounds__(256) k_prolong(const T *__restrict__ wc, T *__restrict__ xf, const XferGeo<T> g) {
+  constexpr int ND = DEG + 1;
+  const int nxy = g.fdim[0] * g.fdim[1];
+  const int t = blockIdx.x * 256 + threadIdx.x;
   const int nz = DIM == 3 ? g.fdim[2] : 1;
-  const int comp = blockIdx.z / nz;
-  const int fz = blockIdx.z - comp * nz;
-  if (fx >= g.fdim[0]) return;
+  const int comp = blockIdx.y / nz;
+  const int fz = blockIdx.y - comp * nz;
+  if (t >= nxy) return;
+  const int fy = t / g.fdim[0];
+  const int fx = t - fy * g.fdim[0];
   if (BC) {
     const bool fbc = fx == 0 || fx == g.fdim[0] - 1 || fy == 0 || fy == g.fdim[1] - 1 ||
                      (DIM == 3 && (fz == 0 || fz == g.fdim[2] - 1));
@@ -56,45 +73,58 @@ __global__ void __launch_bounds__(128) k_prolong(const T *__restrict__ wc, T *__
   fine_pos<DEG>(fx, g.ncell_f[0], ccx, px);
   fine_pos<DEG>(fy, g.ncell_f[1], ccy, py);
   if (DIM == 3) fine_pos<DEG>(fz, g.ncell_f[2], ccz, pz);
-  T wx[ND];
-  int cxs[ND];
-  bool okx[ND];
+  T wx[ND], wy[ND], wz[ND];
 #pragma unroll
   for (int j = 0; j < ND; ++j) {
-    wx[j] = g.W[px * ND + j];
-    cxs[j] = DEG * ccx + j;
-    okx[j] = !(BC && (cxs[j] == 0 || cxs[j] == g.cdim[0] - 1));
+    wx[j] = weight_at<DEG>(g.W, px, j);
+    wy[j] = weight_at<DEG>(g.W, py, j);
+    wz[j] = DIM == 3 ? weight_at<DEG>(g.W, pz, j) : T(j == 0 ? 1 : 0);
+    if (BC) {
+      const int cx = DEG * ccx + j, cy = DEG * ccy + j, cz = DEG * ccz + j;
+      if (cx == 0 || cx == g.cdim[0] - 1) wx[j] = 0;
+      if (cy == 0 || cy == g.cdim[1] - 1) wy[j] = 0;
+      if (DIM == 3 && (cz == 0 || cz == g.cdim[2] - 1)) wz[j] = 0;
+    }
   }
-  const T *src = wc + g.coff + (i64)comp * g.cstride;
+  const T *src = wc + g.coff + (i64)comp * g.cstride + DEG * ccx +
+                 (i64)g.cdim[0] * (DEG * ccy + (i64)g.cdim[1] * (DEG * ccz));
   T s = 0;
 #pragma unroll
   for (int jz = 0; jz < (DIM == 3 ? ND : 1); ++jz) {
-    const T wz = DIM == 3 ? g.W[pz * ND + jz] : T(1);
-    const int cz = DIM == 3 ? DEG * ccz + jz : 0;
-    if (wz == T(0)) continue;  // uniform
-    if (DIM == 3 && BC && (cz == 0 || cz == g.cdim[2] - 1)) continue;
+    T r = 0;
 #pragma unroll
     for (int jy = 0; jy < ND; ++jy) {
-      const T wy = g.W[py * ND + jy];
-      const int cy = DEG * ccy + jy;
-      if (wy == T(0)) continue;  // uniform
-      if (BC && (cy == 0 || cy == g.cdim[1] - 1)) continue;
-      const T *row = src + (i64)g.cdim[0] * (cy + (i64)g.cdim[1] * cz);
-      T r = 0;
+      const T *row = src + (i64)g.cdim[0] * (jy + (i64)g.cdim[1] * jz);
+      T q = 0;
 #pragma unroll
-      for (int jx = 0; jx < ND; ++jx) r += (okx[jx] ? wx[jx] : T(0)) * row[cxs[jx]];
-      s += wz * wy * r;
+      for (int jx = 0; jx < ND; ++jx) q += wx[jx] * row[jx];
+      r += wy[jy] * q;
     }
+    s += wz[jz] * r;
   }
   T &out = xf[g.foff + (i64)comp * g.fstride + fx + (i64)g.fdim[0] * (fy + (i64)g.fdim[1] * fz)];
   out += s;
 }
 
+// Restriction r_c = P^T r_f: one block per run of CX coarse nodes along x at
+// fixed (y, z) and component.  The fine rows of the (y, z) support with a
+// non-zero weight are listed first (the same list for every lane: candidate
+// rows tested by one thread each, compacted by wave ballots in candidate
+// order, so the summation order is fixed); phase 1 then sums those rows into
+// an LDS row, eight rows per round of requests; phase 2 applies each coarse
+// node's x weights to the row.  One pass over the fine vector, no
+// intermediate vectors.
 template <typename T, int DIM, int DEG, bool BC, int CX>
 __global__ void __launch_bounds__(256) k_restrict(const T *__restrict__ rf, T *__restrict__ rc, const XferGeo<T> g) {
-  constexpr int ND = DEG + 1;
+  constexpr int NC = 4 * DEG + 1;  // candidate fine rows per direction
+  constexpr int NCAND = DIM == 3 ? NC * NC : NC;
+  static_assert(NCAND <= 256, "one candidate per thread");
   constexpr int ROW = 2 * (CX - 1) + 4 * DEG + 1;
+  constexpr int UNR = 8;
   __shared__ T tmp[ROW];
+  __shared__ T s_w[NCAND];
+  __shared__ i64 s_off[NCAND];
+  __shared__ int s_cnt[4];
   const int cx0 = blockIdx.x * CX;
   const int cy = blockIdx.y;
   const int nz = DIM == 3 ? g.cdim[2] : 1;
@@ -106,35 +136,63 @@ __global__ void __launch_bounds__(256) k_restrict(const T *__restrict__ rf, T *_
   if (fx_hi > g.fdim[0] - 1) fx_hi = g.fdim[0] - 1;
   const T *src = rf + g.foff + (i64)comp * g.fstride;
 
-  // 1. fine row: sum over the (y, z) support of (cy, cz) with uniform weights
+  // weight of fine row f (along a direction) for coarse node c
+  auto wrow = [&](int f, int c, int nf_cells, int fdim) -> T {
+    if (f < 0 || f > fdim - 1) return T(0);
+    if (BC && (f == 0 || f == fdim - 1)) return T(0);
+    int cc, pos;
+    fine_pos<DEG>(f, nf_cells, cc, pos);
+    const int j = c - DEG * cc;
+    if (j < 0 || j > DEG) return T(0);
+    return weight_at<DEG>(g.W, pos, j);
+  };
+
+  // 0. list of the support rows with non-zero weight
+  {
+    const int t = (int)threadIdx.x;
+    T w = 0;
+    i64 off = 0;
+    if (t < NCAND) {
+      const int iy = t % NC, iz = t / NC;
+      const int fy = 2 * cy - 2 * DEG + iy;
+      w = wrow(fy, cy, g.ncell_f[1], g.fdim[1]);
+      int fz = 0;
+      if (DIM == 3) {
+        fz = 2 * cz - 2 * DEG + iz;
+        w *= wrow(fz, cz, g.ncell_f[2], g.fdim[2]);
+      }
+      off = (i64)g.fdim[0] * (fy + (i64)g.fdim[1] * fz);
+    }
+    const bool nzw = w != T(0);
+    const unsigned long long m = __ballot(nzw);
+    const int lane = t % 64, wave = t / 64;
+    const int before = __popcll(m & ((1ull << lane) - 1ull));
+    if (lane == 0) s_cnt[wave] = __popcll(m);
+    __syncthreads();
+    int base = 0;
+    for (int v = 0; v < wave; ++v) base += s_cnt[v];
+    if (nzw) {
+      s_w[base + before] = w;
+      s_off[base + before] = off;
+    }
+    __syncthreads();
+  }
+  const int nrow = s_cnt[0] + s_cnt[1] + s_cnt[2] + s_cnt[3];
+
+  // 1. fine row
   for (int fx = fx_lo + (int)threadIdx.x; fx <= fx_hi; fx += 256) {
     const bool xbc = BC && (fx == 0 || fx == g.fdim[0] - 1);
     T s = 0;
-    const int fz_lo = DIM == 3 ? (2 * cz - 2 * DEG > 0 ? 2 * cz - 2 * DEG : 0) : 0;
-    const int fz_hi = DIM == 3 ? (2 * cz + 2 * DEG < g.fdim[2] - 1 ? 2 * cz + 2 * DEG : g.fdim[2] - 1) : 0;
-    for (int fz = fz_lo; fz <= fz_hi; ++fz) {
-      T wz = 1;
-      if (DIM == 3) {
-        int cc, pos;
-        fine_pos<DEG>(fz, g.ncell_f[2], cc, pos);
-        const int j = cz - DEG * cc;
-        if (j < 0 || j > DEG) continue;
-        wz = g.W[pos * ND + j];
-        if (wz == T(0)) continue;
-        if (BC && (fz == 0 || fz == g.fdim[2] - 1)) continue;
+    for (int r0 = 0; r0 < nrow; r0 += UNR) {
+      T v[UNR], w[UNR];
+#pragma unroll
+      for (int u = 0; u < UNR; ++u) {
+        const int r = r0 + u < nrow ? r0 + u : r0;
+        w[u] = r0 + u < nrow ? s_w[r] : T(0);
+        v[u] = src[s_off[r] + fx];
       }
-      const int fy_lo = 2 * cy - 2 * DEG > 0 ? 2 * cy - 2 * DEG : 0;
-      const int fy_hi = 2 * cy + 2 * DEG < g.fdim[1] - 1 ? 2 * cy + 2 * DEG : g.fdim[1] - 1;
-      for (int fy = fy_lo; fy <= fy_hi; ++fy) {
-        int cc, pos;
-        fine_pos<DEG>(fy, g.ncell_f[1], cc, pos);
-        const int j = cy - DEG * cc;
-        if (j < 0 || j > DEG) continue;
-        const T wy = g.W[pos * ND + j];
-        if (wy == T(0)) continue;
-        if (BC && (fy == 0 || fy == g.fdim[1] - 1)) continue;
-        s += wz * wy * src[fx + (i64)g.fdim[0] * (fy + (i64)g.fdim[1] * fz)];
-      }
+#pragma unroll
+      for (int u = 0; u < UNR; ++u) s += w[u] * v[u];
     }
     tmp[fx - fx_lo] = xbc ? T(0) : s;
   }
@@ -157,7 +215,7 @@ __global__ void __launch_bounds__(256) k_restrict(const T *__restrict__ rf, T *_
       fine_pos<DEG>(fx, g.ncell_f[0], cc, pos);
       const int j = cx - DEG * cc;
       if (j < 0 || j > DEG) continue;
-      s += g.W[pos * ND + j] * tmp[fx - fx_lo];
+      s += weight_at<DEG>(g.W, pos, j) * tmp[fx - fx_lo];
     }
   }
   rc[g.coff + (i64)comp * g.cstride + cx + (i64)g.cdim[0] * (cy + (i64)g.cdim[1] * cz)] = s;
