@@ -81,3 +81,41 @@ def sample_Kx(mesh, x, dofs, mu=1.0, gamma=0.0, rho=1.0, c_p=0.0):
                 s -= c_p * (Mp_t[c, li, :] @ p[pn[c]])
             out[n_i] = s
     return out
+
+
+def velocity_stencil(mesh, dofs):
+    """Velocity DoFs (same component) of the cells around each velocity DoF in
+    `dofs`: the entries a row of A reads."""
+    d, k = mesh.dim, mesh.k
+    Nv = mesh.n_vnode
+    out = set()
+    for g in dofs:
+        comp, node = divmod(int(g), Nv)
+        lat = mesh._unflat(np.array([node]), mesh.vel_dims)[0]
+        cells = np.array(_cells_touching(mesh, lat, k))
+        for n in mesh.cell_velocity_nodes(cells).ravel():
+            out.add(comp * Nv + int(n))
+    return np.array(sorted(out), dtype=np.int64)
+
+
+def sample_diag_A(mesh, dofs, mu=1.0, gamma=0.0, rho=1.0):
+    """diag(A) of the constrained velocity block at velocity DoFs `dofs`:
+    1 on Dirichlet DoFs, else the sum over the cells around the node of the
+    element matrix's diagonal entry."""
+    k = mesh.k
+    Nv = mesh.n_vnode
+    bnd = mesh.velocity_boundary_nodes()
+    mu_cell = mesh.mu(mu)
+    out = np.zeros(len(dofs))
+    for n_i, g in enumerate(dofs):
+        comp, node = divmod(int(g), Nv)
+        if bnd[node]:
+            out[n_i] = 1.0
+            continue
+        lat = mesh._unflat(np.array([node]), mesh.vel_dims)[0]
+        cells = np.array(_cells_touching(mesh, lat, k))
+        A_t, _, _, _ = element_matrices(mesh, cells, mu_cell[cells], gamma, rho)
+        vn = mesh.cell_velocity_nodes(cells)
+        out[n_i] = sum(A_t[c, li, li] for c in range(len(cells)) for li in np.nonzero(vn[c] == node)[0])
+    return out
+

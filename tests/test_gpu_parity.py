@@ -406,6 +406,43 @@ def test_full_size_2d_512_sampled_rows(dtype, tol):
     gpu.close()
 
 
+@pytest.mark.parametrize("dtype,tol", [(torch.float64, 1e-12), (torch.float32, 2e-5)])
+def test_full_size_2d_512_chebyshev_sampled_rows(dtype, tol):
+    """The kernel of the benchmark's roofline entry at full size: the FP32 /
+    FP64 Chebyshev application for A (k_A = 1) on the 512^2 level through
+    smg_chebyshev, on sampled rows against the oracle's recurrence (with k_A
+    = 1 a row needs only its own row of A d_0).  The eigenvalue bound is set
+    by the test so that both sides use the same one."""
+    from paper_2205_15770_amd import StokesMG
+    from oracle.mesh import BoxMesh
+    from oracle.rows import velocity_stencil, sample_diag_A
+    from oracle.smoother import chebyshev_apply, scaling_constant
+    gpu = StokesMG(dim=2, fe_degree=2, n_coarse=(8, 8), n_levels=7, gamma=1e3, rho=1.0)
+    L = 6
+    beta = 2.75
+    gpu.set_eigs(L, beta, 1.5)
+    nu, _ = gpu.sizes(L)
+    r = si.uniform(nu, 123)
+    y = gpu.chebyshev(L, 0, _dev(r, dtype)).cpu().numpy().astype(np.float64)
+    mesh = BoxMesh(2, (512, 512), 2)
+    rng = np.random.default_rng(8)
+    dofs = np.unique(np.concatenate([rng.integers(0, nu, 200), np.arange(0, 20), np.arange(nu - 20, nu),
+                                     [1025 * 30 + 30, 1025 * 60 + 61, 1025 * 1025 + 1025 * 7 + 13]]))
+    need = velocity_stencil(mesh, dofs)
+    dinv = np.ones(nu)
+    dinv[need] = 1.0 / sample_diag_A(mesh, need, gamma=1e3, rho=1.0)
+    rin = r if dtype == torch.float64 else r.astype(np.float32).astype(np.float64)
+
+    def rows_of_A(v):   # A v on the sampled rows (the only rows the result is read at)
+        out = np.zeros(nu)
+        out[dofs] = sample_Kx(mesh, np.concatenate([v, np.zeros(mesh.n_pnode)]), dofs, gamma=1e3, rho=1.0)
+        return out
+
+    ref = scaling_constant(1) * chebyshev_apply(rows_of_A, dinv, rin, 1, beta)
+    assert np.linalg.norm(y[dofs] - ref[dofs]) / np.linalg.norm(ref[dofs]) < tol
+    gpu.close()
+
+
 def _sampled_dofs(n, nu, lat_v, extra, seed):
     rng = np.random.default_rng(seed)
     return np.unique(np.concatenate([rng.integers(0, n, 400), np.arange(0, 40), np.arange(n - 40, n),

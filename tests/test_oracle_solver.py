@@ -307,6 +307,21 @@ def test_sampled_rows_match_assembled_matrix():
     assert np.allclose(ys, y[dofs], rtol=1e-13, atol=1e-13)
 
 
+def test_sampled_diagonal_and_stencil_match_assembled_matrix():
+    from oracle.rows import sample_diag_A, velocity_stencil
+    V = si.perturbed_box_vertices(4, dim=2, amplitude=0.2, seed=9)
+    mesh = BoxMesh(2, (4, 4), 2, vertices=V, mu_cell=np.linspace(1, 3, 16))
+    asm = Assembled(mesh, gamma=2.0, rho=0.5)
+    nu = asm.A.shape[0]
+    dofs = np.arange(0, nu, 5)
+    assert np.allclose(sample_diag_A(mesh, dofs, gamma=2.0, rho=0.5), asm.A.diagonal()[dofs], rtol=1e-14)
+    # the stencil holds every column a free row of the constrained A reads
+    Au = asm.A_unconstrained.tocsr()
+    st = set(velocity_stencil(mesh, dofs).tolist())
+    for g in dofs:
+        assert set(Au.indices[Au.indptr[g]:Au.indptr[g + 1]].tolist()) <= st
+
+
 # --------------------------------------------------------------------------
 # multigrid behaviour (Sec. 3.1, 4.3-4.6) -- qualitative
 # --------------------------------------------------------------------------
