@@ -848,35 +848,26 @@ class EngineT : public EngineBase {
     return g;
   }
 
+  // both fields in one launch each (see k_prolong / k_restrict)
   template <typename T>
   void prolongate_t(int lf, const T *wc, T *xf) {
-    for (int field = 0; field < 2; ++field) {
-      const bool vel = field == 0;
-      const XferGeo<T> g = xfer_geo<T>(lf, vel);
-      const unsigned nz = (unsigned)((DIM == 3 ? g.fdim[2] : 1) * (vel ? DIM : 1));
-      const dim3 grid((unsigned)(((int64_t)g.fdim[0] * g.fdim[1] + 255) / 256), nz);
-      if (vel)
-        hipLaunchKernelGGL((k_prolong<T, DIM, K, true>), grid, dim3(256), 0, stream, wc, xf, g);
-      else
-        hipLaunchKernelGGL((k_prolong<T, DIM, K - 1, false>), grid, dim3(256), 0, stream, wc, xf, g);
-      check_launch();
-    }
+    const XferGeo<T> gv = xfer_geo<T>(lf, true), gp = xfer_geo<T>(lf, false);
+    const int nzv = (DIM == 3 ? gv.fdim[2] : 1) * DIM, nzp = DIM == 3 ? gp.fdim[2] : 1;
+    const int64_t nxy = std::max((int64_t)gv.fdim[0] * gv.fdim[1], (int64_t)gp.fdim[0] * gp.fdim[1]);
+    const dim3 grid((unsigned)((nxy + 255) / 256), (unsigned)(nzv + nzp));
+    hipLaunchKernelGGL((k_prolong<T, DIM, K>), grid, dim3(256), 0, stream, wc, xf, gv, gp, nzv);
+    check_launch();
   }
 
   template <typename T>
   void restrict_t(int lf, const T *rf, T *rc) {
     constexpr int CX = 128;
-    for (int field = 0; field < 2; ++field) {
-      const bool vel = field == 0;
-      const XferGeo<T> g = xfer_geo<T>(lf, vel);
-      const unsigned nz = (unsigned)((DIM == 3 ? g.cdim[2] : 1) * (vel ? DIM : 1));
-      const dim3 grid((unsigned)((g.cdim[0] + CX - 1) / CX), (unsigned)g.cdim[1], nz);
-      if (vel)
-        hipLaunchKernelGGL((k_restrict<T, DIM, K, true, CX>), grid, dim3(256), 0, stream, rf, rc, g);
-      else
-        hipLaunchKernelGGL((k_restrict<T, DIM, K - 1, false, CX>), grid, dim3(256), 0, stream, rf, rc, g);
-      check_launch();
-    }
+    const XferGeo<T> gv = xfer_geo<T>(lf, true), gp = xfer_geo<T>(lf, false);
+    const int nzv = (DIM == 3 ? gv.cdim[2] : 1) * DIM, nzp = DIM == 3 ? gp.cdim[2] : 1;
+    const int nx = std::max(gv.cdim[0], gp.cdim[0]), ny = std::max(gv.cdim[1], gp.cdim[1]);
+    const dim3 grid((unsigned)((nx + CX - 1) / CX), (unsigned)ny, (unsigned)(nzv + nzp));
+    hipLaunchKernelGGL((k_restrict<T, DIM, K, CX>), grid, dim3(256), 0, stream, rf, rc, gv, gp, nzv);
+    check_launch();
   }
 
   // --------------------------------------------------------- coarse solve

@@ -54,13 +54,14 @@ __device__ __forceinline__ T weight_at(const T *W, int pos, int j) {
 // (deg+1)^d coarse values of the node's support are requested at once (zero
 // weights included; coarse Dirichlet nodes get weight 0).
 template <typename T, int DIM, int DEG, bool BC>
-__global__ void __launch_bounds__(256) k_prolong(const T *__restrict__ wc, T *__restrict__ xf, const XferGeo<T> g) {
+__device__ __forceinline__ void prolong_block(const T *__restrict__ wc, T *__restrict__ xf, const XferGeo<T> &g, int bx,
+                                              int by) {
   constexpr int ND = DEG + 1;
   const int nxy = g.fdim[0] * g.fdim[1];
-  const int t = blockIdx.x * 256 + threadIdx.x;
+  const int t = bx * 256 + threadIdx.x;
   const int nz = DIM == 3 ? g.fdim[2] : 1;
-  const int comp = blockIdx.y / nz;
-  const int fz = blockIdx.y - comp * nz;
+  const int comp = by / nz;
+  const int fz = by - comp * nz;
   if (t >= nxy) return;
   const int fy = t / g.fdim[0];
   const int fx = t - fy * g.fdim[0];
@@ -115,7 +116,8 @@ __global__ void __launch_bounds__(256) k_prolong(const T *__restrict__ wc, T *__
 // node's x weights to the row.  One pass over the fine vector, no
 // intermediate vectors.
 template <typename T, int DIM, int DEG, bool BC, int CX>
-__global__ void __launch_bounds__(256) k_restrict(const T *__restrict__ rf, T *__restrict__ rc, const XferGeo<T> g) {
+__device__ __forceinline__ void restrict_block(const T *__restrict__ rf, T *__restrict__ rc, const XferGeo<T> &g,
+                                               int bx, int by, int bz) {
   constexpr int NC = 4 * DEG + 1;  // candidate fine rows per direction
   constexpr int NCAND = DIM == 3 ? NC * NC : NC;
   static_assert(NCAND <= 256, "one candidate per thread");
@@ -125,11 +127,12 @@ __global__ void __launch_bounds__(256) k_restrict(const T *__restrict__ rf, T *_
   __shared__ T s_w[NCAND];
   __shared__ i64 s_off[NCAND];
   __shared__ int s_cnt[4];
-  const int cx0 = blockIdx.x * CX;
-  const int cy = blockIdx.y;
+  const int cx0 = bx * CX;
+  if (cx0 >= g.cdim[0] || by >= g.cdim[1]) return;  // whole block: beyond this field's lattice
+  const int cy = by;
   const int nz = DIM == 3 ? g.cdim[2] : 1;
-  const int comp = blockIdx.z / nz;
-  const int cz = blockIdx.z - comp * nz;
+  const int comp = bz / nz;
+  const int cz = bz - comp * nz;
   int fx_lo = 2 * cx0 - 2 * DEG;
   if (fx_lo < 0) fx_lo = 0;
   int fx_hi = 2 * (cx0 + CX - 1) + 2 * DEG;
@@ -219,6 +222,24 @@ __global__ void __launch_bounds__(256) k_restrict(const T *__restrict__ rf, T *_
     }
   }
   rc[g.coff + (i64)comp * g.cstride + cx + (i64)g.cdim[0] * (cy + (i64)g.cdim[1] * cz)] = s;
+}
+
+// Both fields of a level pair in one launch: blocks [0, nv) of the field
+// dimension (y for the prolongation, z for the restriction) carry the
+// velocity components (degree K, Dirichlet rows), the rest the pressure
+// (degree K - 1); the grid's other extents are those of the larger field.
+template <typename T, int DIM, int K>
+__global__ void __launch_bounds__(256) k_prolong(const T *__restrict__ wc, T *__restrict__ xf, const XferGeo<T> gv,
+                                                 const XferGeo<T> gp, int nv) {
+  if ((int)blockIdx.y < nv) prolong_block<T, DIM, K, true>(wc, xf, gv, blockIdx.x, blockIdx.y);
+  else prolong_block<T, DIM, K - 1, false>(wc, xf, gp, blockIdx.x, blockIdx.y - nv);
+}
+
+template <typename T, int DIM, int K, int CX>
+__global__ void __launch_bounds__(256) k_restrict(const T *__restrict__ rf, T *__restrict__ rc, const XferGeo<T> gv,
+                                                  const XferGeo<T> gp, int nv) {
+  if ((int)blockIdx.z < nv) restrict_block<T, DIM, K, true, CX>(rf, rc, gv, blockIdx.x, blockIdx.y, blockIdx.z);
+  else restrict_block<T, DIM, K - 1, false, CX>(rf, rc, gp, blockIdx.x, blockIdx.y, blockIdx.z - nv);
 }
 
 }  // namespace smg
