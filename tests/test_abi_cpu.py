@@ -40,13 +40,14 @@ def test_desc_default_values():
     assert (d.cheb_deg_A, d.cheb_deg_S, d.smooth_steps, d.cycle_index) == (1, 1, 2, 1)
     assert d.mu == 1.0 and d.rho == 1.0 and d.gamma == 0.0 and d.c_pressure == 0.0
     assert d.fgmres_restart == 30
+    assert d.form == _lib.SMG_FORM_GRAD and d.schur_diag == _lib.SMG_SCHUR_D
 
 
 @pytest.mark.parametrize("field,value,code", [
     ("dim", 4, -1), ("fe_degree", 1, -1), ("fe_degree", 4, -6), ("n_levels", 1, -1),
     ("smooth_steps", 0, -1), ("cycle_index", 3, -1), ("schur_diag", 5, -1), ("precision", 7, -1),
     ("fgmres_restart", 0, -1), ("cheb_deg_A", -1, -1), ("gamma", -1.0, -1), ("mu", 0.0, -1),
-    ("rho", 0.0, -1), ("c_pressure", -0.5, -1),
+    ("rho", 0.0, -1), ("c_pressure", -0.5, -1), ("schur_diag", 4, -1), ("form", 2, -1),
 ])
 def test_invalid_descriptors_rejected_without_device(field, value, code):
     from paper_2205_15770_amd import _lib
@@ -83,3 +84,23 @@ def test_null_arguments_rejected():
     assert lib.smg_solve(None, None, None, 1e-8, 10, None) == -1
     assert lib.smg_destroy(None) == 0
     assert b"null" in lib.smg_last_error() or lib.smg_last_error() == b""
+
+
+def test_unsupported_combinations_rejected_without_device():
+    from paper_2205_15770_amd import _lib
+    lib = _lib.load()
+    d = _lib.SmgDesc()
+    lib.smg_desc_default(ctypes.byref(d))
+    d.form = _lib.SMG_FORM_EPS
+    d.schur_diag = _lib.SMG_SCHUR_LOC        # needs box cells and the gradient form
+    h = ctypes.c_void_p()
+    assert lib.smg_create(ctypes.byref(d), ctypes.byref(h)) == -6
+    assert h.value is None
+
+
+def test_dirichlet_entry_points_reject_null_arguments():
+    from paper_2205_15770_amd import _lib
+    lib = _lib.load()
+    assert lib.smg_lift_dirichlet(None, 0, 0, None, None) == -1
+    assert lib.smg_insert_dirichlet(None, 0, 0, None, None) == -1
+
