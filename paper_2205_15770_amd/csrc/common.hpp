@@ -37,6 +37,7 @@ struct LevelGeom {
   const T *mu_cell;
   const T *verts;  // vertex coordinates of general cells (nullptr: box cells)
   T *gs;           // scratch of length N for the general-cell path
+  T *cbu, *cbp;    // per-cell results of the general-cell path (every-cell mode)
   double h[3];     // cell widths
   Coef1D<T, K> c[DIM];
 };

@@ -36,6 +36,7 @@ struct Work {
   T *rp = nullptr, *dp = nullptr;                     // pressure (Np)
   T *sr = nullptr, *sx = nullptr, *sd[2] = {nullptr, nullptr};  // Chebyshev state, S~
   T *t1 = nullptr, *t2 = nullptr;                     // scratch (length N): general-cell accumulation
+  T *cbu = nullptr, *cbp = nullptr;                   // general cells: per-cell results (cells x d x (k+1)^d, cells x k^d)
   T *dinvA = nullptr, *dinvS = nullptr;               // inverse diagonals
   T *mu_cell = nullptr;                               // per-cell viscosity (optional)
   T *verts = nullptr;                                 // vertex coordinates (general cells)

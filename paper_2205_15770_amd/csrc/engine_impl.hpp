@@ -199,6 +199,8 @@ class EngineT : public EngineBase {
     g.mu_cell = work<T>(l).mu_cell;
     g.verts = work<T>(l).verts;
     g.gs = work<T>(l).t1;
+    g.cbu = work<T>(l).cbu;
+    g.cbp = work<T>(l).cbp;
     for (int a = 0; a < 3; ++a) g.h[a] = I.h[a];
     const int nv = K + 1, np = K;
     for (int a = 0; a < DIM; ++a) {
@@ -360,6 +362,27 @@ class EngineT : public EngineBase {
     gg.tu = g.gs;
     gg.tp = g.gs + (int64_t)DIM * g.Nv;
     const int64_t n_all = (int64_t)DIM * g.Nv + g.Np;
+    if (g.cbu != nullptr) {
+      // every cell in one launch, results per cell; the epilogue sums them
+      // per node (two launches instead of 2^d colours + epilogue)
+      constexpr int NN = DIM == 3 ? (K + 1) * (K + 1) * (K + 1) : (K + 1) * (K + 1);
+      constexpr int CPB = 64 / NN;
+      gg.step = 1;
+      for (int a = 0; a < 3; ++a) {
+        gg.off[a] = 0;
+        gg.ncol[a] = a < DIM ? gg.n[a] : 1;
+      }
+      gg.cbu = g.cbu;
+      gg.cbp = g.cbp;
+      const int64_t ncells = (int64_t)gg.n[0] * gg.n[1] * (DIM == 3 ? gg.n[2] : 1);
+      hipLaunchKernelGGL((gen_apply_kernel<DIM, K, T, BLK, Op>), dim3((unsigned)((ncells + CPB - 1) / CPB)), dim3(64), 0,
+                         stream, gg, op);
+      check_launch();
+      hipLaunchKernelGGL((gen_gather_epilogue_kernel<DIM, K, T, BLK, Op>), dim3(grid_for(n_all)), dim3(VB), 0, stream,
+                         gg, op);
+      check_launch();
+      return;
+    }
     gen_accumulate<T, BLK, Op>(gg, op);
     hipLaunchKernelGGL((gen_epilogue_kernel<DIM, T, BLK, Op>), dim3(grid_for(n_all)), dim3(VB), 0, stream, gg, op);
     check_launch();
@@ -370,6 +393,9 @@ class EngineT : public EngineBase {
   void gen_accumulate(GenGeo<T> &gg, const Op &op) {
     const int64_t n_all = (int64_t)DIM * gg.Nv + gg.Np;
     vset<T>(gg.tu, (T)0, n_all);
+    gg.step = 2;
+    gg.cbu = nullptr;
+    gg.cbp = nullptr;
     constexpr int NN = DIM == 3 ? (K + 1) * (K + 1) * (K + 1) : (K + 1) * (K + 1);
     constexpr int CPB = 64 / NN;
     for (int colour = 0; colour < (1 << DIM); ++colour) {
@@ -1263,6 +1289,16 @@ class EngineT : public EngineBase {
       I.mp1 = dalloc<double>(I.Np);
       lv[l].w64.t1 = dalloc<double>(I.N);
       lv[l].w32.t1 = dalloc<float>(I.N);
+      if (general) {
+        // per-cell results of the one-launch general-cell operator
+        constexpr int64_t NN = DIM == 3 ? (K + 1) * (K + 1) * (K + 1) : (K + 1) * (K + 1);
+        constexpr int64_t NPN = DIM == 3 ? K * K * K : K * K;
+        const int64_t nc = (int64_t)I.n[0] * I.n[1] * (DIM == 3 ? I.n[2] : 1);
+        lv[l].w64.cbu = dalloc<double>(nc * DIM * NN);
+        lv[l].w64.cbp = dalloc<double>(nc * NPN);
+        lv[l].w32.cbu = dalloc<float>(nc * DIM * NN);
+        lv[l].w32.cbp = dalloc<float>(nc * NPN);
+      }
       auto g = geom<double>(l);
       if (general) {
         probe_diagonals(l);

@@ -34,6 +34,8 @@ struct GenGeo {
   const T *verts;   // (n+1)^d vertices x d coordinates, x fastest
   T *tu, *tp;       // accumulated cell sums (velocity [u_1|..|u_d], pressure)
   int sym;          // viscous term mu eps(u):eps(v) instead of mu grad u : grad v
+  int step;         // 2: one colour (cells off + 2 i), 1: every cell
+  T *cbu, *cbp;     // every-cell mode: per-cell results [cell][comp][node], [cell][pressure node]
 };
 
 // a[i] for a lane-dependent i without dynamic indexing into private memory
@@ -70,10 +72,11 @@ __global__ void __launch_bounds__(64) gen_apply_kernel(const GenGeo<T> g, const 
   int cx = 0, cy = 0, cz = 0;
   if (live) {
     const i64 r = ci / g.ncol[0];
-    cx = 2 * (int)(ci - r * g.ncol[0]) + g.off[0];
-    cy = 2 * (int)(r % g.ncol[1]) + g.off[1];
-    cz = DIM == 3 ? 2 * (int)(r / g.ncol[1]) + g.off[2] : 0;
+    cx = g.step * (int)(ci - r * g.ncol[0]) + g.off[0];
+    cy = g.step * (int)(r % g.ncol[1]) + g.off[1];
+    cz = DIM == 3 ? g.step * (int)(r / g.ncol[1]) + g.off[2] : 0;
   }
+  const i64 cell = cx + (i64)g.n[0] * (cy + (i64)g.n[1] * cz);
   const int qx = q % NV, qy = (q / NV) % NV, qz = DIM == 3 ? q / (NV * NV) : 0;
   const int qd[3] = {qx, qy, qz};
   T *A = lds[sl][0], *Bf = lds[sl][1], *Cf = lds[sl][2];
@@ -333,7 +336,10 @@ __global__ void __launch_bounds__(64) gen_apply_kernel(const GenGeo<T> g, const 
         t = pass(A, cV[2], 2);
       }
       __syncthreads();
-      if (live) g.tu[(i64)c * g.Nv + vnode] += t;
+      if (live) {
+        if (g.cbu != nullptr) g.cbu[(cell * DIM + c) * NN + q] = t;
+        else g.tu[(i64)c * g.Nv + vnode] += t;
+      }
     }
   }
 
@@ -389,8 +395,12 @@ __global__ void __launch_bounds__(64) gen_apply_kernel(const GenGeo<T> g, const 
         }
       }
       if (live && q < NPN) {
-        const i64 pn = ((K - 1) * cx + ox) + (i64)g.pd[0] * (((K - 1) * cy + oy) + (i64)g.pd[1] * ((K - 1) * cz + oz));
-        g.tp[pn] += s;
+        if (g.cbp != nullptr) {
+          g.cbp[cell * NPN + q] = s;
+        } else {
+          const i64 pn = ((K - 1) * cx + ox) + (i64)g.pd[0] * (((K - 1) * cy + oy) + (i64)g.pd[1] * ((K - 1) * cz + oz));
+          g.tp[pn] += s;
+        }
       }
     }
   }
@@ -421,6 +431,83 @@ __global__ void gen_epilogue_kernel(const GenGeo<T> g, const Op op) {
     } else {
       const i64 j = i - nu;
       op.store_p(j, g.tp[j], NEED_P ? op.load_p(j) : T(0), op.fetch_p(j));
+    }
+  }
+}
+
+// Every-cell mode: the sum over the cells around a lattice node of their
+// per-cell results, cells in increasing index order (fixed summation order).
+// deg: node spacing per cell (K for the velocity, K - 1 for the pressure);
+// nn: results per cell and component; lattice node (x, y, z).
+template <int DIM, int DEG, int NPC, typename T>
+__device__ __forceinline__ T gather_cells(const GenGeo<T> &g, const T *cb, int ncomp, int comp, int x, int y, int z) {
+  int c0[3], nc[3];
+  const int xyz[3] = {x, y, z};
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    if (a >= DIM) {
+      c0[a] = 0;
+      nc[a] = 1;
+      continue;
+    }
+    const int c = xyz[a] / DEG;
+    if (xyz[a] % DEG == 0) {
+      // a cell boundary: the cells on both sides that exist
+      c0[a] = c > 0 ? c - 1 : 0;
+      nc[a] = (c > 0 ? 1 : 0) + (c < g.n[a] ? 1 : 0);
+    } else {
+      c0[a] = c;
+      nc[a] = 1;
+    }
+  }
+  constexpr int NS = DEG + 1;  // nodes per cell and direction
+  T acc = 0;
+  for (int k = 0; k < nc[2]; ++k)
+    for (int j = 0; j < nc[1]; ++j)
+      for (int i = 0; i < nc[0]; ++i) {
+        const int cx = c0[0] + i, cy = c0[1] + j, cz = c0[2] + k;
+        const int lx = x - DEG * cx, ly = y - DEG * cy, lz = z - DEG * cz;
+        const i64 cell = cx + (i64)g.n[0] * (cy + (i64)g.n[1] * cz);
+        acc += cb[(cell * ncomp + comp) * NPC + lx + NS * (ly + NS * lz)];
+      }
+  return acc;
+}
+
+// Every-cell mode epilogue: sums of the per-cell results, then the Dirichlet
+// rows and the caller's epilogue as in gen_epilogue_kernel.
+template <int DIM, int K, typename T, int BLK, class Op>
+__global__ void gen_gather_epilogue_kernel(const GenGeo<T> g, const Op op) {
+  constexpr int NV = K + 1, NP = K;
+  constexpr int NN = DIM == 3 ? NV * NV * NV : NV * NV;
+  constexpr int NPN = DIM == 3 ? NP * NP * NP : NP * NP;
+  constexpr bool NEED_U = (BLK & (BLK_A | BLK_MASS | BLK_B)) != 0;
+  constexpr bool NEED_P = (BLK & (BLK_BT | BLK_C)) != 0;
+  constexpr bool OUT_U = (BLK & (BLK_A | BLK_MASS | BLK_BT)) != 0;
+  constexpr bool OUT_P = (BLK & (BLK_B | BLK_C)) != 0;
+  const i64 nu = OUT_U ? (i64)DIM * g.Nv : 0;
+  const i64 total = nu + (OUT_P ? g.Np : 0);
+  SMG_GRID_LOOP(i, total) {
+    if (i < nu) {
+      const int c = (int)(i / g.Nv);
+      const i64 node = i - (i64)c * g.Nv;
+      const int x = (int)(node % g.vd[0]);
+      const i64 r = node / g.vd[0];
+      const int y = (int)(r % g.vd[1]);
+      const int z = (int)(r / g.vd[1]);
+      const bool bc = on_box_boundary(x, g.vd[0]) || on_box_boundary(y, g.vd[1]) ||
+                      (DIM == 3 && on_box_boundary(z, g.vd[2]));
+      const T v = NEED_U ? op.load_u(i) : T(0);
+      const T tsum = bc ? T(0) : gather_cells<DIM, K, NN>(g, g.cbu, DIM, c, x, y, z);
+      const T t = bc ? ((BLK & BLK_A) != 0 ? v : T(0)) : tsum;
+      op.store_u(i, t, bc ? t : v, bc, op.fetch_u(i));
+    } else {
+      const i64 j = i - nu;
+      const int x = (int)(j % g.pd[0]);
+      const i64 r = j / g.pd[0];
+      const int y = (int)(r % g.pd[1]);
+      const int z = (int)(r / g.pd[1]);
+      const T t = gather_cells<DIM, K - 1, NPN>(g, g.cbp, 1, 0, x, y, z);
+      op.store_p(j, t, NEED_P ? op.load_p(j) : T(0), op.fetch_p(j));
     }
   }
 }
