@@ -885,14 +885,15 @@ class EngineT : public EngineBase {
     check_launch();
   }
 
+  // zc (optional): a coarse vector zeroed in the same pass
   template <typename T>
-  void restrict_t(int lf, const T *rf, T *rc) {
+  void restrict_t(int lf, const T *rf, T *rc, T *zc = nullptr) {
     constexpr int CX = 128;
     const XferGeo<T> gv = xfer_geo<T>(lf, true), gp = xfer_geo<T>(lf, false);
     const int nzv = (DIM == 3 ? gv.cdim[2] : 1) * DIM, nzp = DIM == 3 ? gp.cdim[2] : 1;
     const int nx = std::max(gv.cdim[0], gp.cdim[0]), ny = std::max(gv.cdim[1], gp.cdim[1]);
     const dim3 grid((unsigned)((nx + CX - 1) / CX), (unsigned)ny, (unsigned)(nzv + nzp));
-    hipLaunchKernelGGL((k_restrict<T, DIM, K, CX>), grid, dim3(256), 0, stream, rf, rc, gv, gp, nzv);
+    hipLaunchKernelGGL((k_restrict<T, DIM, K, CX>), grid, dim3(256), 0, stream, rf, rc, zc, gv, gp, nzv);
     check_launch();
   }
 
@@ -916,8 +917,7 @@ class EngineT : public EngineBase {
     Work<T> &C = work<T>(l - 1);
     smooth_t<T>(l, x, b, desc.smooth_steps, zero_init);
     residual_t<T>(l, x, b, W.r);
-    restrict_t<T>(l, W.r, C.b);
-    vset<T>(C.x, (T)0, lv[l - 1].N);
+    restrict_t<T>(l, W.r, C.b, C.x);   // also C.x = 0
     for (int j = 0; j < desc.cycle_index; ++j) cycle_t<T>(l - 1, C.x, C.b, j == 0);
     prolongate_t<T>(l, C.x, x);
     smooth_t<T>(l, x, b, desc.smooth_steps, false);

@@ -116,8 +116,8 @@ __device__ __forceinline__ void prolong_block(const T *__restrict__ wc, T *__res
 // node's x weights to the row.  One pass over the fine vector, no
 // intermediate vectors.
 template <typename T, int DIM, int DEG, bool BC, int CX>
-__device__ __forceinline__ void restrict_block(const T *__restrict__ rf, T *__restrict__ rc, const XferGeo<T> &g,
-                                               int bx, int by, int bz) {
+__device__ __forceinline__ void restrict_block(const T *__restrict__ rf, T *__restrict__ rc, T *__restrict__ zc,
+                                               const XferGeo<T> &g, int bx, int by, int bz) {
   constexpr int NC = 4 * DEG + 1;  // candidate fine rows per direction
   constexpr int NCAND = DIM == 3 ? NC * NC : NC;
   static_assert(NCAND <= 256, "one candidate per thread");
@@ -221,7 +221,9 @@ __device__ __forceinline__ void restrict_block(const T *__restrict__ rf, T *__re
       s += weight_at<DEG>(g.W, pos, j) * tmp[fx - fx_lo];
     }
   }
-  rc[g.coff + (i64)comp * g.cstride + cx + (i64)g.cdim[0] * (cy + (i64)g.cdim[1] * cz)] = s;
+  const i64 ci = g.coff + (i64)comp * g.cstride + cx + (i64)g.cdim[0] * (cy + (i64)g.cdim[1] * cz);
+  rc[ci] = s;
+  if (zc != nullptr) zc[ci] = T(0);  // the coarse iterate starts at zero (Algorithm 1)
 }
 
 // Both fields of a level pair in one launch: blocks [0, nv) of the field
@@ -235,11 +237,13 @@ __global__ void __launch_bounds__(256) k_prolong(const T *__restrict__ wc, T *__
   else prolong_block<T, DIM, K - 1, false>(wc, xf, gp, blockIdx.x, blockIdx.y - nv);
 }
 
+// zc (optional): a coarse vector set to zero on every entry written, in the
+// same pass.
 template <typename T, int DIM, int K, int CX>
-__global__ void __launch_bounds__(256) k_restrict(const T *__restrict__ rf, T *__restrict__ rc, const XferGeo<T> gv,
-                                                  const XferGeo<T> gp, int nv) {
-  if ((int)blockIdx.z < nv) restrict_block<T, DIM, K, true, CX>(rf, rc, gv, blockIdx.x, blockIdx.y, blockIdx.z);
-  else restrict_block<T, DIM, K - 1, false, CX>(rf, rc, gp, blockIdx.x, blockIdx.y, blockIdx.z - nv);
+__global__ void __launch_bounds__(256) k_restrict(const T *__restrict__ rf, T *__restrict__ rc, T *__restrict__ zc,
+                                                  const XferGeo<T> gv, const XferGeo<T> gp, int nv) {
+  if ((int)blockIdx.z < nv) restrict_block<T, DIM, K, true, CX>(rf, rc, zc, gv, blockIdx.x, blockIdx.y, blockIdx.z);
+  else restrict_block<T, DIM, K - 1, false, CX>(rf, rc, zc, gp, blockIdx.x, blockIdx.y, blockIdx.z - nv);
 }
 
 }  // namespace smg
