@@ -103,6 +103,7 @@ class EngineT : public EngineBase {
   Ref1D ref;
   TransferTables ttab;
   bool general = false;                      // cells given by vertices
+  bool gen_op = false;                       // operator through the vertex-given cell kernel
   int block3d_max_n = block3d_max_n_from_env();
   int split2d_max_n = split2d_max_n_from_env();
   int sweep_waves = sweep_waves_from_env();
@@ -250,14 +251,13 @@ class EngineT : public EngineBase {
 
   template <typename T, int BLK, class Op>
   void tile(const LevelGeom<T, DIM, K> &g, const Op &op) {
-    const unsigned nblk = (unsigned)(g.tiles[0] * g.tiles[1] * g.tiles[2]);
     hipEvent_t ea = nullptr, eb = nullptr;
     if (profiling) {
       ea = next_event();
       eb = next_event();
       SMG_HIP(hipEventRecord(ea, stream));
     }
-    if (general) {
+    if (gen_op) {
       gen_tile<T, BLK, Op>(g, op);
     } else if constexpr (DIM == 2) {
       // 8 x 8 cells per wave, one cell per lane
@@ -274,10 +274,8 @@ class EngineT : public EngineBase {
         hipLaunchKernelGGL((wave2d_kernel<K, T, BLK, Op>), dim3(nb2), dim3(64), 0, stream, g2, op);
       }
     } else if constexpr (K != 2) {
-      // Q3-Q2 in 3D: colour-phase tile kernel (the column sweep is built for
-      // Q2-Q1 only; its Q3 variants spill to scratch and are switched off)
-      hipLaunchKernelGGL((tile_apply_kernel<DIM, K, T, BLK, Op, TX, TY, TZ>), dim3(nblk), dim3(TX * TY * TZ), 0, stream,
-                         g, op);
+      // Q3-Q2 in 3D always runs on the vertex-given cell kernel (gen_op)
+      throw Error{SMG_EUNSUPPORTED, "3D Q3-Q2 box kernel"};
     } else {
       // 8 x 8 cell columns per wave, one wave per output field; the z extent
       // is cut into chunks so that the launch has about sweep_waves waves
@@ -1237,11 +1235,14 @@ class EngineT : public EngineBase {
     dvec = dalloc<double>(1024);
     // general cells: vertex coordinates of every level (level l takes the
     // finest-level vertex at the same lattice point)
-    // the deformation-rate form runs on the vertex-given cell kernel: a box
-    // mesh is handed to it as its vertex lattice
+    // the deformation-rate form and Q3-Q2 in 3D run on the vertex-given cell
+    // kernel: a box mesh is handed to it as its vertex lattice (box-cell
+    // diagonals, node coordinates and the local Schur diagonal still apply
+    // to 3D Q3-Q2 box meshes)
     std::vector<double> lattice;
     const double *fverts = desc.fine_vertices;
-    if (!fverts && desc.form == SMG_FORM_EPS) {
+    general = desc.fine_vertices != nullptr || desc.form == SMG_FORM_EPS;
+    if (!fverts && (desc.form == SMG_FORM_EPS || (DIM == 3 && K == 3))) {
       const LevelInfo &F = lv[L];
       const int nz = DIM == 3 ? F.n[2] + 1 : 1;
       lattice.resize((size_t)(F.n[0] + 1) * (F.n[1] + 1) * nz * DIM);
@@ -1256,7 +1257,7 @@ class EngineT : public EngineBase {
       fverts = lattice.data();
     }
     if (fverts) {
-      general = true;
+      gen_op = true;
       hverts.resize(L + 1);
       const LevelInfo &F = lv[L];
       const int64_t fx = F.n[0] + 1, fy = F.n[1] + 1;
@@ -1289,7 +1290,7 @@ class EngineT : public EngineBase {
       I.mp1 = dalloc<double>(I.Np);
       lv[l].w64.t1 = dalloc<double>(I.N);
       lv[l].w32.t1 = dalloc<float>(I.N);
-      if (general) {
+      if (gen_op) {
         // per-cell results of the one-launch general-cell operator
         constexpr int64_t NN = DIM == 3 ? (K + 1) * (K + 1) * (K + 1) : (K + 1) * (K + 1);
         constexpr int64_t NPN = DIM == 3 ? K * K * K : K * K;
