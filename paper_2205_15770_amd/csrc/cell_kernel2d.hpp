@@ -293,6 +293,39 @@ wave2d_split_kernel(const Geo2<T> g, const Op op) {
 
 
 // ---------------------------------------------------------------------------
+// After hand_over_xy a lane holds the complete sums of its cell's nodes with
+// local indices [0, N-1) in both directions (and of the faces on the
+// domain's high boundary).  This fills the faces x = N-1 / y = N-1 and their
+// corner from the lanes that hold them completely: the right cell (lane + 1),
+// the upper cell (lane + TX) and the upper-right cell (lane + TX + 1).  On the
+// domain's high faces the local values are kept.  The result is the whole
+// cell on every lane whose right, upper and upper-right neighbours hold
+// complete sums.
+template <int TX, typename T, int N>
+__device__ __forceinline__ void gather_high_faces(T (&v)[N][N], bool bxh, bool byh) {
+  constexpr int E = N - 1;
+  T colE[E], rowE[E];
+#pragma unroll
+  for (int j = 0; j < E; ++j) colE[j] = __shfl_down(v[j][0], 1, 64);
+#pragma unroll
+  for (int i = 0; i < E; ++i) rowE[i] = __shfl_down(v[0][i], TX, 64);
+  const T c9 = __shfl_down(v[0][0], TX + 1, 64);   // (0, 0) of the upper-right cell
+  const T c8 = __shfl_down(v[0][E], TX, 64);       // (E, 0) of the upper cell (its right face is local)
+  const T c1 = __shfl_down(v[E][0], 1, 64);        // (0, E) of the right cell (its upper face is local)
+  if (!bxh) {
+#pragma unroll
+    for (int j = 0; j < E; ++j) v[j][E] = colE[j];
+  }
+  if (!byh) {
+#pragma unroll
+    for (int i = 0; i < E; ++i) v[E][i] = rowE[i];
+  }
+  if (!bxh && !byh) v[E][E] = c9;
+  else if (bxh && !byh) v[E][E] = c8;
+  else if (!bxh && byh) v[E][E] = c1;
+}
+
+// ---------------------------------------------------------------------------
 // Two operator applications in one launch (small levels, where a launch costs
 // more than its arithmetic): a velocity field v is formed by a first
 // application -- q = B^T d (OpGrad) or the residual r = f - A u - B^T p
@@ -423,27 +456,7 @@ wave2d_fused_kernel(const Geo2<T> g, const Op1 op1, const OpChebA<T, true, LAST>
       v[y][x] = vbc(x, y) ? bc_v : free_v;
     }
   // 3. right / upper faces and corner from the owners (lane + 1, + 8, + 9)
-  {
-    T colK[K], rowK[K];
-#pragma unroll
-    for (int j = 0; j < K; ++j) colK[j] = __shfl_down(v[j][0], 1, 64);
-#pragma unroll
-    for (int i = 0; i < K; ++i) rowK[i] = __shfl_down(v[0][i], TX, 64);
-    const T c9 = __shfl_down(v[0][0], TX + 1, 64);   // (0, 0) of the upper-right cell
-    const T c8 = __shfl_down(v[0][K], TX, 64);       // (K, 0) of the upper cell (its right face is local)
-    const T c1 = __shfl_down(v[K][0], 1, 64);        // (0, K) of the right cell (its upper face is local)
-    if (!bxh) {
-#pragma unroll
-      for (int j = 0; j < K; ++j) v[j][K] = colK[j];
-    }
-    if (!byh) {
-#pragma unroll
-      for (int i = 0; i < K; ++i) v[K][i] = rowK[i];
-    }
-    if (!bxh && !byh) v[K][K] = c9;
-    else if (bxh && !byh) v[K][K] = c8;
-    else if (!bxh && byh) v[K][K] = c1;
-  }
+  gather_high_faces<TX>(v, bxh, byh);
   // 4. second stage: t2 = A d0, d0 = D^-1 v / theta (inputs of the valid lanes only)
   T d0[1][NV][NV], t2[1][NV][NV];
 #pragma unroll
@@ -471,6 +484,255 @@ wave2d_fused_kernel(const Geo2<T> g, const Op1 op1, const OpChebA<T, true, LAST>
   for (int y = 0; y < K; ++y)
 #pragma unroll
     for (int x = 0; x < K; ++x) op2.store_u(u_at(x, y), t2[0][y][x], d0[0][y][x], false, pre_at(x, y, bs[y][x]));
+  if (bxl | byl) {
+#pragma unroll
+    for (int y = 0; y < K; ++y)
+#pragma unroll
+      for (int x = 0; x < K; ++x) {
+        if (!vbc(x, y)) continue;
+        const T rw = dv[y][x] * v[y][x] * op2.inv_theta;
+        op2.store_u(u_at(x, y), rw, rw, true, pre_at(x, y, bs[y][x]));
+      }
+  }
+  if (bxh | byh) {
+#pragma unroll
+    for (int y = 0; y < NV; ++y)
+#pragma unroll
+      for (int x = 0; x < NV; ++x) {
+        if (x < K && y < K) continue;
+        if ((x == K && !bxh) || (y == K && !byh)) continue;
+        const BOff gi = u_at(x, y);
+        const T rw = dv[y][x] * v[y][x] * op2.inv_theta;
+        op2.store_u(gi, rw, rw, true, pre_at(x, y, (LAST && op2.base) ? at(op2.base, gi) : T(0)));
+      }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Three operator applications in one launch (small levels, k_S = 1): a
+// pressure stage in front of the fused pair above.  Stage 0 applies B (and
+// C) to the pressure patch of every lane and turns the sums into a pressure
+// vector z; stage 1 forms q_c = B_c^T z; stage 2 is the first Chebyshev step
+// for A on q_c.  Each stage shrinks the region of complete sums by one cell
+// ring: the 8 x 8 tile owns 3 x 3 cells (halo: three rings below, two
+// above).  Stage 0 is one of
+//   F3_DIVRES: r_p = B u - C p - g (stored by the owners), z = D~_S^-1 r_p / theta_S,
+//              the Uzawa pressure residual and the first S~ direction;
+//   F3_CHEBS:  the only step of Cheb(S~, D~_S, 1): d_0 = D~_S^-1 r_0 / theta_S,
+//              t = B w + C d_0, z = tau (d_0 + c1 d_0 + c2 D~_S^-1 (r_0 - t)),
+//              p += z by the owners; z is the pressure update dp.
+// Both velocity components of u (w) are read by every wave; one wave per
+// (tile, velocity component), and the component-0 wave stores the pressure
+// output.  The arithmetic is that of the separate launches.
+enum : int { F3_DIVRES = 0, F3_CHEBS = 1 };
+
+template <typename T>
+struct Fuse3P {
+  const T *u;        // velocity input of B: u_hat (F3_DIVRES) or w (F3_CHEBS)
+  const T *p0;       // F3_DIVRES: pressure iterate of the C term
+  const T *g;        // F3_DIVRES: pressure right-hand side (nullable)
+  T *rp;             // F3_DIVRES: r_p
+  const T *rin;      // F3_CHEBS: r_0
+  const T *dinv_s;   // D~_S^-1
+  T *p;              // F3_CHEBS: pressure iterate, += dp (nullable)
+  T inv_theta, c1, c2, tau;  // of the S~ Chebyshev step
+};
+
+template <int K, typename T, int MODE, bool LAST>
+__global__ void __launch_bounds__(64)
+wave2d_fused3_kernel(const Geo2<T> g, const Fuse3P<T> P, const OpChebA<T, true, LAST> op2) {
+  constexpr int NV = K + 1, NP = K, TX = 8, OWN = TX - 5;
+  constexpr uint32_t ST = sizeof(T);
+  constexpr cfe::TabT<K, T> R = cfe::make_tab_t<K, T>();
+
+  const int bb = xcd_contiguous_tile(blockIdx.x, gridDim.x);
+  const int c = bb % 2, b = bb / 2;
+  const int tx = b % g.tiles[0], ty = b / g.tiles[0];
+  const int lcx = threadIdx.x % TX, lcy = threadIdx.x / TX;
+  const int gcx = tx * OWN - 3 + lcx, gcy = ty * OWN - 3 + lcy;
+  const bool active = gcx >= 0 && gcx < g.n[0] && gcy >= 0 && gcy < g.n[1];
+  const bool valid1 = active && lcx >= 1 && lcx <= TX - 2 && lcy >= 1 && lcy <= TX - 2;
+  const bool valid2 = active && lcx >= 2 && lcx <= TX - 3 && lcy >= 2 && lcy <= TX - 3;
+  const bool owner = active && lcx >= 3 && lcx <= TX - 3 && lcy >= 3 && lcy <= TX - 3;
+  const bool bxl = gcx == 0, bxh = gcx == g.n[0] - 1, byl = gcy == 0, byh = gcy == g.n[1] - 1;
+  const int ax = gcx < 0 ? 0 : (gcx >= g.n[0] ? g.n[0] - 1 : gcx);
+  const int ay = gcy < 0 ? 0 : (gcy >= g.n[1] ? g.n[1] - 1 : gcy);
+  const uint32_t suy = ST * (uint32_t)g.vd[0], spy = ST * (uint32_t)g.pd[0];
+  const uint32_t base_u0 = ST * (uint32_t)(K * ax) + suy * (uint32_t)(K * ay);
+  const uint32_t base_p = ST * (uint32_t)((K - 1) * ax) + spy * (uint32_t)((K - 1) * ay);
+  auto uc_at = [&](int cc, int x, int y) { return BOff{(uint32_t)cc * g.nv_bytes + base_u0 + suy * (uint32_t)y, ST * (uint32_t)x}; };
+  auto u_at = [&](int x, int y) { return uc_at(c, x, y); };
+  auto p_at = [&](int x, int y) { return BOff{base_p + spy * (uint32_t)y, ST * (uint32_t)x}; };
+  auto vbc = [&](int x, int y) { return ((x == 0) & bxl) | ((x == K) & bxh) | ((y == 0) & byl) | ((y == K) & byh); };
+  const bool has_c = g.cp != T(0);
+
+  // 1. requests: both velocity components and the pressure data of stage 0
+  //    on the whole cell, D_A^-1 of this component, the base vector
+  T uu[2][1][NV][NV], pa[NP][NP], ds[NP][NP], pc[1][NP][NP], dv[NV][NV], bs[K][K], pold[K - 1][K - 1];
+#pragma unroll
+  for (int cc = 0; cc < 2; ++cc)
+#pragma unroll
+    for (int y = 0; y < NV; ++y)
+#pragma unroll
+      for (int x = 0; x < NV; ++x) uu[cc][0][y][x] = at(P.u, uc_at(cc, x, y));
+#pragma unroll
+  for (int y = 0; y < NP; ++y)
+#pragma unroll
+    for (int x = 0; x < NP; ++x) {
+      ds[y][x] = at(P.dinv_s, p_at(x, y));
+      if constexpr (MODE == F3_DIVRES) pa[y][x] = P.g ? at(P.g, p_at(x, y)) : T(0);
+      else pa[y][x] = at(P.rin, p_at(x, y));
+      pc[0][y][x] = (MODE == F3_DIVRES && has_c) ? at(P.p0, p_at(x, y)) : T(0);
+    }
+#pragma unroll
+  for (int y = 0; y < NV; ++y)
+#pragma unroll
+    for (int x = 0; x < NV; ++x) dv[y][x] = at(op2.dinv, u_at(x, y));
+  const T mu = g.mu_cell != nullptr ? g.mu_cell[(uint32_t)ax + (uint32_t)g.n[0] * (uint32_t)ay] : g.mu;
+  if (owner) {
+#pragma unroll
+    for (int y = 0; y < K; ++y)
+#pragma unroll
+      for (int x = 0; x < K; ++x) bs[y][x] = (LAST && op2.base) ? at(op2.base, u_at(x, y)) : T(0);
+    if constexpr (MODE == F3_CHEBS) {
+#pragma unroll
+      for (int y = 0; y < K - 1; ++y)
+#pragma unroll
+        for (int x = 0; x < K - 1; ++x) pold[y][x] = (c == 0 && P.p) ? at(P.p, p_at(x, y)) : T(0);
+    }
+  }
+  __asm__ volatile("" ::: "memory");
+
+  // 2. stage 0: t0 = B u + sc M_p pc on the pressure nodes
+#pragma unroll
+  for (int cc = 0; cc < 2; ++cc)
+#pragma unroll
+    for (int y = 0; y < NV; ++y)
+#pragma unroll
+      for (int x = 0; x < NV; ++x) uu[cc][0][y][x] = (active && !vbc(x, y)) ? uu[cc][0][y][x] : T(0);
+  T d0[NP][NP];
+#pragma unroll
+  for (int y = 0; y < NP; ++y)
+#pragma unroll
+    for (int x = 0; x < NP; ++x) {
+      d0[y][x] = ds[y][x] * pa[y][x] * P.inv_theta;   // F3_CHEBS: d_0
+      if constexpr (MODE == F3_CHEBS) pc[0][y][x] = d0[y][x];
+      pc[0][y][x] = active ? pc[0][y][x] : T(0);
+    }
+  T t0[1][NP][NP];
+  {
+    T w[1][NV][NP];
+    pass_x<false, false>(R.Gr, uu[0], w, T(1));
+    pass_y<false, false>(R.Nr, w, t0, -g.sB[0]);
+    pass_x<false, false>(R.Nr, uu[1], w, T(1));
+    pass_y<false, true>(R.Gr, w, t0, -g.sB[1]);
+  }
+  if (has_c) {
+    const T sc = (MODE == F3_CHEBS ? g.cp : -g.cp) * g.sM;
+    T q[1][NP][NP];
+    pass_x<false, false>(R.Mpr, pc, q, T(1));
+    pass_y<false, true>(R.Mpr, q, t0, sc);
+  }
+  hand_over_xy<TX>(t0, lcx, lcy, bxh, byh);
+  // z on the nodes this lane holds completely; the pressure output
+  T z[NP][NP];
+#pragma unroll
+  for (int y = 0; y < NP; ++y)
+#pragma unroll
+    for (int x = 0; x < NP; ++x) {
+      if constexpr (MODE == F3_DIVRES) {
+        z[y][x] = t0[0][y][x] - pa[y][x];   // r_p
+      } else {
+        const T rn = pa[y][x] - t0[0][y][x];
+        const T dn = P.c1 * d0[y][x] + P.c2 * ds[y][x] * rn;
+        z[y][x] = P.tau * ((T(0) + d0[y][x]) + dn);
+      }
+    }
+  if (owner && c == 0) {
+#pragma unroll
+    for (int y = 0; y < NP; ++y)
+#pragma unroll
+      for (int x = 0; x < NP; ++x) {
+        const bool main = x < K - 1 && y < K - 1;
+        if (!main && !(((x < K - 1) | bxh) & ((y < K - 1) | byh))) continue;
+        if constexpr (MODE == F3_DIVRES) {
+          at(P.rp, p_at(x, y)) = z[y][x];
+        } else if (P.p) {
+          const T po = main ? pold[main ? y : 0][main ? x : 0] : at(P.p, p_at(x, y));
+          at(P.p, p_at(x, y)) = po + z[y][x];
+        }
+      }
+  }
+  if constexpr (MODE == F3_DIVRES) {
+#pragma unroll
+    for (int y = 0; y < NP; ++y)
+#pragma unroll
+      for (int x = 0; x < NP; ++x) z[y][x] = ds[y][x] * z[y][x] * P.inv_theta;
+  }
+  gather_high_faces<TX>(z, bxh, byh);
+
+  // 3. stage 1: q_c = B_c^T z (inputs of the lanes holding the whole cell)
+  T zm[1][NP][NP], t1[1][NV][NV];
+#pragma unroll
+  for (int y = 0; y < NP; ++y)
+#pragma unroll
+    for (int x = 0; x < NP; ++x) zm[0][y][x] = valid1 ? z[y][x] : T(0);
+  if (c == 0) {
+    T s1[1][NV][NP];
+    pass_y<true, false>(R.Nr, zm, s1, T(1));
+    pass_x<true, false>(R.Gr, s1, t1, -g.sB[0]);
+  } else {
+    T s2[1][NP][NV];
+    pass_x<true, false>(R.Nr, zm, s2, T(1));
+    pass_y<true, false>(R.Gr, s2, t1, -g.sB[1]);
+  }
+  hand_over_xy<TX>(t1, lcx, lcy, bxh, byh);
+  T v[NV][NV];
+#pragma unroll
+  for (int y = 0; y < NV; ++y)
+#pragma unroll
+    for (int x = 0; x < NV; ++x) v[y][x] = vbc(x, y) ? T(0) : t1[0][y][x];   // Dirichlet rows of q are 0
+  gather_high_faces<TX>(v, bxh, byh);
+
+  // 4. stage 2: t2 = A d0, d0 = D_A^-1 q / theta_A
+  const T axk = mu * g.sKx, bxm = g.gr * g.sM, sy = mu * g.sKy;
+  T X[NV][NV];
+#pragma unroll
+  for (int i = 0; i < NV; ++i)
+#pragma unroll
+    for (int j = 0; j < NV; ++j) X[i][j] = axk * R.Kr[i][j] + bxm * R.Mr[i][j];
+  T da[1][NV][NV], t2[1][NV][NV];
+#pragma unroll
+  for (int y = 0; y < NV; ++y)
+#pragma unroll
+    for (int x = 0; x < NV; ++x) {
+      const T d = dv[y][x] * v[y][x] * op2.inv_theta;
+      da[0][y][x] = (valid2 && !vbc(x, y)) ? d : T(0);
+    }
+  {
+    T t[1][NV][NV];
+    pass_y<false, false>(R.Mr, da, t, T(1));
+    pass_x<false, false>(X, t, t2, T(1));
+    pass_y<false, false>(R.Kr, da, t, T(1));
+    pass_x<false, true>(R.Mr, t, t2, sy);
+  }
+  hand_over_xy<TX>(t2, lcx, lcy, bxh, byh);
+
+  // 5. owned nodes through the Chebyshev epilogue
+  if (!owner) return;
+  using Pre2 = typename OpChebA<T, true, LAST>::Pre;
+  auto pre_at = [&](int x, int y, T base) {
+    Pre2 q;
+    q.r = v[y][x];
+    q.x = T(0);
+    q.dinv = dv[y][x];
+    q.base = base;
+    return q;
+  };
+#pragma unroll
+  for (int y = 0; y < K; ++y)
+#pragma unroll
+    for (int x = 0; x < K; ++x) op2.store_u(u_at(x, y), t2[0][y][x], da[0][y][x], false, pre_at(x, y, bs[y][x]));
   if (bxl | byl) {
 #pragma unroll
     for (int y = 0; y < K; ++y)

@@ -36,6 +36,17 @@ inline int fuse2d_max_n_from_env() {
   return e != nullptr ? std::atoi(e) : 256;
 }
 
+// Largest 2D level (cells per direction) on which an Uzawa step with k_S = 1
+// runs as three launches: the velocity update, then the pressure residual
+// fused with the first S~ direction and its A_hat^-1 application, then the
+// S~ Chebyshev step fused with B^T dp and the final A_hat^-1 application
+// (8 x 8 tiles owning 3 x 3 cells).  SMG_FUSE3_2D_MAX_N overrides it (0:
+// never).
+inline int fuse3_2d_max_n_from_env() {
+  const char *e = std::getenv("SMG_FUSE3_2D_MAX_N");
+  return e != nullptr ? std::atoi(e) : 128;
+}
+
 // Largest 3D Q2 level (cells per direction) whose cell-block launches use
 // one wave per output plane of the cells; SMG_PLANE3D_MAX_N overrides it
 // (0: never).
@@ -108,6 +119,7 @@ class EngineT : public EngineBase {
   int split2d_max_n = split2d_max_n_from_env();
   int sweep_waves = sweep_waves_from_env();
   int fuse2d_max_n = fuse2d_max_n_from_env();
+  int fuse3_2d_max_n = fuse3_2d_max_n_from_env();
   int plane3d_max_n = plane3d_max_n_from_env();
   std::vector<std::vector<double>> hverts;   // per level, host copy (node coordinates)
   double *Kinv = nullptr;
@@ -837,6 +849,7 @@ class EngineT : public EngineBase {
         cheb_A<T>(l, W.ru, u, W.uhat, sigma);
       }
     }
+    if (uzawa_tail_fused3<T>(l, u, p, gp)) return;
     OpDivResidual<T> od{W.uhat, p, gp, W.rp};
     if (has_c()) tile<T, BLK_B | BLK_C>(g, od);
     else tile<T, BLK_B>(g, od);
@@ -845,6 +858,102 @@ class EngineT : public EngineBase {
     if (!cheb_A_fused<T>(l, og, (const T *)W.uhat, u, -sigma)) {
       tile<T, BLK_BT>(g, og);
       cheb_A<T>(l, W.q, W.uhat, u, -sigma);
+    }
+  }
+
+  // The rest of an Uzawa step after u_hat, in two launches of the
+  // three-stage kernel (2D box levels of at most fuse3_2d_max_n cells per
+  // direction, k_S = 1, k_A >= 1):
+  //   1. r_p = B u_hat - C p - g, d_0 = D~_S^-1 r_p / theta_S,
+  //      w = Cheb(A, D_A, k_A) B^T d_0;
+  //   2. dp = the Chebyshev step for S~ from w and d_0, p += dp,
+  //      u = u_hat - sigma Cheb(A, D_A, k_A) B^T dp.
+  // Returns false, launching nothing, where it does not apply.
+  template <typename T>
+  bool uzawa_tail_fused3(int l, T *u, T *p, const T *gp) {
+    if constexpr (DIM != 2) {
+      return false;
+    } else {
+      const int kA = desc.cheb_deg_A, kS = desc.cheb_deg_S;
+      if (general || kA < 1 || kS != 1 || fuse3_2d_max_n <= 0 ||
+          std::max(lv[l].n[0], lv[l].n[1]) > fuse3_2d_max_n)
+        return false;
+      Work<T> &W = work<T>(l);
+      const double bA = lv[l].beta_A, thA = 0.75 * bA, deA = 0.25 * bA, s1A = thA / deA;
+      const double rhoA = 1.0 / s1A, rnA = 1.0 / (2.0 * s1A - rhoA);
+      const double bS = lv[l].beta_S, thS = 0.75 * bS, deS = 0.25 * bS, s1S = thS / deS;
+      const double rhoS = 1.0 / s1S, rnS = 1.0 / (2.0 * s1S - rhoS);
+      OpChebA<T, true, true> o;
+      std::memset(&o, 0, sizeof(o));
+      o.dinv = W.dinvA;
+      o.r_out = W.cr;
+      o.x_out = W.cx;
+      o.d_out = W.cd[1];
+      o.inv_theta = (T)(1.0 / thA);
+      o.c1 = (T)(rnA * rhoA);
+      o.c2 = (T)(2.0 * rnA / deA);
+      Fuse3P<T> P;
+      std::memset(&P, 0, sizeof(P));
+      P.dinv_s = W.dinvS;
+      P.inv_theta = (T)(1.0 / thS);
+      P.c1 = (T)(rnS * rhoS);
+      P.c2 = (T)(2.0 * rnS / deS);
+      P.tau = (T)tau;
+      auto g = geom<T>(l);
+      const Geo2<T> g2 = geo2<T>(g, 3);
+      const unsigned nb = (unsigned)(g2.tiles[0] * g2.tiles[1] * 2);
+      const double nu = (double)(DIM * g.Nv), np = (double)g.Np;
+      for (int stage = 0; stage < 2; ++stage) {
+        if (stage == 0) {
+          P.u = W.uhat;
+          P.p0 = p;
+          P.g = gp;
+          P.rp = W.rp;
+          o.base = nullptr;
+          o.out = W.w;
+          o.s = (T)sigma;
+        } else {
+          P.u = W.w;
+          P.rin = W.rp;
+          P.p = p;
+          o.base = W.uhat;
+          o.out = u;
+          o.s = (T)(-sigma);
+        }
+        hipEvent_t ea = nullptr, eb = nullptr;
+        if (profiling) {
+          ea = next_event();
+          eb = next_event();
+          SMG_HIP(hipEventRecord(ea, stream));
+        }
+        if (stage == 0) {
+          if (kA == 1)
+            hipLaunchKernelGGL((wave2d_fused3_kernel<K, T, F3_DIVRES, true>), dim3(nb), dim3(64), 0, stream, g2, P, o);
+          else
+            hipLaunchKernelGGL((wave2d_fused3_kernel<K, T, F3_DIVRES, false>), dim3(nb), dim3(64), 0, stream, g2, P,
+                               cast_op<OpChebA<T, true, false>>(o));
+        } else {
+          if (kA == 1)
+            hipLaunchKernelGGL((wave2d_fused3_kernel<K, T, F3_CHEBS, true>), dim3(nb), dim3(64), 0, stream, g2, P, o);
+          else
+            hipLaunchKernelGGL((wave2d_fused3_kernel<K, T, F3_CHEBS, false>), dim3(nb), dim3(64), 0, stream, g2, P,
+                               cast_op<OpChebA<T, true, false>>(o));
+        }
+        check_launch();
+        if (profiling) {
+          SMG_HIP(hipEventRecord(eb, stream));
+          char key[160];
+          std::snprintf(key, sizeof(key), "%s+grad+cheb_A/v%d/fused3/%s/%dx%dx%d",
+                        stage == 0 ? "div_residual" : "cheb_S", kA == 1 ? 3 : 1,
+                        std::is_same<T, double>::value ? "f64" : "f32", g.n[0], g.n[1], g.n[2]);
+          // velocity input of B, the pressure vectors, D_A^-1, the velocity outputs
+          const double pres = stage == 0 ? (has_c() ? 4 : 3) : (P.p ? 4 : 2);
+          const double bytes = sizeof(T) * (nu + pres * np + nu * (kA == 1 ? (stage == 1 ? 3 : 2) : 4));
+          prof.push_back(ProfRec{key, ea, eb, bytes});
+        }
+        if (kA > 1) cheb_A<T>(l, nullptr, o.base, o.out, stage == 0 ? sigma : -sigma, 1);
+      }
+      return true;
     }
   }
 

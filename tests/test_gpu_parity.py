@@ -36,14 +36,15 @@ CONFIGS = {
     # levels of at most 16 cells per direction use one wave per output plane
     # of the cell block by default; the same levels with one wave per block:
     "3d_k2_cellblock": dict(dim=3, k=2, n_coarse=(2, 3, 2), levels=3, env={"SMG_PLANE3D_MAX_N": "0"}),
-    # small 2D levels take one wave per output field and fuse the producer of
-    # each Chebyshev right-hand side with the first Chebyshev step by
-    # default; the same levels with one wave per tile for all fields and
+    # small 2D levels take one wave per output field, fuse the producer of
+    # each Chebyshev right-hand side with the first Chebyshev step, and (k_S
+    # = 1) run the pressure part of an Uzawa step as two three-stage launches
+    # by default; the same levels with one wave per tile for all fields and
     # separate launches:
     "2d_k2_plain": dict(dim=2, k=2, n_coarse=(5, 3), levels=4,
-                        env={"SMG_SPLIT2D_MAX_N": "0", "SMG_FUSE2D_MAX_N": "0"}),
+                        env={"SMG_SPLIT2D_MAX_N": "0", "SMG_FUSE2D_MAX_N": "0", "SMG_FUSE3_2D_MAX_N": "0"}),
     "2d_k3_plain": dict(dim=2, k=3, n_coarse=(3, 2), levels=4,
-                        env={"SMG_SPLIT2D_MAX_N": "0", "SMG_FUSE2D_MAX_N": "0"}),
+                        env={"SMG_SPLIT2D_MAX_N": "0", "SMG_FUSE2D_MAX_N": "0", "SMG_FUSE3_2D_MAX_N": "0"}),
     "3d_k3": dict(dim=3, k=3, n_coarse=(2, 2, 3), levels=2),
     # vertex-given (multilinear) cells: interior vertices of the finest mesh
     # moved by up to 0.2 h, coarse levels take the finest vertices
@@ -343,33 +344,44 @@ def test_c1_protocol_16x16_stationary():
     gpu.close()
 
 
-@pytest.mark.parametrize("kA,kS", [(1, 1), (2, 1), (3, 2), (0, 1)])
-def test_small_level_variants_equal_separate_launches(kA, kS):
-    """The small-level 2D kernels (one wave per field, operator application
-    fused with the first Chebyshev step) against one wave per tile and
-    separate launches, on every level of the same problem: the same
-    arithmetic in another launch order, so the results agree to rounding."""
+@pytest.mark.parametrize("c_p", [0.2, 0.0])
+@pytest.mark.parametrize("k,kA,kS", [(2, 1, 1), (2, 2, 1), (2, 3, 2), (2, 0, 1), (3, 1, 1), (3, 2, 1)])
+def test_small_level_variants_equal_separate_launches(k, kA, kS, c_p):
+    """The small-level 2D kernels (one wave per field; operator application
+    fused with the first Chebyshev step; for k_S = 1 the pressure part of an
+    Uzawa step in two three-stage launches) against the two-stage fusion
+    alone and against one wave per tile with separate launches, on every
+    level of the same problem: the same arithmetic in another launch order,
+    so the results agree to rounding."""
     from paper_2205_15770_amd import StokesMG
-    cfg = CONFIGS["2d_k2"]
-    mu_cell = si.uniform(40 * 24, 17, 0.5, 3.0)
-    kw = dict(dim=2, fe_degree=2, n_coarse=cfg["n_coarse"], n_levels=cfg["levels"], mu_cell=mu_cell,
-              gamma=PHYS["gamma"], rho=PHYS["rho"], c_pressure=0.2, cheb_deg_A=kA, cheb_deg_S=kS)
+    cfg = CONFIGS["2d_k2" if k == 2 else "2d_k3"]
+    n_f = [c * 2 ** (cfg["levels"] - 1) for c in cfg["n_coarse"]]
+    mu_cell = si.uniform(n_f[0] * n_f[1], 17, 0.5, 3.0)
+    kw = dict(dim=2, fe_degree=k, n_coarse=cfg["n_coarse"], n_levels=cfg["levels"], mu_cell=mu_cell,
+              gamma=PHYS["gamma"], rho=PHYS["rho"], c_pressure=c_p, cheb_deg_A=kA, cheb_deg_S=kS)
     a = StokesMG(**kw)
     with _env(CONFIGS["2d_k2_plain"]):
         b = StokesMG(**kw)
+    with _env(dict(env={"SMG_FUSE3_2D_MAX_N": "0"})):
+        c = StokesMG(**kw)
     for l in range(1, cfg["levels"]):
         bA, bS = a.eigs(l)
         b.set_eigs(l, bA, bS)
+        c.set_eigs(l, bA, bS)
         n = a.n_total(l)
         for dtype, tol in ((torch.float64, 1e-13), (torch.float32, 1e-5)):
             x0 = _dev(si.uniform(n, 60 + l), dtype)
             rhs = _dev(si.uniform(n, 70 + l), dtype)
-            xa, xb = x0.clone(), x0.clone()
+            xa, xb, xc = x0.clone(), x0.clone(), x0.clone()
             a.smooth(l, xa, rhs, 2)
             b.smooth(l, xb, rhs, 2)
-            assert _rel(xa, xb.cpu().numpy().astype(np.float64)) < tol, (l, dtype)
+            c.smooth(l, xc, rhs, 2)
+            ref = xb.cpu().numpy().astype(np.float64)
+            assert _rel(xa, ref) < tol, (l, dtype)
+            assert _rel(xc, ref) < tol, (l, dtype)
     a.close()
     b.close()
+    c.close()
 
 
 def test_vmult_is_deterministic():
