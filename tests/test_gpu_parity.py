@@ -252,6 +252,38 @@ def test_cycle(name, cycle):
     assert _rel(x32, ora.cycle(L, x0.copy(), b)) < 1e-4
 
 
+@pytest.mark.parametrize("name", ["2d_k2", "2d_k3", "2d_k2_plain", "2d_k3_plain", "3d_k2"])
+def test_uniform_viscosity(name):
+    """Uniform viscosity (no per-cell field; the other parity tests give each
+    cell its own mu): vmult on every level, the smoother and a V-cycle against
+    the oracle, with C != 0."""
+    ora, gpu = _setup(name, c_p=0.3, percell=False)
+    _inject_betas(ora, gpu)
+    for l in range(ora.L + 1):
+        K = ora.levels[l].K
+        x = si.uniform(K.shape[0], 200 + l)
+        assert _rel(gpu.vmult(l, _dev(x)), K @ x) < 1e-12, l
+        assert _rel(gpu.vmult(l, _dev(x, torch.float32)), K @ x.astype(np.float32).astype(np.float64)) < 2e-5, l
+    L = ora.L
+    S = ora.smoothers[L]
+    n = ora.levels[L].K.shape[0]
+    x = si.uniform(n, 223)
+    b = si.uniform(n, 224)
+    xg = _dev(x)
+    gpu.smooth(L, xg, _dev(b), 2)
+    assert _rel(xg, S.smooth(x, b, 2)) < 1e-10
+    f = si.nodal_random_f(ora.meshes[L].dim, ora.meshes[L].n_vnode, seed=3)
+    b = ora.levels[L].rhs_from_nodal_f(f)
+    x0 = si.uniform(n, 71) * 0.1
+    x0[ora.levels[L].constrained] = 0.0
+    xg = _dev(x0)
+    gpu.vcycle(L, xg, _dev(b))
+    assert _rel(xg, ora.cycle(L, x0.copy(), b)) < 1e-10
+    x32 = _dev(x0, torch.float32)
+    gpu.vcycle(L, x32, _dev(b, torch.float32))
+    assert _rel(x32, ora.cycle(L, x0.copy(), b)) < 1e-4
+
+
 @pytest.mark.parametrize("name", ["2d_k2", "2d_k2_plain", "3d_k2", "3d_k2_sweep", "3d_k2_cellblock", "2d_k3", "3d_k3_pert"])
 @pytest.mark.parametrize("precision", ["f64", "f32"])
 def test_fgmres_solve(name, precision):
