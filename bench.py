@@ -284,11 +284,28 @@ def cpu_baseline():
     finally:
         if ctx is not None:
             ctx.unregister() if hasattr(ctx, "unregister") else None
+    # the library's solves of the same system (FP32 and FP64 V-cycle) against
+    # the oracle's solution, pressure means removed from both
+    import torch
+    from oracle.mg import pressure_mean_free
+    from paper_2205_15770_amd import StokesMG
+    xo = pressure_mean_free(asm, x)
+    diffs = {}
+    for prec in ("f32", "f64"):
+        mg = StokesMG(dim=2, fe_degree=2, n_coarse=(8, 8), n_levels=6, mu=1.0, rho=1.0, gamma=1e3, cheb_deg_A=1,
+                      cheb_deg_S=1, smooth_steps=2, cycle_index=1, schur_diag="d", precision=prec)
+        bg = torch.tensor(b, dtype=torch.float64, device="cuda")
+        xg = torch.zeros_like(bg)
+        mg.solve(xg, bg, rtol=1e-8, maxit=300)
+        xs = pressure_mean_free(asm, xg.cpu().numpy())
+        diffs["f32_mixed" if prec == "f32" else "f64"] = float(np.linalg.norm(xs - xo) / np.linalg.norm(xo))
+        mg.close()
     return {"value": n / t / 1e9, "unit": "GDoF/s", "cores": 1, "kind": "oracle",
             "sample": f"oracle FGMRES(30) + FP64 V-cycle solve to 1e-8 of the same generalized Stokes problem on "
                       f"256x256 cells ({n} DoFs, 6 levels), {len(hist) - 1} iterations, {t:.2f} s, setup excluded; "
                       f"CSR SpMV {n / tv / 1e9:.4f} GDoF/s",
-            "spmv_gdofs": n / tv / 1e9}
+            "spmv_gdofs": n / tv / 1e9,
+            "library_vs_oracle_solution_rel_diff": diffs}
 
 
 def main():
