@@ -417,7 +417,9 @@ def main():
         g32, t32 = time_vmult(mg, L, torch.float32)
         extra["vmult"] = {"f64_gdofs": round(g64, 2), "f32_gdofs": round(g32, 2),
                           "f64_us": round(t64 * 1e6, 2), "f32_us": round(t32 * 1e6, 2),
-                          "f64_hbm_gbs": round(2 * 8 * N / t64 / 1e9, 1), "f32_hbm_gbs": round(2 * 4 * N / t32 / 1e9, 1)}
+                          "f64_hbm_gbs": round(2 * 8 * N / t64 / 1e9, 1), "f32_hbm_gbs": round(2 * 4 * N / t32 / 1e9, 1),
+                          "f64_frac_of_hbm_peak": round(2 * 8 * N / t64 / 1e9 / HBM_PEAK_GBS, 3),
+                          "f32_frac_of_hbm_peak": round(2 * 4 * N / t32 / 1e9 / HBM_PEAK_GBS, 3)}
         x_mixed = x.clone()
         mg64 = StokesMG(precision="f64", **common)
         x64 = torch.zeros_like(x)
