@@ -184,7 +184,7 @@ def test_lanczos_bounds(name):
 
 
 @pytest.mark.parametrize("name", list(CONFIGS))
-@pytest.mark.parametrize("kA,kS", [(0, 0), (1, 1), (3, 2)])
+@pytest.mark.parametrize("kA,kS", [(0, 0), (1, 1), (3, 2), (2, 1)])
 def test_chebyshev_and_smoother(name, kA, kS):
     ora, gpu = _setup(name, kA=kA, kS=kS)
     _inject_betas(ora, gpu)
