@@ -29,6 +29,9 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+# MI355X FP32 vector peak (256 CUs x 4 SIMDs x 2.4 GHz, packed issue); the
+# kernels are built without packed FP32, which halves what they can issue
+FP32_PEAK_TFLOPS = 157.3
 
 WORKLOADS = {
     "stokes2d_q2q1_512": dict(dim=2, fe_degree=2, n_coarse=(8, 8), n_levels=7, mu=1.0, rho=1.0, gamma=1e3,
@@ -403,6 +406,20 @@ def main():
     bytes_per_launch = nbytes / cnt
     achieved = bytes_per_launch / (cheb_ms * 1e-3) / 1e9
     traffic = traffic_from_profiles(key)
+    # the same launch as vector-ALU work: the sum-factorised A of every cell
+    # (2D: 4 passes of (k+1)^3 FMA per component, 3D: 7 passes of (k+1)^4),
+    # against the FP32 vector peak (box cells only)
+    alu = None
+    if "perturb" not in wl:
+        k, d = wl["fe_degree"], wl["dim"]
+        ncell = 1
+        for v in cells(wl)[:d]:
+            ncell *= v
+        fma = d * (4 * (k + 1) ** 3 if d == 2 else 7 * (k + 1) ** 4)
+        flops = 2.0 * fma * ncell
+        tfl = flops / (cheb_ms * 1e-3) / 1e12
+        alu = {"achieved": round(tfl, 2), "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
+               "frac": round(tfl / FP32_PEAK_TFLOPS, 4), "flops_per_launch": flops}
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                 "kernel": key, "avg_us_timed_region": round(cheb_ms * 1e3, 2),
@@ -410,7 +427,7 @@ def main():
                 "achieved_16_vector_pairs": round(bytes_per_launch / (cheb_rot_ms * 1e-3) / 1e9, 1),
                 "algorithmic_bytes_per_launch": bytes_per_launch,
                 "share_of_solve_kernel_time": round(ms / kern_ms, 3),
-                "largest_kernel_in_solve": dom}
+                "largest_kernel_in_solve": dom, "alu": alu}
     extra = {}
     if not args.quick:
         g64, t64 = time_vmult(mg, L, torch.float64)
