@@ -29,8 +29,10 @@
 //   B_c    = -sB_c (Gr in direction c, Nr in the others),  C = cp sM Mpr^(x)3,
 // with sKx = h_y h_z / h_x (cyclic), sM = h_x h_y h_z, sB_c = prod_{a != c} h_a.
 #pragma once
+#include <type_traits>
 #include "cell_kernel.hpp"
 #include "fe1d_const.hpp"
+#include "ops.hpp"
 
 namespace smg {
 
@@ -994,8 +996,17 @@ block3d_plane_kernel(const Geo3<T> g, const Op op) {
   if constexpr (OUT_P) block_pres_planes<K, T, BLK, Op>(g, op, col, s, o, lds);
 }
 
+// FP32 operator applications (OpApply) of the sweep ask for three waves per
+// SIMD (168 VGPRs): measured faster than two although a few registers spill;
+// the other epilogues spill inside the sweep at that limit and keep the
+// default.
+template <class Op, typename T>
+constexpr int tile3d_waves_per_eu() {
+  return (sizeof(T) == 4 && std::is_same<Op, OpApply<T>>::value) ? 3 : 1;
+}
+
 template <int K, typename T, int BLK, class Op, int TX, int TY>
-__global__ void __launch_bounds__(64)
+__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(tile3d_waves_per_eu<Op, T>())))
 tile3d_kernel(const Geo3<T> g, const Op op) {
   static_assert(TX * TY == 64, "one wave per tile");
   constexpr bool OUT_U = (BLK & (BLK_A | BLK_MASS | BLK_BT)) != 0;
