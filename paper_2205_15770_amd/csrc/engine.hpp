@@ -122,10 +122,16 @@ class EngineBase {
     allocations.push_back(p);
     return (T *)p;
   }
+  // pinned host mirror of the small device result vector (reduction
+  // results copied back once per Krylov iteration; pinned, so the copies
+  // are true asynchronous DMA transfers)
+  double *hpin = nullptr;
   void free_all() {
     destroy_events();
     for (void *p : allocations) (void)hipFree(p);
     allocations.clear();
+    if (hpin) (void)hipHostFree(hpin);
+    hpin = nullptr;
   }
 };
 

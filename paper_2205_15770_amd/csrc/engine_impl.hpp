@@ -1040,10 +1040,9 @@ class EngineT : public EngineBase {
   }
   double dot(const double *a, const double *b, int64_t n) {
     multidot(a, 0, 1, b, n, dvec);
-    double h = 0;
-    SMG_HIP(hipMemcpyAsync(&h, dvec, sizeof(double), hipMemcpyDeviceToHost, stream));
+    SMG_HIP(hipMemcpyAsync(hpin + 1000, dvec, sizeof(double), hipMemcpyDeviceToHost, stream));
     SMG_HIP(hipStreamSynchronize(stream));
-    return h;
+    return hpin[1000];
   }
   double norm(const double *a, int64_t n) { return std::sqrt(dot(a, a, n)); }
 
@@ -1342,6 +1341,7 @@ class EngineT : public EngineBase {
     for (int i = 0; i < 4; ++i) lz[i] = dalloc<double>(nmax);
     partial = dalloc<double>((int64_t)RB * 256);
     dvec = dalloc<double>(1024);
+    SMG_HIP(hipHostMalloc((void **)&hpin, sizeof(double) * 1024, hipHostMallocDefault));
     // general cells: vertex coordinates of every level (level l takes the
     // finest-level vertex at the same lattice point)
     // the deformation-rate form and Q3-Q2 in 3D run on the vertex-given cell
@@ -1540,7 +1540,10 @@ class EngineT : public EngineBase {
       double beta = norm(V, N);
       rel = beta / bnorm;
       record(rel);
-      std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), gv(m + 1), y(m), hbuf(513);
+      std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), gv(m + 1);
+      // pinned: hbuf = this iteration's coefficients and norm (dvec[0..512]),
+      // y = the correction's coefficients (host to device, dvec[0..m))
+      double *hbuf = hpin, *y = hpin + 600;
       while (it < maxit && rel > rtol) {
         hipLaunchKernelGGL((k_jacobi<double>), dim3(grid_for(N)), dim3(VB), 0, stream, V, (const double *)nullptr, 1.0 / beta, unit_vec(N), (const double *)V, (i64)N);
         check_launch();
@@ -1564,7 +1567,7 @@ class EngineT : public EngineBase {
           multidot(w, 0, 1, w, N, dvec + 512);
           hipLaunchKernelGGL((k_scale_inv_sqrt<double>), dim3(grid_for(N)), dim3(VB), 0, stream, w, (const double *)(dvec + 512), (i64)N);
           check_launch();
-          SMG_HIP(hipMemcpyAsync(hbuf.data(), dvec, sizeof(double) * 513, hipMemcpyDeviceToHost, stream));
+          SMG_HIP(hipMemcpyAsync(hbuf, dvec, sizeof(double) * 513, hipMemcpyDeviceToHost, stream));
           SMG_HIP(hipStreamSynchronize(stream));
           for (int i = 0; i <= j; ++i) H[(size_t)i * m + j] += hbuf[i] + hbuf[256 + i];
           const double hn = std::sqrt(std::max(hbuf[512], 0.0));
@@ -1595,7 +1598,7 @@ class EngineT : public EngineBase {
           for (int c = i + 1; c < jdone; ++c) s -= H[(size_t)i * m + c] * y[c];
           y[i] = s / H[(size_t)i * m + i];
         }
-        SMG_HIP(hipMemcpyAsync(dvec, y.data(), sizeof(double) * jdone, hipMemcpyHostToDevice, stream));
+        SMG_HIP(hipMemcpyAsync(dvec, y, sizeof(double) * jdone, hipMemcpyHostToDevice, stream));
         hipLaunchKernelGGL((k_multi_axpy<double>), dim3(grid_for(N)), dim3(VB), 0, stream, x, (const double *)Z, (i64)N, jdone, (const double *)dvec, 1.0, (i64)N);
         check_launch();
         residual_t<double>(L, x, b, V);
