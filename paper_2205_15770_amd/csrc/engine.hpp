@@ -126,12 +126,16 @@ class EngineBase {
   // results copied back once per Krylov iteration; pinned, so the copies
   // are true asynchronous DMA transfers)
   double *hpin = nullptr;
+  // marks the arrival of those results while later work is already queued
+  hipEvent_t hpin_ready = nullptr;
   void free_all() {
     destroy_events();
     for (void *p : allocations) (void)hipFree(p);
     allocations.clear();
     if (hpin) (void)hipHostFree(hpin);
     hpin = nullptr;
+    if (hpin_ready) (void)hipEventDestroy(hpin_ready);
+    hpin_ready = nullptr;
   }
 };
 

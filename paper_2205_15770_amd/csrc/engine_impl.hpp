@@ -1342,6 +1342,7 @@ class EngineT : public EngineBase {
     partial = dalloc<double>((int64_t)RB * 256);
     dvec = dalloc<double>(1024);
     SMG_HIP(hipHostMalloc((void **)&hpin, sizeof(double) * 1024, hipHostMallocDefault));
+    SMG_HIP(hipEventCreateWithFlags(&hpin_ready, hipEventDisableTiming));
     // general cells: vertex coordinates of every level (level l takes the
     // finest-level vertex at the same lattice point)
     // the deformation-rate form and Q3-Q2 in 3D run on the vertex-given cell
@@ -1552,10 +1553,16 @@ class EngineT : public EngineBase {
         gv[0] = beta;
         int jdone = 0;
         bool broke = false;
+        // z_j = M^-1 v_j and w = K z_j of iteration j already queued (ahead)
+        bool queued = false;
+        double rel_prev = rel, rel_prev2 = -1.0;
         for (int j = 0; j < m; ++j) {
           double *vj = V + (int64_t)j * N, *zj = Z + (int64_t)j * N, *w = V + (int64_t)(j + 1) * N;
-          precondition(vj, zj);
-          vmult_t<double>(L, zj, w);
+          if (!queued) {
+            precondition(vj, zj);
+            vmult_t<double>(L, zj, w);
+          }
+          queued = false;
           // classical Gram-Schmidt, twice; coefficients and the norm stay on
           // the device until one copy per iteration
           for (int pass = 0; pass < 2; ++pass) {
@@ -1568,7 +1575,24 @@ class EngineT : public EngineBase {
           hipLaunchKernelGGL((k_scale_inv_sqrt<double>), dim3(grid_for(N)), dim3(VB), 0, stream, w, (const double *)(dvec + 512), (i64)N);
           check_launch();
           SMG_HIP(hipMemcpyAsync(hbuf, dvec, sizeof(double) * 513, hipMemcpyDeviceToHost, stream));
-          SMG_HIP(hipStreamSynchronize(stream));
+          SMG_HIP(hipEventRecord(hpin_ready, stream));
+          // While the host waits for this iteration's coefficients, queue the
+          // next iteration's preconditioner and operator (they need only
+          // v_{j+1}, normalised on the device) unless this iteration may
+          // reach the tolerance: the residual estimate is extrapolated
+          // geometrically from the last two (a factor 100 per iteration at
+          // the start of a cycle).  Queued work of an iteration that does not
+          // run is discarded; it changes no result.
+          {
+            const double pred = rel_prev2 > 0.0 ? rel_prev * (rel_prev / rel_prev2) : rel_prev * 1e-2;
+            if (j + 1 < m && it + 1 < maxit && pred > 2.0 * rtol) {
+              double *zn = Z + (int64_t)(j + 1) * N, *wn = V + (int64_t)(j + 2) * N;
+              precondition(w, zn);
+              vmult_t<double>(L, zn, wn);
+              queued = true;
+            }
+          }
+          SMG_HIP(hipEventSynchronize(hpin_ready));
           for (int i = 0; i <= j; ++i) H[(size_t)i * m + j] += hbuf[i] + hbuf[256 + i];
           const double hn = std::sqrt(std::max(hbuf[512], 0.0));
           H[(size_t)(j + 1) * m + j] = hn;
@@ -1590,6 +1614,8 @@ class EngineT : public EngineBase {
           rel = std::fabs(gv[j + 1]) / bnorm;
           if (!finite(rel)) { broke = true; break; }
           record(rel);
+          rel_prev2 = rel_prev;
+          rel_prev = rel;
           if (rel <= rtol || it >= maxit) break;
         }
         if (broke) { st = SMG_EBREAKDOWN; break; }
