@@ -153,7 +153,8 @@ void smg_desc_default(smg_desc *desc);
  * a close approximation: 30 Lanczos steps in the D inner product from a
  * SplitMix64 start vector, times 1.02), the dense inverse of the bordered
  * coarse matrix [K_0 m; m^T 0], m = (0, M_p 1) (Sec. 4.1, direct coarse solve;
- * the border fixes the pressure mean), and all workspace.  Synchronises.
+ * the border fixes the pressure mean; with c_pressure > 0, K_0 is regular and
+ * is inverted without the border), and all workspace.  Synchronises.
  * Errors: EINVAL for an invalid descriptor, EUNSUPPORTED for dim/degree not
  * built, ENOMEM, EDEVICE.  On success *out owns everything until smg_destroy. */
 smg_status smg_create(const smg_desc *desc, smg_ctx **out);
@@ -218,7 +219,8 @@ smg_status smg_restrict(smg_ctx *ctx, int fine_level, int dtype, const void *r_f
 smg_status smg_prolongate_add(smg_ctx *ctx, int fine_level, int dtype, const void *w_coarse, void *x_fine);
 
 /* x_0 = K_0^+ b_0 on level 0 by the dense bordered inverse, computed in FP64
- * for either dtype (Sec. 4.1).  b_0 should satisfy 1^T b_p = 0. */
+ * for either dtype (Sec. 4.1).  b_0 should satisfy 1^T b_p = 0.  With
+ * c_pressure > 0: x_0 = K_0^-1 b_0 (no border, no condition on b_0). */
 smg_status smg_coarse_solve(smg_ctx *ctx, int dtype, const void *b0, void *x0);
 
 /* One multigrid cycle (Algorithm 1, cycle index of the descriptor) on level
@@ -230,7 +232,8 @@ smg_status smg_vcycle(smg_ctx *ctx, int level, int dtype, void *x, const void *b
  * per iteration in the precision of desc.precision (FP32: the FP64 Krylov
  * vector is cast to FP32, the FP32 cycle is applied, the result is cast back;
  * the coarse solve stays FP64).  x (FP64, length N) is the initial guess and
- * the result; the pressure of the result is shifted to M_p-weighted mean zero.
+ * the result; for c_pressure = 0 the pressure of the result is shifted to
+ * M_p-weighted mean zero (with c_pressure > 0 it is unique and left as is).
  * Returns ENOTCONV if maxit iterations do not reach rtol (x holds the last
  * iterate), EBREAKDOWN on NaN/Inf.  Synchronises; info may be NULL. */
 smg_status smg_solve(smg_ctx *ctx, double *x, const double *b, double rtol, int maxit, smg_solve_info *info);

@@ -7,9 +7,11 @@ direct solve on level 0 (Section 4.1: assembled coarse matrix, direct method).
 Reading of Algorithm 1: on level 0 the exact solve is the whole cycle (it
 returns without smoothing).
 
-Coarse solve reading: the pressure is only fixed up to a constant (Q = L^2_0
-in Section 2), so level 0 solves the bordered system [K_0 m; m^T 0] with
-m = (0, M_p 1), i.e. the discrete zero-mean condition on p.
+Coarse solve reading: for C = 0 the pressure is only fixed up to a constant
+(Q = L^2_0 in Section 2), so level 0 solves the bordered system
+[K_0 m; m^T 0] with m = (0, M_p 1), i.e. the discrete zero-mean condition on
+p.  With C = c_p M_p, c_p > 0, constants are no longer in the kernel of K_0,
+which is regular and solved as it is.
 """
 import numpy as np
 
@@ -34,18 +36,24 @@ class Multigrid:
         K0 = self.levels[0].K.toarray()
         n0 = K0.shape[0]
         nu0 = self.levels[0].A.shape[0]
-        mvec = np.zeros(n0)
-        mvec[nu0:] = self.levels[0].Mp @ np.ones(n0 - nu0)
-        Kb = np.zeros((n0 + 1, n0 + 1))
-        Kb[:n0, :n0] = K0
-        Kb[:n0, n0] = mvec
-        Kb[n0, :n0] = mvec
-        self.K0_bordered = Kb
+        self.bordered = c_p == 0.0
+        if self.bordered:
+            mvec = np.zeros(n0)
+            mvec[nu0:] = self.levels[0].Mp @ np.ones(n0 - nu0)
+            Kb = np.zeros((n0 + 1, n0 + 1))
+            Kb[:n0, :n0] = K0
+            Kb[:n0, n0] = mvec
+            Kb[n0, :n0] = mvec
+            self.K0_bordered = Kb
+        else:
+            self.K0_bordered = K0
 
     def K(self, l):
         return self.levels[l].K
 
     def coarse_solve(self, b0):
+        if not self.bordered:
+            return np.linalg.solve(self.K0_bordered, b0)
         rhs = np.concatenate([b0, [0.0]])
         return np.linalg.solve(self.K0_bordered, rhs)[:-1]
 

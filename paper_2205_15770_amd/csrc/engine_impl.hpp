@@ -123,6 +123,7 @@ class EngineT : public EngineBase {
   int plane3d_max_n = plane3d_max_n_from_env();
   std::vector<std::vector<double>> hverts;   // per level, host copy (node coordinates)
   double *Kinv = nullptr;
+  int coarse_ld = 0;   // leading dimension of Kinv: n0 + 1 (bordered) or n0
   int n0 = 0;
   double sigma = 0, tau = 0;
   // FGMRES storage
@@ -1008,7 +1009,7 @@ class EngineT : public EngineBase {
   template <typename T>
   void coarse_t(const T *b0, T *x0) {
     const unsigned nb = (unsigned)((n0 + (VB / 64) - 1) / (VB / 64));
-    hipLaunchKernelGGL((k_coarse_gemv<T>), dim3(nb), dim3(VB), 0, stream, Kinv, (i64)(n0 + 1), n0, b0, x0);
+    hipLaunchKernelGGL((k_coarse_gemv<T>), dim3(nb), dim3(VB), 0, stream, Kinv, (i64)coarse_ld, n0, b0, x0);
     check_launch();
   }
 
@@ -1046,7 +1047,9 @@ class EngineT : public EngineBase {
   }
   double norm(const double *a, int64_t n) { return std::sqrt(dot(a, a, n)); }
 
+  // only for C = 0, where the pressure is fixed up to a constant
   void remove_pressure_mean(double *x) {
+    if (has_c()) return;
     const LevelInfo &I = lv[L];
     multidot(I.mp1, 0, 1, x + I.Nu, I.Np, dvec);
     hipLaunchKernelGGL(k_subtract_scalar, dim3(grid_for(I.Np)), dim3(VB), 0, stream, x + I.Nu, (const double *)dvec, mp1_sum, (i64)I.Np);
@@ -1175,14 +1178,20 @@ class EngineT : public EngineBase {
     SMG_HIP(hipMemcpyAsync(Kc.data(), cols, sizeof(double) * Kc.size(), hipMemcpyDeviceToHost, stream));
     SMG_HIP(hipMemcpyAsync(m.data() + I.Nu, I.mp1, sizeof(double) * I.Np, hipMemcpyDeviceToHost, stream));
     SMG_HIP(hipStreamSynchronize(stream));
-    const int nb = n0 + 1;
+    // C = 0: constant pressures span ker K_0, and the border [K_0 m; m^T 0]
+    // fixes the pressure mean; C = c_p M_p with c_p > 0: K_0 is regular and
+    // is inverted as it is
+    const bool border = !has_c();
+    const int nb = n0 + (border ? 1 : 0);
+    coarse_ld = nb;
     std::vector<double> A((size_t)nb * nb, 0.0), Inv((size_t)nb * nb, 0.0);
     for (int i = 0; i < n0; ++i)
       for (int j = 0; j < n0; ++j) A[(size_t)i * nb + j] = Kc[(size_t)j * n0 + i];  // column j = K e_j
-    for (int i = 0; i < n0; ++i) {
-      A[(size_t)i * nb + n0] = m[i];
-      A[(size_t)n0 * nb + i] = m[i];
-    }
+    if (border)
+      for (int i = 0; i < n0; ++i) {
+        A[(size_t)i * nb + n0] = m[i];
+        A[(size_t)n0 * nb + i] = m[i];
+      }
     for (int i = 0; i < nb; ++i) Inv[(size_t)i * nb + i] = 1.0;
     // Gauss-Jordan elimination with partial pivoting
     for (int c = 0; c < nb; ++c) {

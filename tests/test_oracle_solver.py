@@ -266,6 +266,22 @@ def test_bordered_coarse_solve():
     assert abs((a0.Mp @ np.ones(a0.Mp.shape[0])) @ x[nu:]) < 1e-12 * np.linalg.norm(x)
 
 
+def test_coarse_solve_with_pressure_mass_is_exact():
+    """With C = c_p M_p (c_p > 0) constants leave the kernel of K_0: the coarse
+    solve is the plain inverse, exact for any right-hand side, and the
+    pressure mean is not forced to zero."""
+    mg = Multigrid(make_hierarchy(2, (4, 4), 2, 2), gamma=1.0, c_p=0.3)
+    a0 = mg.levels[0]
+    rng = np.random.default_rng(3)
+    b = rng.standard_normal(a0.K.shape[0])
+    b[a0.constrained] = 0
+    nu = a0.A.shape[0]
+    x = mg.coarse_solve(b)
+    assert np.linalg.norm(a0.K @ x - b) < 1e-12 * np.linalg.norm(b)
+    # a pressure right-hand side with non-zero mean gives a pressure with non-zero mean
+    assert abs((a0.Mp @ np.ones(a0.Mp.shape[0])) @ x[nu:]) > 1e-3 * np.linalg.norm(x[nu:])
+
+
 def test_fgmres_matches_direct_solve_on_indefinite_system():
     rng = np.random.default_rng(2)
     n = 80
