@@ -318,6 +318,34 @@ def test_fgmres_solve(name, precision):
     gpu.close()
 
 
+@pytest.mark.parametrize("name", ["2d_k2", "3d_k2", "2d_k3_pert"])
+def test_fgmres_solve_with_pressure_mass(name):
+    """C = c_p M_p, c_p > 0: K is regular, the coarse solve inverts K_0
+    without the zero-mean border and the solution is not shifted; the FGMRES
+    solution against the oracle's sparse direct solve of K x = b."""
+    from paper_2205_15770_amd import StokesMG
+    import scipy.sparse.linalg as spla
+    ora, _ = _setup(name, c_p=0.3)
+    cfg = CONFIGS[name]
+    L = ora.L
+    n_f = [c * 2 ** (cfg["levels"] - 1) for c in cfg["n_coarse"]]
+    mu_cell = si.uniform(int(np.prod(n_f)), 17, 0.5, 3.0)
+    gpu = StokesMG(dim=cfg["dim"], fe_degree=cfg["k"], n_coarse=cfg["n_coarse"], n_levels=cfg["levels"],
+                   mu_cell=mu_cell, gamma=PHYS["gamma"], rho=PHYS["rho"], c_pressure=0.3, precision="f32",
+                   fine_vertices=_vertices(name))
+    asm = ora.levels[L]
+    b = asm.rhs_from_nodal_f(si.nodal_random_f(cfg["dim"], ora.meshes[L].n_vnode, seed=5))
+    nu = asm.A.shape[0]
+    b[nu:] = si.uniform(len(b) - nu, 6)            # a pressure right-hand side with non-zero mean
+    x = torch.zeros(len(b), dtype=torch.float64, device="cuda")
+    gpu.solve(x, _dev(b), rtol=1e-10, maxit=100)
+    xs = x.cpu().numpy()
+    assert np.linalg.norm(b - asm.K @ xs) <= 1.05e-10 * np.linalg.norm(b)
+    xd = spla.spsolve(asm.K.tocsc(), b)
+    assert _rel(xs, xd) < 1e-6
+    gpu.close()
+
+
 def test_stationary_protocol_matches_oracle_rates():
     from oracle.krylov import stationary, rate_q
     ora, gpu = _setup("2d_k2", kA=3, kS=3, m=2)
