@@ -257,8 +257,9 @@ smg_status smg_batch_solve(smg_ctx *const *ctxs, int n, double *const *x, const 
 
 /* Autotuner for smg_batch_solve: times `probe_iterations` FGMRES iterations
  * of every instance for each thread count in candidates[0..ncand) and returns
- * the fastest in *best (wall times in times_ms[c] if not NULL).  Overwrites
- * x[i]. */
+ * the fastest in *best (wall times in times_ms[c] if not NULL); a candidate
+ * replaces an earlier one only if it is at least 3 % faster, so timing noise
+ * does not decide between near-equal counts.  Overwrites x[i]. */
 smg_status smg_batch_autotune(smg_ctx *const *ctxs, int n, double *const *x, const double *const *b,
                               const int *candidates, int ncand, int probe_iterations, int *best, double *times_ms);
 

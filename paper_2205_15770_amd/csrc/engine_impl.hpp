@@ -1533,7 +1533,13 @@ class EngineT : public EngineBase {
     auto t0 = std::chrono::steady_clock::now();
     const int64_t N = lv[L].N;
     const int m = restart;
-    const double bnorm = norm(b, N);
+    // ||b|| and the initial residual norm with one copy back
+    residual_t<double>(L, x, b, V);
+    multidot(b, 0, 1, b, N, dvec);
+    multidot(V, 0, 1, V, N, dvec + 1);
+    SMG_HIP(hipMemcpyAsync(hpin + 1000, dvec, 2 * sizeof(double), hipMemcpyDeviceToHost, stream));
+    SMG_HIP(hipStreamSynchronize(stream));
+    const double bnorm = std::sqrt(hpin[1000]), beta0 = std::sqrt(hpin[1001]);
     int hist_len = 0;
     auto record = [&](double v) {
       if (info && info->history && hist_len < info->history_capacity) info->history[hist_len] = v;
@@ -1546,8 +1552,7 @@ class EngineT : public EngineBase {
       vset<double>(x, 0.0, N);
       record(0.0);
     } else {
-      residual_t<double>(L, x, b, V);
-      double beta = norm(V, N);
+      double beta = beta0;
       rel = beta / bnorm;
       record(rel);
       std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), gv(m + 1);

@@ -475,7 +475,7 @@ smg_status smg_batch_autotune(smg_ctx *const *ctxs, int n, double *const *x, con
     const double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
     if (s != SMG_OK && s != SMG_ENOTCONV) return s;
     if (times_ms) times_ms[c] = ms;
-    if (ms < tbest) {
+    if (ms < 0.97 * tbest) {   // a clear gain only: near-equal timings keep the earlier count
       tbest = ms;
       *best = candidates[c];
     }
