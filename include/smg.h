@@ -34,7 +34,10 @@
  * the device that was current at smg_create, of the element type `dtype`
  * (SMG_F64: double, SMG_F32: float), contiguous, of the length stated.  The
  * library owns all level data and workspace, allocated once in smg_create and
- * released in smg_destroy; no other entry point allocates device memory.
+ * released in smg_destroy; apart from two first-use items (the HIP graph of
+ * the preconditioning cycle, on the first smg_solve; on box meshes the vertex
+ * lattice of smg_gradient, on its first call) no other entry point allocates
+ * device memory.
  *
  * Streams: all device work is enqueued on the stream of the context
  * (smg_desc.stream or smg_set_stream; NULL = the default stream).  Entry
