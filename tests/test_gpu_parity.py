@@ -444,6 +444,30 @@ def test_small_level_variants_equal_separate_launches(k, kA, kS, c_p):
     c.close()
 
 
+def test_small_level_variants_full_size_hierarchy():
+    """The three-stage launches on the 64^2 and 128^2 levels of the 512^2,
+    7-level hierarchy (the largest levels they run on) against the two-stage
+    fusion alone: smoothing steps agree to rounding."""
+    from paper_2205_15770_amd import StokesMG
+    kw = dict(dim=2, fe_degree=2, n_coarse=(8, 8), n_levels=7, gamma=1e3, rho=1.0)
+    a = StokesMG(**kw)
+    with _env(dict(env={"SMG_FUSE3_2D_MAX_N": "0"})):
+        c = StokesMG(**kw)
+    for l in (3, 4):
+        bA, bS = a.eigs(l)
+        c.set_eigs(l, bA, bS)
+        n = a.n_total(l)
+        for dtype, tol in ((torch.float64, 1e-13), (torch.float32, 1e-5)):
+            x0 = _dev(si.uniform(n, 80 + l), dtype)
+            rhs = _dev(si.uniform(n, 90 + l), dtype)
+            xa, xc = x0.clone(), x0.clone()
+            a.smooth(l, xa, rhs, 2)
+            c.smooth(l, xc, rhs, 2)
+            assert _rel(xa, xc.cpu().numpy().astype(np.float64)) < tol, (l, dtype)
+    a.close()
+    c.close()
+
+
 def test_vmult_is_deterministic():
     ora, gpu = _setup("2d_k2")
     l = ora.L
