@@ -83,6 +83,60 @@ def sample_Kx(mesh, x, dofs, mu=1.0, gamma=0.0, rho=1.0, c_p=0.0):
     return out
 
 
+def sample_abs_Kx(mesh, x, dofs, mu=1.0, gamma=0.0, rho=1.0, c_p=0.0):
+    """(|K| |x|)_i at the DoFs `dofs`: the entries K_ij of each sampled row
+    are summed over the cells around DoF i (per global column j), then
+    sum_j |K_ij| |x_j|.  The scale of the componentwise error measure
+    |y - K x|_i / (|K| |x|)_i of a computed y."""
+    d, k = mesh.dim, mesh.k
+    Nv = mesh.n_vnode
+    x = np.asarray(x, dtype=np.float64)
+    bnd = mesh.velocity_boundary_nodes()
+    mu_cell = mesh.mu(mu)
+    out = np.zeros(len(dofs))
+    for n_i, g in enumerate(dofs):
+        g = int(g)
+        row = {}
+        if g < d * Nv:
+            comp, node = divmod(g, Nv)
+            if bnd[node]:
+                out[n_i] = abs(x[g])
+                continue
+            lat = mesh._unflat(np.array([node]), mesh.vel_dims)[0]
+            cells = np.array(_cells_touching(mesh, lat, k))
+            A_t, B_t, _, _ = element_matrices(mesh, cells, mu_cell[cells], gamma, rho)
+            vn = mesh.cell_velocity_nodes(cells)
+            pn = mesh.cell_pressure_nodes(cells)
+            for c in range(len(cells)):
+                li = int(np.nonzero(vn[c] == node)[0][0])
+                for j, col in enumerate(vn[c]):
+                    if not bnd[col]:
+                        key = comp * Nv + int(col)
+                        row[key] = row.get(key, 0.0) + A_t[c, li, j]
+                for j, col in enumerate(pn[c]):
+                    key = d * Nv + int(col)
+                    row[key] = row.get(key, 0.0) + B_t[c, j, comp, li]
+        else:
+            node = g - d * Nv
+            lat = mesh._unflat(np.array([node]), mesh.p_dims)[0]
+            cells = np.array(_cells_touching(mesh, lat, k - 1))
+            A_t, B_t, Mp_t, _ = element_matrices(mesh, cells, mu_cell[cells], gamma, rho)
+            vn = mesh.cell_velocity_nodes(cells)
+            pn = mesh.cell_pressure_nodes(cells)
+            for c in range(len(cells)):
+                li = int(np.nonzero(pn[c] == node)[0][0])
+                for comp in range(d):
+                    for j, col in enumerate(vn[c]):
+                        if not bnd[col]:
+                            key = comp * Nv + int(col)
+                            row[key] = row.get(key, 0.0) + B_t[c, li, comp, j]
+                for j, col in enumerate(pn[c]):
+                    key = d * Nv + int(col)
+                    row[key] = row.get(key, 0.0) - c_p * Mp_t[c, li, j]
+        out[n_i] = sum(abs(v) * abs(x[key]) for key, v in row.items())
+    return out
+
+
 def velocity_stencil(mesh, dofs):
     """Velocity DoFs (same component) of the cells around each velocity DoF in
     `dofs`: the entries a row of A reads."""

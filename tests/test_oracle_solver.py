@@ -186,6 +186,28 @@ def test_kA0_schur_diagonal_identity():
     assert np.allclose(diagS, S.D_S / S.beta_A, rtol=1e-12)
 
 
+def test_local_schur_diagonal_matches_hand_derivation():
+    """D~_S_loc = sum_tau P_tau^T diag(B_tau diag(A_tau)^-1 B_tau^T) P_tau
+    (Sec. 3.3.1) against exact rationals derived by hand from the 1D textbook
+    element matrices (tests/golden/make_schur_loc_golden.py): non-square
+    Cartesian cells, per-cell viscosity and a mass term, 2D and 3D.  Using
+    the global diag(A), keeping the constrained velocity columns, or a
+    transposed cell shape each moves entries by far more than the tolerance."""
+    from fractions import Fraction
+    g = _gold("schur_loc_golden.json")
+    for cs in g["cases"]:
+        d = len(cs["n"])
+        hi = [float(Fraction(v)) for v in cs["box_hi"]]
+        mu = np.array([float(Fraction(v)) for v in cs["mu_cell"]])
+        mesh = BoxMesh(d, cs["n"], 2, lo=[0.0] * d, hi=hi, mu_cell=mu)
+        asm = Assembled(mesh, gamma=float(Fraction(cs["gamma_rho"])), rho=1.0)
+        ref = np.array([float(Fraction(v)) for v in cs["D_loc"]])
+        D = schur_diagonal(asm, "loc")
+        assert np.abs(D - ref).max() <= 1e-14 * np.abs(ref).max(), cs["name"]
+        # the assembled-B choice is a different diagonal on the same mesh
+        assert np.abs(schur_diagonal(asm, "d") - ref).max() > 0.1 * np.abs(ref).max()
+
+
 def test_schur_diagonal_choices_are_spectrally_equivalent():
     # the three choices of Sec. 3.3.1 are all ~ diag(M_p) (their analysis)
     for n in (4, 8, 16):
@@ -323,6 +345,19 @@ def test_sampled_rows_match_assembled_matrix():
     assert np.allclose(ys, y[dofs], rtol=1e-13, atol=1e-13)
 
 
+def test_sampled_abs_rows_match_assembled_matrix():
+    """(|K| |x|)_i of sampled rows, the scale of the componentwise parity
+    measure, against the assembled matrix with its entries made absolute."""
+    from oracle.rows import sample_abs_Kx
+    V = si.perturbed_box_vertices(4, dim=2, amplitude=0.2, seed=9)
+    mesh = BoxMesh(2, (4, 4), 3, vertices=V, mu_cell=np.linspace(1, 3, 16))
+    asm = Assembled(mesh, gamma=2.0, rho=0.5, c_p=0.3)
+    x = si.uniform(mesh.n_total, 5)
+    dofs = np.arange(0, mesh.n_total, 3)
+    ref = abs(asm.K) @ np.abs(x)
+    assert np.allclose(sample_abs_Kx(mesh, x, dofs, gamma=2.0, rho=0.5, c_p=0.3), ref[dofs], rtol=1e-13, atol=0)
+
+
 def test_sampled_diagonal_and_stencil_match_assembled_matrix():
     from oracle.rows import sample_diag_A, velocity_stencil
     V = si.perturbed_box_vertices(4, dim=2, amplitude=0.2, seed=9)
@@ -336,6 +371,97 @@ def test_sampled_diagonal_and_stencil_match_assembled_matrix():
     st = set(velocity_stencil(mesh, dofs).tolist())
     for g in dofs:
         assert set(Au.indices[Au.indptr[g]:Au.indptr[g + 1]].tolist()) <= st
+
+
+# --------------------------------------------------------------------------
+# the multigrid cycle as a linear iteration (Algorithm 1, Sec. 3.2)
+# --------------------------------------------------------------------------
+def _spectral_cheb_inverse(M, D, k, beta):
+    """sigma Cheb(M, D, k) as a dense matrix from the eigen-decomposition of
+    D^-1/2 M D^-1/2 and the closed-form residual polynomial s_k(t) = (1 -
+    T_{k+1}(t)) / t of the Chebyshev iteration on [beta/2, beta] (Lemma 1)."""
+    dh = 1.0 / np.sqrt(D)
+    lam, Q = np.linalg.eigh(dh[:, None] * M * dh[None, :])
+    alpha = beta / 2
+    T = _cheb_T_closed(k + 1, (beta + alpha - 2 * lam) / (beta - alpha)) / \
+        _cheb_T_closed(k + 1, np.array([(beta + alpha) / (beta - alpha)]))[0]
+    return scaling_constant(k) * (dh[:, None] * (Q * ((1.0 - T) / lam)) @ Q.T * dh[None, :])
+
+
+def _dense_smoother_inverse(asm, sm, kA, kS):
+    """K_hat^-1 of the compact form of the smoother (Sec. 3.3.1):
+    K_hat = [A_hat B^T; B B A_hat^-1 B^T - S_hat], A_hat, S_hat from the
+    spectral form above with the smoother's own bounds beta_A, beta_S."""
+    A, B, C = asm.A.toarray(), asm.B.toarray(), asm.C.toarray()
+    Ai = _spectral_cheb_inverse(A, np.diag(A), kA, sm.beta_A)
+    St = B @ Ai @ B.T + C
+    Si = _spectral_cheb_inverse(0.5 * (St + St.T), sm.D_S, kS, sm.beta_S)
+    Khat = np.block([[np.linalg.inv(Ai), B.T], [B, B @ Ai @ B.T - np.linalg.inv(Si)]])
+    return np.linalg.inv(Khat)
+
+
+def _coarse_pseudo_inverse(asm):
+    """Level-0 solve as a matrix: the Moore-Penrose inverse of K_0, each
+    column moved along the kernel vector (0, 1_p) to M_p-weighted pressure
+    mean zero (the zero-mean reading of Q = L^2_0); K_0^-1 when C != 0."""
+    K0 = asm.K.toarray()
+    if asm.c_p != 0.0:
+        return np.linalg.inv(K0)
+    n, nu = K0.shape[0], asm.A.shape[0]
+    X = np.linalg.pinv(K0, rcond=1e-13)
+    kern = np.zeros(n)
+    kern[nu:] = 1.0
+    m = np.zeros(n)
+    m[nu:] = asm.Mp @ np.ones(n - nu)
+    return X - np.outer(kern, m @ X) / (m @ kern)
+
+
+@pytest.mark.parametrize("levels,cycle,m,kA,kS,c_p", [(2, 1, 2, 1, 1, 0.0), (3, 1, 2, 1, 1, 0.0),
+                                                     (3, 2, 1, 2, 1, 0.0), (2, 1, 1, 3, 2, 0.4)])
+def test_cycle_is_the_multigrid_iteration(levels, cycle, m, kA, kS, c_p):
+    """Algorithm 1 is the affine map x -> E_l x + N_l b with E_0 = 0, N_0 =
+    K_0^+, and for l >= 1, with S = I - K_hat^-1 K_l (one smoothing step),
+    S_m = S^m, N_m = sum_{i<m} S^i K_hat^-1, G = sum_{j<gamma_MG} E_{l-1}^j
+    N_{l-1} (gamma_MG recursive calls from zero), CGC = I - P G P^T K_l
+    (the coarse-grid correction of Sec. 3.2):
+        E_l = S_m CGC S_m,   N_l = S_m (CGC N_m + P G P^T) + N_m.
+    The oracle's cycle probed with unit vectors must equal these matrices: the
+    error propagation everywhere, the right-hand-side map on consistent
+    right-hand sides (b_p orthogonal to the constants).  Dropping either
+    smoothing phase, the wrong number of recursive calls or a transposed
+    transfer changes E by O(1)."""
+    ms = make_hierarchy(2, (2, 2), levels, 2)
+    mg = Multigrid(ms, gamma=3.0, c_p=c_p, k_A=kA, k_S=kS, smooth_steps=m, cycle_index=cycle)
+    n = [mg.levels[l].K.shape[0] for l in range(levels)]
+    E = [np.zeros((n[0], n[0]))]
+    N = [_coarse_pseudo_inverse(mg.levels[0])]
+    for l in range(1, levels):
+        K = mg.levels[l].K.toarray()
+        I = np.eye(n[l])
+        Kh = _dense_smoother_inverse(mg.levels[l], mg.smoothers[l], kA, kS)
+        S = I - Kh @ K
+        Sm = np.linalg.matrix_power(S, m)
+        Nm = sum(np.linalg.matrix_power(S, i) for i in range(m)) @ Kh
+        P = mg.P[l].toarray()
+        G = sum(np.linalg.matrix_power(E[l - 1], j) for j in range(cycle)) @ N[l - 1]
+        CGC = I - P @ G @ P.T @ K
+        E.append(Sm @ CGC @ Sm)
+        N.append(Sm @ (CGC @ Nm + P @ G @ P.T) + Nm)
+    L = levels - 1
+    eye = np.eye(n[L])
+    E_cyc = np.column_stack([mg.cycle(L, eye[:, j], np.zeros(n[L])) for j in range(n[L])])
+    N_cyc = np.column_stack([mg.cycle(L, np.zeros(n[L]), eye[:, j]) for j in range(n[L])])
+    assert np.abs(E_cyc - E[L]).max() <= 1e-12 * np.abs(E[L]).max()
+    nu = mg.levels[L].A.shape[0]
+    Pi = eye.copy()
+    if c_p == 0.0:
+        kern = np.zeros(n[L])
+        kern[nu:] = 1.0
+        Pi -= np.outer(kern, kern) / (kern @ kern)
+    ref = N[L] @ Pi
+    assert np.abs(N_cyc @ Pi - ref).max() <= 1e-12 * np.abs(ref).max()
+    # the cycle without its post-smoothing is a different map
+    assert np.abs(E_cyc - CGC @ Sm).max() > 1e-3 * np.abs(E[L]).max()
 
 
 # --------------------------------------------------------------------------
