@@ -140,6 +140,8 @@ typedef struct {
   double rel_residual;     /* ||b - K x||_2 / ||b||_2 at return, FP64                  */
   double rate_q;           /* stationary protocol: (r_j / r_{j-3})^(1/3), Sec. 4.1     */
   double t_solve_ms;       /* wall time of the call                                    */
+  double t_setup_ms;       /* wall time of smg_create for this context (hierarchy,     */
+                           /* diagonals, eigenvalue bounds, coarse inverse)            */
   double *history;         /* HOST array provided by the caller or NULL; receives the  */
   int history_capacity;    /* relative residual per iteration (entry 0 = initial)      */
   int history_len;         /* entries written                                          */
@@ -285,6 +287,16 @@ smg_status smg_node_coordinates(const smg_ctx *ctx, int level, double *xyz);
  * one entry per finest cell (x fastest), or NULL.  g_f: DEVICE FP64, length
  * d*Nv, or NULL.  Asynchronous on the context's stream. */
 smg_status smg_gradient(smg_ctx *ctx, const double *x, const double *lam, double *g_logmu, double *g_f);
+
+/* Transpose of the pressure normalisation that smg_solve applies to its
+ * result (Sec. 2: the pressure space is L^2_0; the returned pressure has
+ * M_p-weighted mean zero, p <- p - 1 (m . p) / (m . 1), m = M_p 1), for
+ * adjoint computations: with J depending on the normalised solution, the
+ * adjoint right-hand side is g <- g_p - m (1 . g_p) / (m . 1) on the pressure
+ * block (velocity block unchanged).  With c_pressure > 0 the solution is not
+ * normalised and g is left as it is.  g: DEVICE FP64, length N of the finest
+ * level, in place.  Asynchronous on the context's stream. */
+smg_status smg_pressure_mean_adjoint(smg_ctx *ctx, double *g);
 
 /* Kernel timing for measurement: with enable != 0, every later operator-kernel
  * launch of this context is bracketed by two HIP events recorded on the

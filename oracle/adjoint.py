@@ -35,6 +35,30 @@ def bordered_solve(asm, rhs):
     return spla.spsolve(Kb, np.concatenate([rhs, [0.0]]))[:-1]
 
 
+def state_solve(asm, rhs):
+    """The solution map of Section 2's discrete problem: for C = 0 the
+    pressure is fixed up to a constant and the bordered solve above returns
+    the one with M_p-weighted mean zero; for C = c_p M_p, c_p > 0, K is
+    regular and solved as it is."""
+    if asm.c_p == 0.0:
+        return bordered_solve(asm, rhs)
+    return spla.spsolve(asm.K.tocsc(), rhs)
+
+
+def normalisation_adjoint(asm, g):
+    """Transpose of the pressure normalisation p <- p - 1 (m.p)/(m.1), m =
+    M_p 1, applied to an adjoint right-hand side g (velocity block
+    unchanged): g_p <- g_p - m (1.g_p)/(m.1).  Identity for C != 0, where the
+    solution is not normalised."""
+    if asm.c_p != 0.0:
+        return g.copy()
+    nu = asm.A.shape[0]
+    m = asm.Mp @ np.ones(asm.Mp.shape[0])
+    out = g.copy()
+    out[nu:] = g[nu:] - m * (g[nu:].sum() / m.sum())
+    return out
+
+
 def rhs_from_force(asm, f_nodal):
     """b = [Z M_v f; 0] for a nodal velocity field f of shape (d, Nv)."""
     return asm.rhs_from_nodal_f(np.asarray(f_nodal).reshape(asm.mesh.dim, -1))

@@ -231,7 +231,7 @@ class StokesMG:
         info.history_capacity = len(hist)
         st = fn(self._h, _ptr(x), _ptr(b), float(rtol), int(maxit), ctypes.byref(info))
         out = {"status": st, "iterations": info.iterations, "rel_residual": info.rel_residual,
-               "rate_q": info.rate_q, "t_solve_ms": info.t_solve_ms,
+               "rate_q": info.rate_q, "t_solve_ms": info.t_solve_ms, "t_setup_ms": info.t_setup_ms,
                "history": hist[:info.history_len].copy()}
         if st != _lib.SMG_OK and raise_on_failure:
             _lib.check(st)
@@ -280,6 +280,17 @@ class StokesMG:
                                          _ptr(g_logmu) if want_logmu else None,
                                          _ptr(g_f) if want_f else None))
         return (g_logmu if want_logmu else None), (g_f if want_f else None)
+
+    def pressure_mean_adjoint(self, g):
+        """In place on the float64 finest-level vector g: the transpose of the
+        pressure normalisation of solve (smg_pressure_mean_adjoint); no-op
+        when c_pressure > 0."""
+        import torch
+        self._check(g, self.n_total(self.n_levels - 1), "g")
+        if g.dtype != torch.float64:
+            raise TypeError("pressure_mean_adjoint works on float64 vectors")
+        _lib.check(self.lib.smg_pressure_mean_adjoint(self._h, _ptr(g)))
+        return g
 
     def cells(self, level):
         """Cells per direction of a level."""

@@ -24,7 +24,8 @@ EXPORTS = ["smg_desc_default", "smg_create", "smg_destroy", "smg_sizes", "smg_se
            "smg_set_eigs", "smg_chebyshev", "smg_smooth", "smg_restrict", "smg_prolongate_add",
            "smg_coarse_solve", "smg_vcycle", "smg_solve", "smg_solve_stationary", "smg_batch_solve",
            "smg_batch_autotune",
-           "smg_node_coordinates", "smg_gradient", "smg_profile", "smg_profile_report", "smg_last_error"]
+           "smg_node_coordinates", "smg_gradient", "smg_pressure_mean_adjoint", "smg_profile", "smg_profile_report",
+           "smg_last_error"]
 
 
 class SmgDesc(ctypes.Structure):
@@ -42,7 +43,7 @@ class SmgDesc(ctypes.Structure):
 
 class SmgSolveInfo(ctypes.Structure):
     _fields_ = [("iterations", ctypes.c_int), ("rel_residual", ctypes.c_double),
-                ("rate_q", ctypes.c_double), ("t_solve_ms", ctypes.c_double),
+                ("rate_q", ctypes.c_double), ("t_solve_ms", ctypes.c_double), ("t_setup_ms", ctypes.c_double),
                 ("history", ctypes.POINTER(ctypes.c_double)), ("history_capacity", ctypes.c_int),
                 ("history_len", ctypes.c_int)]
 
@@ -95,6 +96,7 @@ def load(path=LIB_PATH):
                                    ctypes.POINTER(I), I, I, ctypes.POINTER(I), ctypes.POINTER(D)]),
         "smg_node_coordinates": (I, [P, I, P]),
         "smg_gradient": (I, [P, P, P, P, P]),
+        "smg_pressure_mean_adjoint": (I, [P, P]),
         "smg_profile": (I, [P, I]),
         "smg_profile_report": (I, [P, ctypes.c_char_p, ctypes.c_int64, i64p]),
         "smg_last_error": (ctypes.c_char_p, []),

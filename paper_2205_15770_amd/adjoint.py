@@ -13,7 +13,7 @@ diagonals, eigenvalue bounds and the coarse inverse depend on mu).
 """
 import torch
 
-from . import StokesMG, SMG_BLOCK_MASS, SMG_BLOCK_MP
+from . import StokesMG, SMG_BLOCK_MASS
 
 
 class StokesSolve(torch.autograd.Function):
@@ -35,15 +35,12 @@ class StokesSolve(torch.autograd.Function):
     def backward(ctx, gx):
         (x,) = ctx.saved_tensors
         mg = ctx.mg
-        L = mg.n_levels - 1
-        nu, np_ = mg.sizes(L)
         g = gx.detach().to(torch.float64).contiguous().clone()
-        if torch.count_nonzero(g[nu:]) > 0:
-            # the returned pressure is normalised, p <- p - (m.p)/(m.1) with
-            # m = M_p 1; the adjoint of that map keeps the right-hand side
-            # orthogonal to the constant pressure
-            m = mg.apply_block(L, SMG_BLOCK_MP, torch.ones(np_, dtype=torch.float64, device=g.device))
-            g[nu:] -= m * (g[nu:].sum() / m.sum())
+        # for C = 0 the returned pressure is normalised to M_p-weighted mean
+        # zero; the transpose of that map (a library call, which leaves g as
+        # it is for C != 0, where nothing is normalised) makes the adjoint
+        # right-hand side orthogonal to the constant pressure
+        mg.pressure_mean_adjoint(g)
         lam = torch.zeros_like(g)
         if torch.count_nonzero(g) > 0:
             mg.solve(lam, g, rtol=ctx.rtol, maxit=ctx.maxit)

@@ -61,6 +61,7 @@ class EngineBase {
   std::vector<LevelInfo> lv;
   hipStream_t stream = nullptr;
   int L = 0;  // finest level index
+  double t_setup_ms = 0;  // wall time of setup()
 
   virtual void setup() = 0;
   virtual void vmult(int l, int dt, const void *x, void *y) = 0;
@@ -78,6 +79,7 @@ class EngineBase {
   virtual smg_status solve_stationary(double *x, const double *b, double rtol, int maxit, smg_solve_info *info) = 0;
   virtual void node_coordinates(int l, double *xyz) = 0;
   virtual void gradient(const double *x, const double *lam, double *g_logmu, double *g_f) = 0;
+  virtual void pressure_mean_adjoint(double *g) = 0;
   virtual void invalidate_graphs() {}
   bool use_graphs = true;
 

@@ -1056,6 +1056,17 @@ class EngineT : public EngineBase {
     check_launch();
   }
 
+  // transpose of remove_pressure_mean: g_p -= M_p 1 (1 . g_p) / (1 . M_p 1);
+  // nothing to do for C != 0, where solutions are not normalised
+  void pressure_mean_adjoint(double *g) override {
+    if (has_c()) return;
+    const LevelInfo &I = lv[L];
+    multidot(unit_vec(I.Np), 0, 1, g + I.Nu, I.Np, dvec);
+    hipLaunchKernelGGL(k_subtract_weighted, dim3(grid_for(I.Np)), dim3(VB), 0, stream, g + I.Nu, (const double *)I.mp1,
+                       (const double *)dvec, mp1_sum, (i64)I.Np);
+    check_launch();
+  }
+
   // ------------------------------------------------------------- set-up
   double lanczos(int l, int which) {
     const LevelInfo &I = lv[l];
@@ -1657,6 +1668,7 @@ class EngineT : public EngineBase {
       info->rate_q = 0.0;
       info->history_len = std::min(hist_len, info->history_capacity);
       info->t_solve_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+      info->t_setup_ms = t_setup_ms;
     }
     return st;
   }
@@ -1691,6 +1703,7 @@ class EngineT : public EngineBase {
         if (info->history && (int)i < info->history_capacity) { info->history[i] = r0 > 0 ? hist[i] / r0 : 0.0; ++n; }
       info->history_len = n;
       info->t_solve_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+      info->t_setup_ms = t_setup_ms;
     }
     return st;
   }

@@ -180,7 +180,9 @@ smg_status smg_create(const smg_desc *desc, smg_ctx **out) {
     int dev = 0;
     SMG_HIP(hipGetDevice(&dev));
     ctx->device = dev;
+    const auto t0 = std::chrono::steady_clock::now();
     eng->setup();
+    eng->t_setup_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
     eng->desc.mu_cell = nullptr;
     eng->desc.fine_vertices = nullptr;
   } catch (const smg::Error &e) {
@@ -489,6 +491,13 @@ smg_status smg_gradient(smg_ctx *ctx, const double *x, const double *lam, double
   if (s == SMG_OK) s = check_ptrs({x, lam});
   if (s != SMG_OK) return s;
   SMG_TRY(ctx->eng->gradient(x, lam, g_logmu, g_f));
+}
+
+smg_status smg_pressure_mean_adjoint(smg_ctx *ctx, double *g) {
+  smg_status s = check_ctx(ctx);
+  if (s == SMG_OK) s = check_ptrs({g});
+  if (s != SMG_OK) return s;
+  SMG_TRY(ctx->eng->pressure_mean_adjoint(g));
 }
 
 smg_status smg_profile(smg_ctx *ctx, int enable) {

@@ -143,4 +143,10 @@ static __global__ void k_subtract_scalar(double *p, const double *scal, double d
   SMG_GRID_LOOP(i, n) p[i] -= m;
 }
 
+// g -= w (1 . g) / (w . 1): the transpose of the mean removal above
+static __global__ void k_subtract_weighted(double *g, const double *w, const double *scal, double denom, i64 n) {
+  const double m = scal[0] / denom;
+  SMG_GRID_LOOP(i, n) g[i] -= w[i] * m;
+}
+
 }  // namespace smg

@@ -117,3 +117,51 @@ def test_autograd_central_differences(name):
             fd = (J(f0 + h * df, lm0 + h * dl) - J(f0 - h * df, lm0 - h * dl)).item() / (2 * h)
         an = (lm.grad @ dl + f.grad @ df).item()
         assert abs(fd - an) <= 1e-5 * abs(an) + 1e-6 * loss.item(), (fd, an)
+
+
+@pytest.mark.parametrize("c_p", [0.0, 0.5])
+def test_autograd_pressure_objective(c_p):
+    """J = ||u - u_t||^2 + ||p - p_t||^2 depends on the pressure.  For C = 0
+    the returned pressure is normalised to mean zero and the adjoint
+    right-hand side takes the transpose of that normalisation; for C = c_p
+    M_p, c_p > 0, nothing is normalised and the adjoint solve is the plain
+    one.  Gradients against the oracle's adjoint (direct solves of the same
+    system) and against central differences."""
+    from paper_2205_15770_amd.adjoint import solve
+    from oracle.adjoint import state_solve, normalisation_adjoint
+    c, n_f, V, logmu, problem = _case("2d_k2_pert")
+    problem = dict(problem, c_pressure=c_p)
+    nu = c["dim"] * int(np.prod([c["k"] * v + 1 for v in n_f]))
+    f0 = si.uniform(nu, 44)
+    meshes = make_hierarchy(c["dim"], c["n_coarse"], c["levels"], c["k"], fine_mu=np.exp(logmu), fine_vertices=V)
+    asm = Assembled(meshes[-1], gamma=GAMMA, rho=1.0, c_p=c_p)
+    n = asm.K.shape[0]
+    target = si.uniform(n, 46)
+    x = state_solve(asm, rhs_from_force(asm, f0))
+    J = float((x - target) @ (x - target))
+    lam = state_solve(asm, normalisation_adjoint(asm, 2.0 * (x - target)))
+    g_mu, g_f = gradients(asm, x, lam)
+    tg = torch.tensor(target, dtype=torch.float64, device="cuda")
+
+    def Jg(f, lm):
+        xg = solve(f, lm, rtol=1e-13, **problem)
+        return ((xg - tg) ** 2).sum()
+
+    f = torch.tensor(f0, dtype=torch.float64, device="cuda", requires_grad=True)
+    lm = torch.tensor(logmu, dtype=torch.float64, device="cuda", requires_grad=True)
+    loss = Jg(f, lm)
+    loss.backward()
+    assert abs(loss.item() - J) <= 1e-9 * J
+    assert _rel(lm.grad, g_mu) < 1e-8
+    assert _rel(f.grad, g_f) < 1e-8
+    rng = np.random.default_rng(11)
+    h = 1e-6
+    f0t = torch.tensor(f0, dtype=torch.float64, device="cuda")
+    lm0 = torch.tensor(logmu, dtype=torch.float64, device="cuda")
+    for _ in range(4):
+        dl = torch.tensor(rng.standard_normal(len(logmu)), dtype=torch.float64, device="cuda")
+        df = torch.tensor(rng.standard_normal(nu), dtype=torch.float64, device="cuda")
+        with torch.no_grad():
+            fd = (Jg(f0t + h * df, lm0 + h * dl) - Jg(f0t - h * df, lm0 - h * dl)).item() / (2 * h)
+        an = (lm.grad @ dl + f.grad @ df).item()
+        assert abs(fd - an) <= 1e-5 * abs(an) + 1e-6 * loss.item(), (fd, an)

@@ -2,10 +2,13 @@
 the FP64 CPU oracle on the same seeded inputs.
 
 Sizes: meshes the oracle assembles in seconds that still span several tiles
-with ragged last tiles in every direction (2D tiles own 15 x 15 cells, 3D
-tiles 3 x 3 x 3 (k = 2) / 2 x 2 x 2 (k = 3) cells).  Tolerances:
+with ragged last tiles in every direction (2D wave tiles own 7 x 7 cells, or
+5 x 5 / 3 x 3 in the two- and three-stage fused launches; 3D column sweeps
+own 7 x 7 cell columns, cell blocks 3 x 3 x 3 cells).  Tolerances:
   * FP64 operator applications: relative 2-norm error <= 1e-12 (a few hundred
-    roundings of O(1) terms per entry on random inputs);
+    roundings of O(1) terms per entry on random inputs), and componentwise
+    max_i |y - y_o|_i / (|K| |x|)_i <= 1e-12 (1e-4 in FP32), which is not
+    hidden by cancellation in K x;
   * FP64 iterations (Chebyshev, smoother, cycle): <= 1e-10 (the same linear
     maps composed; rounding differences grow by the iteration's norm);
   * FP32: <= 2e-5 relative (single-precision roundings, same count).
@@ -22,7 +25,7 @@ import synth_inputs as si
 from oracle.mesh import make_hierarchy
 from oracle.mg import Multigrid, pressure_mean_free
 from oracle.smoother import LevelSmoother
-from oracle.rows import sample_Kx
+from oracle.rows import sample_Kx, sample_abs_Kx
 
 pytestmark = pytest.mark.gpu
 
@@ -111,6 +114,16 @@ def _rel(a, b):
     return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300)
 
 
+def _compwise(y, ref, scale):
+    """max_i |y - ref|_i / scale_i with scale = |K| |x| (rows with scale 0
+    must match exactly)."""
+    y = y.detach().cpu().numpy().astype(np.float64) if torch.is_tensor(y) else np.asarray(y, dtype=np.float64)
+    d = np.abs(y - ref)
+    z = scale == 0
+    assert not np.any(d[z] != 0)
+    return float(np.max(d[~z] / scale[~z])) if np.any(~z) else 0.0
+
+
 def _inject_betas(ora, gpu):
     for l in range(1, ora.L + 1):
         gpu.set_eigs(l, ora.smoothers[l].beta_A, ora.smoothers[l].beta_S)
@@ -126,6 +139,8 @@ def test_vmult_fp64_every_level(name, c_p):
         y = gpu.vmult(l, _dev(x))
         err = _rel(y, K @ x)
         assert err < 1e-12, (name, l, err)
+        cw = _compwise(y, K @ x, abs(K) @ np.abs(x))
+        assert cw < 1e-12, (name, l, cw)
 
 
 @pytest.mark.parametrize("name", list(CONFIGS))
@@ -134,7 +149,10 @@ def test_vmult_fp32(name):
     l = ora.L
     x = si.uniform(ora.levels[l].K.shape[0], 5)
     y = gpu.vmult(l, _dev(x, torch.float32))
-    assert _rel(y, ora.levels[l].K @ x.astype(np.float32).astype(np.float64)) < 2e-5
+    x32 = x.astype(np.float32).astype(np.float64)
+    K = ora.levels[l].K
+    assert _rel(y, K @ x32) < 2e-5
+    assert _compwise(y, K @ x32, abs(K) @ np.abs(x32)) < 1e-4
 
 
 @pytest.mark.parametrize("name", list(CONFIGS))
@@ -395,11 +413,20 @@ def test_c1_protocol_16x16_stationary():
     xo, hist = stationary(asm.K, lambda x, b: ora.cycle(L, x, b), b, rtol=1e-10, maxit=30)
     h = np.array(hist) / hist[0]
     assert info["iterations"] == len(hist) - 1
-    # early residuals agree to rounding; late ones (1e-10 of the first) carry
-    # the rounding differences of the iterates, amplified by cond(K)
-    assert np.allclose(info["history"][:4], h[:4], rtol=1e-6)
-    assert np.allclose(info["history"], h, rtol=1e-2)
-    assert abs(info["rate_q"] - rate_q(hist)) < 1e-2 * rate_q(hist)
+    # Both sides run the same iteration; their iterates differ by rounding,
+    # so the computed relative residuals differ by up to about
+    # eps * cond(K) (cond(K) ~ 1.1e5 here, on the complement of the constant
+    # pressure) in absolute terms, besides 1e-6 relative: the early entries
+    # agree to 1e-6, the late ones (~1e-10) to ~10 %.
+    sv = np.linalg.svd(asm.K.toarray(), compute_uv=False)
+    floor = np.finfo(np.float64).eps * sv[0] / sv[-2]
+    hg = np.array(info["history"])
+    assert np.all(np.abs(hg - h) <= 1e-6 * h + floor), (np.abs(hg - h) / h).max()
+    # q = (h_j / h_{j-3})^(1/3): its rounding bound follows from the same floor
+    j = len(h) - 1
+    q = rate_q(hist)
+    tol_q = 1e-6 * q + q * floor * (1.0 / h[j] + 1.0 / h[j - 3]) / 3.0
+    assert abs(info["rate_q"] - q) <= tol_q, (info["rate_q"], q, tol_q)
     assert _rel(x, pressure_mean_free(asm, xo)) < 1e-8
     gpu.close()
 
@@ -499,6 +526,8 @@ def test_full_size_2d_512_sampled_rows(dtype, tol):
         ref = sample_Kx(mesh, xin, dofs, gamma=1e3, rho=1.0)
         err = np.linalg.norm(y[dofs] - ref) / np.linalg.norm(ref)
         assert err < tol, L
+        cw = _compwise(y[dofs], ref, sample_abs_Kx(mesh, xin, dofs, gamma=1e3, rho=1.0))
+        assert cw < (1e-12 if dtype == torch.float64 else 1e-4), (L, cw)
     gpu.close()
 
 
@@ -567,6 +596,8 @@ def test_full_size_3d_64_sampled_rows(dtype, tol):
         xin = x if dtype == torch.float64 else x.astype(np.float32).astype(np.float64)
         ref = sample_Kx(mesh, xin, dofs)
         assert np.linalg.norm(y[dofs] - ref) / np.linalg.norm(ref) < tol, L
+        cw = _compwise(y[dofs], ref, sample_abs_Kx(mesh, xin, dofs))
+        assert cw < (1e-12 if dtype == torch.float64 else 1e-4), (L, cw)
     gpu.close()
 
 
@@ -592,6 +623,8 @@ def test_full_size_3d_q3_32_perturbed_sampled_rows(dtype, tol):
     xin = x if dtype == torch.float64 else x.astype(np.float32).astype(np.float64)
     ref = sample_Kx(mesh, xin, dofs)
     assert np.linalg.norm(y[dofs] - ref) / np.linalg.norm(ref) < tol
+    cw = _compwise(y[dofs], ref, sample_abs_Kx(mesh, xin, dofs))
+    assert cw < (1e-12 if dtype == torch.float64 else 1e-4), cw
     gpu.close()
 
 
