@@ -173,6 +173,22 @@ smg_status smg_set_stream(smg_ctx *ctx, void *stream);
  * saddle-point operator.  x, y length N, distinct. */
 smg_status smg_vmult(smg_ctx *ctx, int level, int dtype, const void *x, void *y);
 
+/* y = K_l x as smg_vmult, allocating nothing: for callers that cannot
+ * allocate device memory while they run (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc).  The per-cell partial
+ * results that the vertex-given (multilinear) cell kernels produce before
+ * summing them per node live in one fixed 16 MiB device buffer per GPU
+ * (a static device array, held until the process ends; its address is
+ * looked up once per device in smg_create) instead of the level's own
+ * buffer; box-cell kernels need no such buffer.  Levels whose partial
+ * results need more than 16 MiB (about 9,500 3D Q3 cells in FP64, 23,500 3D
+ * Q2 cells, 95,000 2D Q2 cells) are rejected with SMG_EINVAL before any
+ * device work.  Every call on one GPU shares that buffer: calls that overlap
+ * on one GPU (other streams, other threads, other contexts) race and must be
+ * ordered by the caller.  Kernel timing (smg_profile) does not record these
+ * launches.  x, y as smg_vmult; asynchronous on the context's stream. */
+smg_status smg_vmult_noalloc(smg_ctx *ctx, int level, int dtype, const void *x, void *y);
+
 /* r = b - K_l x (Algorithm 1, residual step).  r may alias neither x nor b. */
 smg_status smg_residual(smg_ctx *ctx, int level, int dtype, const void *x, const void *b, void *r);
 

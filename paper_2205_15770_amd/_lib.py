@@ -20,7 +20,7 @@ STATUS_NAMES = {0: "SMG_OK", -1: "SMG_EINVAL", -2: "SMG_ENOMEM", -3: "SMG_EDEVIC
                 -4: "SMG_ENOTCONV", -5: "SMG_EBREAKDOWN", -6: "SMG_EUNSUPPORTED"}
 
 EXPORTS = ["smg_desc_default", "smg_create", "smg_destroy", "smg_sizes", "smg_set_stream",
-           "smg_vmult", "smg_residual", "smg_apply_block", "smg_lift_dirichlet", "smg_insert_dirichlet", "smg_get_diagonal", "smg_get_eigs",
+           "smg_vmult", "smg_vmult_noalloc", "smg_residual", "smg_apply_block", "smg_lift_dirichlet", "smg_insert_dirichlet", "smg_get_diagonal", "smg_get_eigs",
            "smg_set_eigs", "smg_chebyshev", "smg_smooth", "smg_restrict", "smg_prolongate_add",
            "smg_coarse_solve", "smg_vcycle", "smg_solve", "smg_solve_stationary", "smg_batch_solve",
            "smg_batch_autotune",
@@ -75,6 +75,7 @@ def load(path=LIB_PATH):
         "smg_sizes": (I, [P, I, i64p, i64p]),
         "smg_set_stream": (I, [P, P]),
         "smg_vmult": (I, [P, I, I, P, P]),
+        "smg_vmult_noalloc": (I, [P, I, I, P, P]),
         "smg_residual": (I, [P, I, I, P, P, P]),
         "smg_apply_block": (I, [P, I, I, I, P, P]),
         "smg_lift_dirichlet": (I, [P, I, I, P, P]),

@@ -80,6 +80,11 @@ class EngineBase {
   virtual void node_coordinates(int l, double *xyz) = 0;
   virtual void gradient(const double *x, const double *lam, double *g_logmu, double *g_f) = 0;
   virtual void pressure_mean_adjoint(double *g) = 0;
+  // y = K_l x with the per-cell partial results of vertex-given cells in a
+  // caller-provided device buffer instead of the level's own (box-cell
+  // kernels need none); no allocation, no kernel timing.
+  virtual int64_t vmult_scratch_bytes(int l, int dt) const = 0;
+  virtual void vmult_scratch(int l, int dt, const void *x, void *y, void *scratch) = 0;
   virtual void invalidate_graphs() {}
   bool use_graphs = true;
 

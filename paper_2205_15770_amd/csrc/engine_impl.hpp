@@ -588,6 +588,45 @@ class EngineT : public EngineBase {
     else tile<T, BLK_A | BLK_BT | BLK_B>(g, op);
   }
 
+  // bytes of the per-cell results of one operator application on level l
+  // (vertex-given cells; 0 for the box-cell kernels), the pressure part
+  // starting at a 256-byte boundary
+  int64_t vmult_scratch_bytes(int l, int dt) const override {
+    if (!gen_op) return 0;
+    constexpr int64_t NN = DIM == 3 ? (K + 1) * (K + 1) * (K + 1) : (K + 1) * (K + 1);
+    constexpr int64_t NPN = DIM == 3 ? K * K * K : K * K;
+    const int64_t es = dt == SMG_F32 ? 4 : 8;
+    const int64_t nc = (int64_t)lv[l].n[0] * lv[l].n[1] * (DIM == 3 ? lv[l].n[2] : 1);
+    return (nc * DIM * NN * es + 255) / 256 * 256 + nc * NPN * es;
+  }
+
+  void vmult_scratch(int l, int dt, const void *x, void *y, void *scratch) override {
+    const bool saved = profiling;   // kernel timing would create events
+    profiling = false;
+    try {
+      if (dt == SMG_F32) vmult_scratch_t<float>(l, (const float *)x, (float *)y, scratch);
+      else vmult_scratch_t<double>(l, (const double *)x, (double *)y, scratch);
+    } catch (...) {
+      profiling = saved;
+      throw;
+    }
+    profiling = saved;
+  }
+
+  template <typename T>
+  void vmult_scratch_t(int l, const T *x, T *y, void *scratch) {
+    auto g = geom<T>(l);
+    if (gen_op) {
+      constexpr int64_t NN = DIM == 3 ? (K + 1) * (K + 1) * (K + 1) : (K + 1) * (K + 1);
+      const int64_t nc = (int64_t)lv[l].n[0] * lv[l].n[1] * (DIM == 3 ? lv[l].n[2] : 1);
+      g.cbu = (T *)scratch;
+      g.cbp = (T *)((char *)scratch + (nc * DIM * NN * (int64_t)sizeof(T) + 255) / 256 * 256);
+    }
+    OpApply<T> op{x, x + lv[l].Nu, y, y + lv[l].Nu};
+    if (has_c()) tile<T, BLK_A | BLK_BT | BLK_B | BLK_C>(g, op);
+    else tile<T, BLK_A | BLK_BT | BLK_B>(g, op);
+  }
+
   template <typename T>
   void residual_t(int l, const T *x, const T *b, T *r) {
     auto g = geom<T>(l);

@@ -6,6 +6,7 @@
 
 #include <chrono>
 #include <map>
+#include <mutex>
 #include <thread>
 #include <vector>
 
@@ -45,7 +46,37 @@ EngineBase *make_engine_3_3();
 struct smg_ctx {
   smg::EngineBase *eng = nullptr;
   int device = 0;
+  void *scratch = nullptr;   // this device's address of `scratch` below (nullptr if unavailable)
 };
+
+// Fixed device buffer of smg_vmult_noalloc: the per-cell partial results of
+// vertex-given cells.  One copy per GPU the library runs on, held until the
+// process ends.  Host code never passes `scratch` itself to a kernel (on the
+// host the name is only a stand-in): its device address comes from
+// hipGetSymbolAddress, once per device (scratch_address below).
+#define SMG_NOALLOC_SCRATCH_BYTES (16u << 20)
+static __device__ __align__(256) unsigned char scratch[SMG_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+std::mutex g_scratch_mu;
+std::map<int, void *> g_scratch_addr;   // device -> address of `scratch` there
+
+// The address of `scratch` on device `dev`, which must be the current device.
+hipError_t scratch_address(int dev, void **out) {
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  auto it = g_scratch_addr.find(dev);
+  if (it != g_scratch_addr.end()) {
+    *out = it->second;
+    return hipSuccess;
+  }
+  void *p = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+  if (e != hipSuccess) return e;
+  g_scratch_addr[dev] = p;
+  *out = p;
+  return hipSuccess;
+}
+}  // namespace
 
 namespace {
 
@@ -183,6 +214,11 @@ smg_status smg_create(const smg_desc *desc, smg_ctx **out) {
     const auto t0 = std::chrono::steady_clock::now();
     eng->setup();
     eng->t_setup_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    // the allocation-free entry point's buffer on this device (set-up, so that
+    // the entry point itself makes no runtime call besides its launches)
+    void *sp = nullptr;
+    if (scratch_address(dev, &sp) == hipSuccess) ctx->scratch = sp;
+    else (void)hipGetLastError();   // leave no sticky error for the next call
     eng->desc.mu_cell = nullptr;
     eng->desc.fine_vertices = nullptr;
   } catch (const smg::Error &e) {
@@ -236,6 +272,22 @@ smg_status smg_vmult(smg_ctx *ctx, int level, int dtype, const void *x, void *y)
   if (s != SMG_OK) return s;
   if (x == y) return fail(SMG_EINVAL, "x and y must be distinct");
   SMG_TRY(ctx->eng->vmult(level, dtype, x, y));
+}
+
+smg_status smg_vmult_noalloc(smg_ctx *ctx, int level, int dtype, const void *x, void *y) {
+  smg_status s = check_level(ctx, level);
+  if (s == SMG_OK) s = check_dtype(dtype);
+  if (s == SMG_OK) s = check_ptrs({x, y});
+  if (s != SMG_OK) return s;
+  if (x == y) return fail(SMG_EINVAL, "x and y must be distinct");
+  const int64_t need = ctx->eng->vmult_scratch_bytes(level, dtype);
+  if (need > (int64_t)SMG_NOALLOC_SCRATCH_BYTES)
+    return fail(SMG_EINVAL, "level " + std::to_string(level) + " needs " + std::to_string(need) +
+                                " bytes of scratch, more than the fixed " + std::to_string(SMG_NOALLOC_SCRATCH_BYTES) +
+                                " of smg_vmult_noalloc (use smg_vmult)");
+  if (need > 0 && ctx->scratch == nullptr)
+    return fail(SMG_EDEVICE, "hipGetSymbolAddress of the fixed scratch buffer failed at smg_create");
+  SMG_TRY(ctx->eng->vmult_scratch(level, dtype, x, y, ctx->scratch));
 }
 
 smg_status smg_residual(smg_ctx *ctx, int level, int dtype, const void *x, const void *b, void *r) {
