@@ -11,7 +11,7 @@ enum : int { BLK_A = 1, BLK_MASS = 2, BLK_BT = 4, BLK_B = 8, BLK_C = 16, BLK_CPL
 
 // Bijection blockIdx -> tile such that the blocks of one XCD (b % 8 == k) take
 // the contiguous tile range [prefix_k, prefix_k + count_k).
-__device__ __forceinline__ int xcd_contiguous_tile(int b, int nb) {
+__host__ __device__ __forceinline__ int xcd_contiguous_tile(int b, int nb) {
   constexpr int NXCD = 8;
   const int k = b % NXCD;
   int prefix = 0;

@@ -64,7 +64,7 @@ struct Column3D {
   uint32_t base_p;     // byte offset of the column's first pressure node
   uint32_t suy, suz, spy, spz;  // byte strides of the velocity / pressure lattices
   uint32_t cell0, cell_sz;      // cell index of the column's first cell, cells per layer
-  __device__ Column3D(const Geo3<T> &g_, int cx, int cy) : g(g_), gcx(cx), gcy(cy) {
+  __host__ __device__ Column3D(const Geo3<T> &g_, int cx, int cy) : g(g_), gcx(cx), gcy(cy) {
     active = cx >= 0 && cx < g.n[0] && cy >= 0 && cy < g.n[1];
     bxl = cx == 0;
     bxh = cx == g.n[0] - 1;
@@ -82,21 +82,22 @@ struct Column3D {
     cell0 = (uint32_t)ax + (uint32_t)g.n[0] * (uint32_t)ay;
     cell_sz = (uint32_t)g.n[0] * (uint32_t)g.n[1];
   }
+  __host__ __device__ uint32_t mu_index(int cz) const { return cell0 + cell_sz * (uint32_t)cz; }
   __device__ T mu_at(int cz) const {
-    if (g.mu_cell != nullptr) return g.mu_cell[cell0 + cell_sz * (uint32_t)cz];
+    if (g.mu_cell != nullptr) return g.mu_cell[mu_index(cz)];
     return g.mu;
   }
   // node (x, y, z) of cell layer cz, velocity component c
-  __device__ BOff u_at(int c, int cz, int x, int y, int z) const {
+  __host__ __device__ BOff u_at(int c, int cz, int x, int y, int z) const {
     return BOff{(uint32_t)c * g.nv_bytes + base_u + suz * (uint32_t)(K * cz + z) + suy * (uint32_t)y,
                 ST * (uint32_t)x};
   }
-  __device__ BOff p_at(int cz, int x, int y, int z) const {
+  __host__ __device__ BOff p_at(int cz, int x, int y, int z) const {
     return BOff{base_p + spz * (uint32_t)((K - 1) * cz + z) + spy * (uint32_t)y, ST * (uint32_t)x};
   }
   // Dirichlet test of local velocity node (x, y, z) of layer cz (bitwise
   // forms: no short-circuit branches on lane-varying flags)
-  __device__ bool vbc(int cz, int x, int y, int z) const {
+  __host__ __device__ bool vbc(int cz, int x, int y, int z) const {
     return ((x == 0) & bxl) | ((x == K) & bxh) | ((y == 0) & byl) | ((y == K) & byh) |
            ((z == 0) & (cz == 0)) | ((z == K) & (cz == g.n[2] - 1));
   }
@@ -153,6 +154,51 @@ struct Sweep {
   bool col_owner;   // column owned by the tile
   bool last_x, last_y;
 };
+
+// Launch shape of the column sweep (host): 8 x 8 column tiles owning 7 x 7
+// columns, NF output fields, the z extent cut into chunks of >= 2 cells so
+// that the launch has about `waves` waves when the level is large enough.
+// Sets g.tiles and returns the number of blocks (one wave each).
+template <typename T>
+inline int sweep3d_chunks(Geo3<T> &g, int NF, int waves) {
+  g.tiles[0] = (g.n[0] + 6) / 7;
+  g.tiles[1] = (g.n[1] + 6) / 7;
+  const int cols = g.tiles[0] * g.tiles[1] * NF;
+  int nzc = (waves + cols - 1) / cols;
+  const int zmax = (g.n[2] + 1) / 2;
+  nzc = nzc < 1 ? 1 : (nzc > zmax ? zmax : nzc);
+  const int zlen = (g.n[2] + nzc - 1) / nzc;
+  g.tiles[2] = (g.n[2] + zlen - 1) / zlen;
+  return cols * g.tiles[2];
+}
+
+// Block b (after the XCD map) and lane -> output field, z chunk, lane cell
+// column (cx, cy) of the sweep; false for an empty chunk (the whole wave
+// returns).  Blocks run (field, x tile, z chunk, y tile), fastest first, so
+// the fields of one tile and chunk run on the same XCD.
+template <int TX, int TY, typename T>
+__host__ __device__ inline bool sweep3d_decode(const Geo3<T> &g, int NF, int b, int lane, int &field, Sweep &s,
+                                               int &cx, int &cy) {
+  field = b % NF;
+  int rest = b / NF;
+  const int tx = rest % g.tiles[0];
+  rest /= g.tiles[0];
+  const int zc = rest % g.tiles[2];
+  const int ty = rest / g.tiles[2];
+  const int zlen = (g.n[2] + g.tiles[2] - 1) / g.tiles[2];
+  s.z_lo = zc * zlen;
+  s.z_hi = s.z_lo + zlen < g.n[2] ? s.z_lo + zlen : g.n[2];
+  if (s.z_lo >= s.z_hi) return false;
+  s.z_start = s.z_lo > 0 ? s.z_lo - 1 : 0;
+  s.lcx = lane % TX;
+  s.lcy = lane / TX;
+  cx = tx * (TX - 1) - 1 + s.lcx;
+  cy = ty * (TY - 1) - 1 + s.lcy;
+  s.col_owner = cx >= 0 && cx < g.n[0] && cy >= 0 && cy < g.n[1] && s.lcx > 0 && s.lcy > 0;
+  s.last_x = cx == g.n[0] - 1;
+  s.last_y = cy == g.n[1] - 1;
+  return true;
+}
 
 // Cell matrices of one velocity component on one box cell:
 //   y = (A u)_COMP (BLK_A) or (M u)_COMP (BLK_MASS), plus (B^T p)_COMP (BLK_BT).
@@ -459,6 +505,39 @@ struct Block3D {
   bool last_x, last_y, last_z;
 };
 
+// Launch shape of the cell-block kernels (host): blocks of 4 x 4 x 4 cells
+// owning 3 x 3 x 3, NF output fields; sets g.tiles, returns the block count.
+template <typename T>
+inline int block3d_tiles(Geo3<T> &g, int NF) {
+  for (int a = 0; a < 3; ++a) g.tiles[a] = (g.n[a] + 2) / 3;
+  return g.tiles[0] * g.tiles[1] * g.tiles[2] * NF;
+}
+
+// Block b (after the XCD map) and lane (0..63) -> output field, the lane's
+// cell (s, clamped layer s.cz) and its cell column (cx, cy).
+template <typename T>
+__host__ __device__ inline void block3d_decode(const Geo3<T> &g, int NF, int b, int lane, int &field, Block3D &s,
+                                               int &cx, int &cy) {
+  field = b % NF;
+  int rest = b / NF;
+  const int tx = rest % g.tiles[0];
+  rest /= g.tiles[0];
+  const int ty = rest % g.tiles[1];
+  const int tz = rest / g.tiles[1];
+  s.lx = lane % 4;
+  s.ly = (lane / 4) % 4;
+  s.lz = lane / 16;
+  cx = tx * 3 - 1 + s.lx;
+  cy = ty * 3 - 1 + s.ly;
+  const int cz = tz * 3 - 1 + s.lz;
+  s.cz = cz < 0 ? 0 : (cz >= g.n[2] ? g.n[2] - 1 : cz);
+  s.active = cx >= 0 && cx < g.n[0] && cy >= 0 && cy < g.n[1] && cz >= 0 && cz < g.n[2];
+  s.owner = s.active && s.lx > 0 && s.ly > 0 && s.lz > 0;
+  s.last_x = cx == g.n[0] - 1;
+  s.last_y = cy == g.n[1] - 1;
+  s.last_z = cz == g.n[2] - 1;
+}
+
 template <int K, typename T, int BLK, class Op, int COMP>
 __device__ __forceinline__ void block_vel(const Geo3<T> &g, const Op &op, const Column3D<K, T> &col,
                                           const Block3D &s) {
@@ -653,24 +732,10 @@ block3d_kernel(const Geo3<T> g, const Op op) {
   constexpr bool OUT_P = (BLK & (BLK_B | BLK_C)) != 0;
   constexpr int NFIELD = (OUT_U ? 3 : 0) + (OUT_P ? 1 : 0);
   const int b = xcd_contiguous_tile(blockIdx.x, gridDim.x);
-  const int field = b % NFIELD;
-  int rest = b / NFIELD;
-  const int tx = rest % g.tiles[0];
-  rest /= g.tiles[0];
-  const int ty = rest % g.tiles[1];
-  const int tz = rest / g.tiles[1];
+  int field, cx, cy;
   Block3D s;
-  s.lx = threadIdx.x % 4;
-  s.ly = (threadIdx.x / 4) % 4;
-  s.lz = threadIdx.x / 16;
-  const Column3D<K, T> col(g, tx * 3 - 1 + s.lx, ty * 3 - 1 + s.ly);
-  const int cz = tz * 3 - 1 + s.lz;
-  s.cz = cz < 0 ? 0 : (cz >= g.n[2] ? g.n[2] - 1 : cz);
-  s.active = col.active && cz >= 0 && cz < g.n[2];
-  s.owner = s.active && s.lx > 0 && s.ly > 0 && s.lz > 0;
-  s.last_x = col.bxh;
-  s.last_y = col.byh;
-  s.last_z = cz == g.n[2] - 1;
+  block3d_decode(g, NFIELD, b, (int)threadIdx.x, field, s, cx, cy);
+  const Column3D<K, T> col(g, cx, cy);
   if constexpr (OUT_U) {
     switch (field) {
       case 0: block_vel<K, T, BLK, Op, 0>(g, op, col, s); return;
@@ -960,31 +1025,17 @@ __device__ __forceinline__ void block_pres_planes(const Geo3<T> &g, const Op &op
 template <int K, typename T, int BLK, class Op>
 __global__ void __launch_bounds__(64 * (K + 1))
 block3d_plane_kernel(const Geo3<T> g, const Op op) {
+  static_assert(K == 2, "the plane switches below cover the K + 1 = 3 velocity planes of Q2");
   constexpr bool OUT_U = (BLK & (BLK_A | BLK_MASS | BLK_BT)) != 0;
   constexpr bool OUT_P = (BLK & (BLK_B | BLK_C)) != 0;
   constexpr int NFIELD = (OUT_U ? 3 : 0) + (OUT_P ? 1 : 0);
   __shared__ T lds[64][K + 1][K + 1];
   const int b = xcd_contiguous_tile(blockIdx.x, gridDim.x);
-  const int field = b % NFIELD;
-  int rest = b / NFIELD;
-  const int tx = rest % g.tiles[0];
-  rest /= g.tiles[0];
-  const int ty = rest % g.tiles[1];
-  const int tz = rest / g.tiles[1];
   const int o = __builtin_amdgcn_readfirstlane((int)threadIdx.x / 64);
-  const int lane = threadIdx.x % 64;
+  int field, cx, cy;
   Block3D s;
-  s.lx = lane % 4;
-  s.ly = (lane / 4) % 4;
-  s.lz = lane / 16;
-  const Column3D<K, T> col(g, tx * 3 - 1 + s.lx, ty * 3 - 1 + s.ly);
-  const int cz = tz * 3 - 1 + s.lz;
-  s.cz = cz < 0 ? 0 : (cz >= g.n[2] ? g.n[2] - 1 : cz);
-  s.active = col.active && cz >= 0 && cz < g.n[2];
-  s.owner = s.active && s.lx > 0 && s.ly > 0 && s.lz > 0;
-  s.last_x = col.bxh;
-  s.last_y = col.byh;
-  s.last_z = cz == g.n[2] - 1;
+  block3d_decode(g, NFIELD, b, (int)threadIdx.x % 64, field, s, cx, cy);
+  const Column3D<K, T> col(g, cx, cy);
   if constexpr (OUT_U) {
     switch (field) {
       case 0: block_vel_planes<K, T, BLK, Op, 0>(g, op, col, s, o, lds); return;
@@ -1016,24 +1067,10 @@ tile3d_kernel(const Geo3<T> g, const Op op) {
   // block -> (field, x tile, z chunk, y tile); the fields of one tile and
   // chunk run on the same XCD and share its L2.
   const int b = xcd_contiguous_tile(blockIdx.x, gridDim.x);
-  const int field = b % NFIELD;
-  int rest = b / NFIELD;
-  const int tx = rest % g.tiles[0];
-  rest /= g.tiles[0];
-  const int zc = rest % g.tiles[2];
-  const int ty = rest / g.tiles[2];
-  const int zlen = (g.n[2] + g.tiles[2] - 1) / g.tiles[2];
+  int field, cx, cy;
   Sweep s;
-  s.z_lo = zc * zlen;
-  s.z_hi = s.z_lo + zlen < g.n[2] ? s.z_lo + zlen : g.n[2];
-  if (s.z_lo >= s.z_hi) return;  // whole wave: empty chunk
-  s.z_start = s.z_lo > 0 ? s.z_lo - 1 : 0;
-  s.lcx = threadIdx.x % TX;
-  s.lcy = threadIdx.x / TX;
-  const Column3D<K, T> col(g, tx * (TX - 1) - 1 + s.lcx, ty * (TY - 1) - 1 + s.lcy);
-  s.col_owner = col.active && s.lcx > 0 && s.lcy > 0;
-  s.last_x = col.bxh;
-  s.last_y = col.byh;
+  if (!sweep3d_decode<TX, TY>(g, NFIELD, b, (int)threadIdx.x, field, s, cx, cy)) return;  // whole wave: empty chunk
+  const Column3D<K, T> col(g, cx, cy);
 
   if constexpr (OUT_U) {
     switch (field) {

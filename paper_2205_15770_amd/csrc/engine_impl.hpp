@@ -317,23 +317,14 @@ class EngineT : public EngineBase {
       g3.sB[2] = (T)(hx * hy);
       if (std::max(g.n[0], std::max(g.n[1], g.n[2])) <= block3d_max_n) {
         // small level: 4 x 4 x 4 cells per wave, one cell per lane, no sweep
-        for (int a = 0; a < 3; ++a) g3.tiles[a] = (g.n[a] + 2) / 3;
-        const unsigned nbb = (unsigned)(g3.tiles[0] * g3.tiles[1] * g3.tiles[2] * NF);
+        const unsigned nbb = (unsigned)block3d_tiles(g3, NF);
         if (std::max(g.n[0], std::max(g.n[1], g.n[2])) <= plane3d_max_n)
           // smallest levels: one wave per output plane of the cells
           hipLaunchKernelGGL((block3d_plane_kernel<K, T, BLK, Op>), dim3(nbb), dim3(64 * (K + 1)), 0, stream, g3, op);
         else
           hipLaunchKernelGGL((block3d_kernel<K, T, BLK, Op>), dim3(nbb), dim3(64), 0, stream, g3, op);
       } else {
-        g3.tiles[0] = (g.n[0] + 6) / 7;
-        g3.tiles[1] = (g.n[1] + 6) / 7;
-        const int cols = g3.tiles[0] * g3.tiles[1] * NF;
-        int nzc = (sweep_waves + cols - 1) / cols;
-        const int zmax = (g.n[2] + 1) / 2;
-        nzc = nzc < 1 ? 1 : (nzc > zmax ? zmax : nzc);
-        const int zlen = (g.n[2] + nzc - 1) / nzc;
-        g3.tiles[2] = (g.n[2] + zlen - 1) / zlen;
-        const unsigned nb3 = (unsigned)(cols * g3.tiles[2]);
+        const unsigned nb3 = (unsigned)sweep3d_chunks(g3, NF, sweep_waves);
         hipLaunchKernelGGL((tile3d_kernel<K, T, BLK, Op, 8, 8>), dim3(nb3), dim3(64), 0, stream, g3, op);
       }
     }
