@@ -264,25 +264,58 @@ smg_status smg_solve(smg_ctx *ctx, double *x, const double *b, double rtol, int 
  * mean reduction of the last three iterations. */
 smg_status smg_solve_stationary(smg_ctx *ctx, double *x, const double *b, double rtol, int maxit, smg_solve_info *info);
 
-/* Batched solves of independent instances (the generalized Stokes problem on
- * meshes of different sizes and with different gamma; Sec. 1 and Sec. 4.3
- * motivate one smoother parameter set for all gamma).  Each context must have
- * its own stream (smg_desc.stream or smg_set_stream); the instances are
- * distributed over `nthreads` host threads, longest first by DoF count, each
- * thread solving its share one after the other with smg_solve, so kernels of
- * different instances overlap on the GPU.  ctxs, x, b, infos: HOST arrays of
- * n entries (x[i], b[i] DEVICE FP64 of instance i; infos may be NULL).
- * Returns the first failing instance's status (all instances are attempted). */
-smg_status smg_batch_solve(smg_ctx *const *ctxs, int n, double *const *x, const double *const *b, double rtol,
-                           int maxit, int nthreads, smg_solve_info *infos);
+/* Batched solves of independent problems (Sec. 1: the generalized Stokes
+ * problem; Sec. 4.3 reports convergence rates robust in gamma, which lets one
+ * smoother parameter set serve every problem of a batch).  A batch groups
+ * existing contexts -- 2D, box cells, gradient form, V-cycle, one device,
+ * one preconditioner precision -- of any sizes and gamma.  Every stage of
+ * the multigrid cycle runs for all problems in one packed launch (a launch
+ * whose table gives each problem's kernel arguments and block range; the
+ * problems whose level takes another kernel variant form another launch of
+ * the same stage), and the whole batched cycle is one HIP graph launch.
+ *
+ * smg_batch_create: records every context's preconditioning cycle, packs it
+ * and captures the graph (allocates the packed tables, the graph and the
+ * reduction buffers; synchronises).  `stream` (hipStream_t or NULL) carries
+ * all batch work.  The contexts must stay alive, unused outside the batch
+ * while a batch call runs, and outlive the batch.  Errors: EINVAL,
+ * EUNSUPPORTED (3D, vertex-given cells, the eps form, W-cycle), EDEVICE. */
+typedef struct smg_batch smg_batch;
+smg_status smg_batch_create(smg_ctx *const *ctxs, int n, void *stream, smg_batch **out);
+smg_status smg_batch_destroy(smg_batch *batch);
 
-/* Autotuner for smg_batch_solve: times `probe_iterations` FGMRES iterations
- * of every instance for each thread count in candidates[0..ncand) and returns
- * the fastest in *best (wall times in times_ms[c] if not NULL); a candidate
- * replaces an earlier one only if it is at least 3 % faster, so timing noise
- * does not decide between near-equal counts.  Overwrites x[i]. */
-smg_status smg_batch_autotune(smg_ctx *const *ctxs, int n, double *const *x, const double *const *b,
-                              const int *candidates, int ncand, int probe_iterations, int *best, double *times_ms);
+/* Solve K_i x_i = b_i for every problem i to ||b_i - K_i x_i|| <= rtol ||b_i||:
+ * FGMRES(m) per problem (m = the smallest fgmres_restart of the batch),
+ * right-preconditioned by one cycle in each context's precision, with the
+ * problems' Krylov iterations in lockstep: each problem keeps its own basis,
+ * coefficients and stopping test (its iterations are those of smg_solve), and
+ * each step -- residual, norms, the copies around the cycle, the batched
+ * cycle, the operator, both Gram-Schmidt passes, the normalisation -- is one
+ * packed launch for all problems, with one copy of all problems'
+ * coefficients to the host per iteration.  x[i], b[i]: HOST arrays of n
+ * DEVICE FP64 pointers (length N_i of the finest level); x[i] is the initial
+ * guess.  infos: HOST array of n (may be NULL).  Pressures are normalised as
+ * by smg_solve.  Returns the first failing problem's status (ENOTCONV,
+ * EBREAKDOWN); every problem is attempted.  Synchronises. */
+smg_status smg_batch_solve(smg_batch *batch, double *const *x, const double *const *b, double rtol, int maxit,
+                           smg_solve_info *infos);
+
+/* z_i = M_i^-1 v_i (one cycle from zero, in each context's precision) for
+ * every problem with one graph launch; v, z: HOST arrays of DEVICE FP64
+ * pointers.  Synchronises. */
+smg_status smg_batch_precondition(smg_batch *batch, const double *const *v, double *const *z);
+
+/* Packed launches per batched cycle and the kernel-variant choice in use. */
+smg_status smg_batch_info(const smg_batch *batch, int *packed_launches_per_cycle, int *variant);
+
+/* Autotuner of the batch's tile shapes: for each built-in choice of which 2D
+ * levels run one wave per output field, the two-stage fused launches (tiles
+ * owning 5 x 5 cells) and the three-stage launches (3 x 3 cells) instead of
+ * one wave per 8 x 8 tile owning 7 x 7 cells, re-packs the batched cycle and
+ * times probe_cycles graph launches of it; keeps the fastest (a later choice
+ * must be 3 % faster) for the batch's contexts.  times_ms: HOST array of at
+ * least 16 entries or NULL; *ncand receives the number of choices. */
+smg_status smg_batch_autotune(smg_batch *batch, int probe_cycles, int *best, double *times_ms, int *ncand);
 
 /* HOST array xyz (Nv x d, node-major) <- physical coordinates of the velocity
  * lattice nodes of level l (for evaluating nodal data such as f). */

@@ -305,67 +305,85 @@ class StokesMG:
 
 
 class StokesBatch:
-    """Independent instances solved together (smg_batch_solve): one StokesMG
-    per instance, each on its own torch stream (default priority), solved by
-    several host threads so that the instances' kernels overlap."""
+    """Independent problems solved together (smg_batch_*): one StokesMG per
+    problem, and a batch handle whose cycle and Krylov steps run every
+    problem in packed launches (the batched cycle is one graph launch)."""
 
-    def __init__(self, problems):
+    def __init__(self, problems, stream=None, solvers=None):
         import torch
-        self.streams = [torch.cuda.Stream() for _ in problems]
-        self.solvers = [StokesMG(stream=st.cuda_stream, **p) for st, p in zip(self.streams, problems)]
+        self._b = ctypes.c_void_p()
+        self._own = solvers is None
+        self.solvers = [StokesMG(**p) for p in problems] if solvers is None else list(solvers)
         self.lib = self.solvers[0].lib
-        self.nthreads = None
+        s = torch.cuda.current_stream().cuda_stream if stream is None else stream
+        n = len(self.solvers)
+        ctxs = (ctypes.c_void_p * n)(*[m._h.value for m in self.solvers])
+        _lib.check(self.lib.smg_batch_create(ctxs, n, ctypes.c_void_p(s), ctypes.byref(self._b)))
+
+    @classmethod
+    def from_solvers(cls, solvers, stream=None):
+        """A batch over existing StokesMG objects (not closed with the batch)."""
+        return cls(None, stream=stream, solvers=solvers)
 
     def __len__(self):
         return len(self.solvers)
 
-    def _arrays(self, xs, bs):
+    def _ptrs(self, ts, name):
+        import torch
+        if len(ts) != len(self.solvers):
+            raise ValueError(f"{name}: one vector per problem")
+        for m, t in zip(self.solvers, ts):
+            m._check(t, m.n_total(m.n_levels - 1), name)
+            if t.dtype != torch.float64:
+                raise TypeError("batch vectors are float64")
+        return (ctypes.c_void_p * len(ts))(*[t.data_ptr() for t in ts])
+
+    def solve(self, xs, bs, rtol=1e-8, maxit=300, raise_on_failure=True):
+        """Solve every problem (smg_batch_solve); returns the per-problem info dicts."""
         n = len(self.solvers)
-        P = ctypes.c_void_p
-        ctxs = (P * n)(*[s._h.value for s in self.solvers])
-        xa = (P * n)(*[x.data_ptr() for x in xs])
-        ba = (P * n)(*[b.data_ptr() for b in bs])
-        return ctxs, xa, ba
-
-    def _check(self, xs, bs):
-        import torch
-        for s, x, b in zip(self.solvers, xs, bs):
-            n = s.n_total(s.n_levels - 1)
-            for t, nm in ((x, "x"), (b, "b")):
-                s._check(t, n, nm)
-                if t.dtype != torch.float64:
-                    raise TypeError("batch solves work on float64 vectors")
-
-    def autotune(self, xs, bs, candidates=(1, 2, 4, 8, 16), probe_iterations=2):
-        """Fastest host-thread count for this batch (smg_batch_autotune);
-        overwrites xs.  Returns (best, {candidate: ms})."""
-        import torch
-        self._check(xs, bs)
-        torch.cuda.synchronize()
-        ctxs, xa, ba = self._arrays(xs, bs)
-        cand = (ctypes.c_int * len(candidates))(*candidates)
-        best = ctypes.c_int()
-        times = (ctypes.c_double * len(candidates))()
-        _lib.check(self.lib.smg_batch_autotune(ctxs, len(self.solvers), xa, ba, cand, len(candidates),
-                                               int(probe_iterations), ctypes.byref(best), times))
-        self.nthreads = best.value
-        return best.value, {c: times[i] for i, c in enumerate(candidates)}
-
-    def solve(self, xs, bs, rtol=1e-8, maxit=300, nthreads=None, raise_on_failure=True):
-        """Solve every instance; returns the per-instance info dicts."""
-        import torch
-        self._check(xs, bs)
-        torch.cuda.synchronize()
-        n = len(self.solvers)
-        nthreads = nthreads or self.nthreads or min(8, n)
+        hist = [np.zeros(maxit + 2) for _ in range(n)]
         infos = (_lib.SmgSolveInfo * n)()
-        ctxs, xa, ba = self._arrays(xs, bs)
-        st = self.lib.smg_batch_solve(ctxs, n, xa, ba, float(rtol), int(maxit), int(nthreads), infos)
+        for i in range(n):
+            infos[i].history = hist[i].ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+            infos[i].history_capacity = len(hist[i])
+        st = self.lib.smg_batch_solve(self._b, self._ptrs(xs, "x"), self._ptrs(bs, "b"), float(rtol), int(maxit), infos)
         if st != _lib.SMG_OK and raise_on_failure:
             _lib.check(st)
-        return [{"iterations": i.iterations, "rel_residual": i.rel_residual, "t_solve_ms": i.t_solve_ms}
-                for i in infos]
+        return [{"iterations": i.iterations, "rel_residual": i.rel_residual, "t_solve_ms": i.t_solve_ms,
+                 "t_setup_ms": i.t_setup_ms, "history": hist[k][:i.history_len].copy()}
+                for k, i in enumerate(infos)]
+
+    def precondition(self, vs, zs=None):
+        """z_i = M_i^-1 v_i for every problem, one graph launch (smg_batch_precondition)."""
+        import torch
+        zs = [torch.empty_like(v) for v in vs] if zs is None else zs
+        _lib.check(self.lib.smg_batch_precondition(self._b, self._ptrs(vs, "v"), self._ptrs(zs, "z")))
+        return zs
+
+    def info(self):
+        """(packed launches per batched cycle, kernel-variant choice)."""
+        nl, var = ctypes.c_int(), ctypes.c_int()
+        _lib.check(self.lib.smg_batch_info(self._b, ctypes.byref(nl), ctypes.byref(var)))
+        return nl.value, var.value
+
+    def autotune(self, probe_cycles=5):
+        """Fastest kernel-variant choice (smg_batch_autotune): (best, [ms per cycle of each choice])."""
+        best, n = ctypes.c_int(), ctypes.c_int()
+        times = (ctypes.c_double * 16)()
+        _lib.check(self.lib.smg_batch_autotune(self._b, int(probe_cycles), ctypes.byref(best), times, ctypes.byref(n)))
+        return best.value, [times[i] for i in range(n.value)]
 
     def close(self):
-        for s in self.solvers:
-            s.close()
+        if getattr(self, "_b", None) is not None and self._b.value:
+            self.lib.smg_batch_destroy(self._b)
+            self._b = ctypes.c_void_p()
+        if getattr(self, "_own", False):
+            for s in self.solvers:
+                s.close()
+            self.solvers = []
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

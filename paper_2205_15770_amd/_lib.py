@@ -22,8 +22,8 @@ STATUS_NAMES = {0: "SMG_OK", -1: "SMG_EINVAL", -2: "SMG_ENOMEM", -3: "SMG_EDEVIC
 EXPORTS = ["smg_desc_default", "smg_create", "smg_destroy", "smg_sizes", "smg_set_stream",
            "smg_vmult", "smg_vmult_noalloc", "smg_residual", "smg_apply_block", "smg_lift_dirichlet", "smg_insert_dirichlet", "smg_get_diagonal", "smg_get_eigs",
            "smg_set_eigs", "smg_chebyshev", "smg_smooth", "smg_restrict", "smg_prolongate_add",
-           "smg_coarse_solve", "smg_vcycle", "smg_solve", "smg_solve_stationary", "smg_batch_solve",
-           "smg_batch_autotune",
+           "smg_coarse_solve", "smg_vcycle", "smg_solve", "smg_solve_stationary", "smg_batch_create",
+           "smg_batch_destroy", "smg_batch_solve", "smg_batch_precondition", "smg_batch_info", "smg_batch_autotune",
            "smg_node_coordinates", "smg_gradient", "smg_pressure_mean_adjoint", "smg_profile", "smg_profile_report",
            "smg_last_error"]
 
@@ -91,10 +91,12 @@ def load(path=LIB_PATH):
         "smg_vcycle": (I, [P, I, I, P, P]),
         "smg_solve": (I, [P, P, P, D, I, ctypes.POINTER(SmgSolveInfo)]),
         "smg_solve_stationary": (I, [P, P, P, D, I, ctypes.POINTER(SmgSolveInfo)]),
-        "smg_batch_solve": (I, [ctypes.POINTER(P), I, ctypes.POINTER(P), ctypes.POINTER(P), D, I, I,
-                                ctypes.POINTER(SmgSolveInfo)]),
-        "smg_batch_autotune": (I, [ctypes.POINTER(P), I, ctypes.POINTER(P), ctypes.POINTER(P),
-                                   ctypes.POINTER(I), I, I, ctypes.POINTER(I), ctypes.POINTER(D)]),
+        "smg_batch_create": (I, [ctypes.POINTER(P), I, P, ctypes.POINTER(P)]),
+        "smg_batch_destroy": (I, [P]),
+        "smg_batch_solve": (I, [P, ctypes.POINTER(P), ctypes.POINTER(P), D, I, ctypes.POINTER(SmgSolveInfo)]),
+        "smg_batch_precondition": (I, [P, ctypes.POINTER(P), ctypes.POINTER(P)]),
+        "smg_batch_info": (I, [P, ctypes.POINTER(I), ctypes.POINTER(I)]),
+        "smg_batch_autotune": (I, [P, I, ctypes.POINTER(I), ctypes.POINTER(D), ctypes.POINTER(I)]),
         "smg_node_coordinates": (I, [P, I, P]),
         "smg_gradient": (I, [P, P, P, P, P]),
         "smg_pressure_mean_adjoint": (I, [P, P]),

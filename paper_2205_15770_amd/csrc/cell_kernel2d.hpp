@@ -346,14 +346,13 @@ template <typename T>
 struct is_residual_op<OpResidual<T>> : std::true_type {};
 
 template <int K, typename T, class Op1, bool LAST>
-__global__ void __launch_bounds__(64)
-wave2d_fused_kernel(const Geo2<T> g, const Op1 op1, const OpChebA<T, true, LAST> op2) {
+__device__ __forceinline__ void wave2d_fused_body(const Geo2<T> &g, const Op1 &op1, const OpChebA<T, true, LAST> &op2,
+                                                  const int bb) {
   constexpr int NV = K + 1, NP = K, TX = 8, OWN = TX - 3;
   constexpr uint32_t ST = sizeof(T);
   constexpr cfe::TabT<K, T> R = cfe::make_tab_t<K, T>();
   constexpr bool RESID = is_residual_op<Op1>::value;
 
-  const int bb = xcd_contiguous_tile(blockIdx.x, gridDim.x);
   const int c = bb % 2, b = bb / 2;
   const int tx = b % g.tiles[0], ty = b / g.tiles[0];
   const int lcx = threadIdx.x % TX, lcy = threadIdx.x / TX;
@@ -539,13 +538,12 @@ struct Fuse3P {
 };
 
 template <int K, typename T, int MODE, bool LAST>
-__global__ void __launch_bounds__(64)
-wave2d_fused3_kernel(const Geo2<T> g, const Fuse3P<T> P, const OpChebA<T, true, LAST> op2) {
+__device__ __forceinline__ void wave2d_fused3_body(const Geo2<T> &g, const Fuse3P<T> &P,
+                                                   const OpChebA<T, true, LAST> &op2, const int bb) {
   constexpr int NV = K + 1, NP = K, TX = 8, OWN = TX - 5;
   constexpr uint32_t ST = sizeof(T);
   constexpr cfe::TabT<K, T> R = cfe::make_tab_t<K, T>();
 
-  const int bb = xcd_contiguous_tile(blockIdx.x, gridDim.x);
   const int c = bb % 2, b = bb / 2;
   const int tx = b % g.tiles[0], ty = b / g.tiles[0];
   const int lcx = threadIdx.x % TX, lcy = threadIdx.x / TX;
@@ -756,5 +754,67 @@ wave2d_fused3_kernel(const Geo2<T> g, const Fuse3P<T> P, const OpChebA<T, true, 
       }
   }
 }
+
+template <int K, typename T, class Op1, bool LAST>
+__global__ void __launch_bounds__(64)
+wave2d_fused_kernel(const Geo2<T> g, const Op1 op1, const OpChebA<T, true, LAST> op2) {
+  wave2d_fused_body<K, T, Op1, LAST>(g, op1, op2, xcd_contiguous_tile(blockIdx.x, gridDim.x));
+}
+
+template <int K, typename T, int MODE, bool LAST>
+__global__ void __launch_bounds__(64)
+wave2d_fused3_kernel(const Geo2<T> g, const Fuse3P<T> P, const OpChebA<T, true, LAST> op2) {
+  wave2d_fused3_body<K, T, MODE, LAST>(g, P, op2, xcd_contiguous_tile(blockIdx.x, gridDim.x));
+}
+
+// ---------------------------------------------------------------------------
+// The 2D launches above as functors (packed launches over many problems,
+// packed.hpp); block b of nb takes tile xcd_contiguous_tile(b, nb) as in a
+// launch of its own.
+// ---------------------------------------------------------------------------
+template <int K, typename T, int BLK, class Op>
+struct LTile2 {
+  static constexpr int THREADS = 64;
+  Geo2<T> g;
+  Op op;
+  __device__ void run(int b, int nb) const { wave2d_tile<K, T, BLK, Op, -1>(g, op, xcd_contiguous_tile(b, nb)); }
+};
+
+template <int K, typename T, int BLK, class Op>
+struct LTile2Split {
+  static constexpr int THREADS = 64;
+  Geo2<T> g;
+  Op op;
+  __device__ void run(int b, int nb) const {
+    constexpr bool OUT_U = (BLK & (BLK_A | BLK_MASS | BLK_BT)) != 0;
+    constexpr bool OUT_P = (BLK & (BLK_B | BLK_C)) != 0;
+    constexpr int NF = (OUT_U ? 2 : 0) + (OUT_P ? 1 : 0);
+    const int bb = xcd_contiguous_tile(b, nb);
+    const int f = bb % NF, t = bb / NF;
+    if constexpr (OUT_U) {
+      if (f == 0) { wave2d_tile<K, T, BLK, Op, 0>(g, op, t); return; }
+      if (f == 1) { wave2d_tile<K, T, BLK, Op, 1>(g, op, t); return; }
+    }
+    if constexpr (OUT_P) wave2d_tile<K, T, BLK, Op, 2>(g, op, t);
+  }
+};
+
+template <int K, typename T, class Op1, bool LAST>
+struct LFused2 {
+  static constexpr int THREADS = 64;
+  Geo2<T> g;
+  Op1 op1;
+  OpChebA<T, true, LAST> op2;
+  __device__ void run(int b, int nb) const { wave2d_fused_body<K, T, Op1, LAST>(g, op1, op2, xcd_contiguous_tile(b, nb)); }
+};
+
+template <int K, typename T, int MODE, bool LAST>
+struct LFused3 {
+  static constexpr int THREADS = 64;
+  Geo2<T> g;
+  Fuse3P<T> P;
+  OpChebA<T, true, LAST> op2;
+  __device__ void run(int b, int nb) const { wave2d_fused3_body<K, T, MODE, LAST>(g, P, op2, xcd_contiguous_tile(b, nb)); }
+};
 
 }  // namespace smg

@@ -54,6 +54,32 @@ struct LevelInfo {
   Work<float> w32;
 };
 
+// A kernel launch recorded instead of run: the launch functor's bytes (see
+// packed.hpp), its block count and the packed kernel that runs many of them.
+struct LaunchRec {
+  int tag = 0;                  // stage of the multigrid cycle (merge key)
+  const void *kernel = nullptr; // k_packed<L>
+  unsigned nblocks = 0, threads = 0;
+  size_t align = 8;
+  std::vector<unsigned char> bytes;
+};
+struct Recorder {
+  int tag = 0;
+  std::vector<LaunchRec> recs;
+};
+
+// Internal buffers of a solver that a batched driver works on.
+struct BatchView {
+  int64_t N = 0;              // finest-level vector length
+  int restart = 0;            // FGMRES basis size
+  double *V = nullptr, *Z = nullptr;   // Krylov bases (restart + 1, restart vectors of N)
+  double *b64 = nullptr, *x64 = nullptr;
+  float *b32 = nullptr, *x32 = nullptr;
+  double *partial = nullptr;  // RB x (restart + 1) reduction partials
+  int precision = 0;
+  bool c_zero = true;         // C = 0: solutions are normalised to pressure mean zero
+};
+
 class EngineBase {
  public:
   virtual ~EngineBase() {}
@@ -87,6 +113,23 @@ class EngineBase {
   virtual void vmult_scratch(int l, int dt, const void *x, void *y, void *scratch) = 0;
   virtual void invalidate_graphs() {}
   bool use_graphs = true;
+
+  // Batched execution: with `rec` set, the launch sites of the 2D box-cell
+  // cycle and operator append functors to it instead of launching.
+  Recorder *rec = nullptr;
+  void set_tag(int t) {
+    if (rec) rec->tag = t;
+  }
+  // the preconditioning cycle from zero on the internal buffers (b32/x32 or
+  // b64/x64 by dt), the finest-level y = K x and r = b - K x (FP64)
+  virtual void record_cycle(int dt, Recorder &r) = 0;
+  virtual void record_vmult(Recorder &r, const double *x, double *y) = 0;
+  virtual void record_residual(Recorder &r, const double *x, const double *b, double *res) = 0;
+  virtual BatchView batch_view() = 0;
+  // the normalisation smg_solve applies to its result (pressure mean zero for C = 0)
+  virtual void normalize_solution(double *x) = 0;
+  // kernel-variant limits of the 2D levels (cells per direction; negative: keep)
+  virtual void set_variants(int split2d, int fuse2d, int fuse3_2d) = 0;
 
   // Optional kernel timing: HIP events recorded around each operator-kernel
   // launch on the launch stream, aggregated per kernel key.

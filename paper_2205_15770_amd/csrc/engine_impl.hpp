@@ -7,6 +7,7 @@
 #include <cstdlib>
 
 #include "cell_kernel2d.hpp"
+#include "packed.hpp"
 #include "gen_kernel.hpp"
 #include "cell_kernel3d.hpp"
 #include "engine.hpp"
@@ -270,6 +271,7 @@ class EngineT : public EngineBase {
       eb = next_event();
       SMG_HIP(hipEventRecord(ea, stream));
     }
+    if (rec && (gen_op || DIM != 2)) throw Error{SMG_EUNSUPPORTED, "batched launches: 2D box cells only"};
     if (gen_op) {
       gen_tile<T, BLK, Op>(g, op);
     } else if constexpr (DIM == 2) {
@@ -282,9 +284,11 @@ class EngineT : public EngineBase {
         // one wave per (tile, output field): fewer instructions per wave.
         // Blocks with only velocity outputs read nothing twice this way; the
         // others read p (and u) once per field, which pays on small levels.
-        hipLaunchKernelGGL((wave2d_split_kernel<K, T, BLK, Op>), dim3(nb2 * NF2), dim3(64), 0, stream, g2, op);
+        if (rec) rec_add(LTile2Split<K, T, BLK, Op>{g2, op}, nb2 * NF2);
+        else hipLaunchKernelGGL((wave2d_split_kernel<K, T, BLK, Op>), dim3(nb2 * NF2), dim3(64), 0, stream, g2, op);
       } else {
-        hipLaunchKernelGGL((wave2d_kernel<K, T, BLK, Op>), dim3(nb2), dim3(64), 0, stream, g2, op);
+        if (rec) rec_add(LTile2<K, T, BLK, Op>{g2, op}, nb2);
+        else hipLaunchKernelGGL((wave2d_kernel<K, T, BLK, Op>), dim3(nb2), dim3(64), 0, stream, g2, op);
       }
     } else if constexpr (K != 2) {
       // Q3-Q2 in 3D always runs on the vertex-given cell kernel (gen_op)
@@ -566,8 +570,24 @@ class EngineT : public EngineBase {
 
   template <typename T>
   void vset(T *y, T v, int64_t n) {
-    hipLaunchKernelGGL((k_set<T>), dim3(grid_for(n)), dim3(VB), 0, stream, y, v, (i64)n);
+    if (rec) rec_add(LSet<T>{y, v, (i64)n}, grid_for(n));
+    else hipLaunchKernelGGL((k_set<T>), dim3(grid_for(n)), dim3(VB), 0, stream, y, v, (i64)n);
     check_launch();
+  }
+
+  // append a launch functor to the recorder (batched execution)
+  template <class L>
+  void rec_add(const L &l, unsigned nb) {
+    static_assert(std::is_trivially_copyable<L>::value, "launch functors are copied as bytes");
+    LaunchRec r;
+    r.tag = rec->tag;
+    r.kernel = (const void *)&k_packed<L>;
+    r.nblocks = nb;
+    r.threads = L::THREADS;
+    r.align = alignof(L);
+    r.bytes.resize(sizeof(L));
+    std::memcpy(r.bytes.data(), &l, sizeof(L));
+    rec->recs.push_back(std::move(r));
   }
 
   // ---------------------------------------------------------------- blocks
@@ -681,7 +701,8 @@ class EngineT : public EngineBase {
     const double beta = lv[l].beta_A, theta = 0.75 * beta, delta = 0.25 * beta, s1 = theta / delta;
     const int k = desc.cheb_deg_A;
     if (k == 0) {
-      hipLaunchKernelGGL((k_jacobi<T>), dim3(grid_for(nu)), dim3(VB), 0, stream, out, base, (T)(s / theta), W.dinvA, r, (i64)nu);
+      if (rec) rec_add(LJacobi<T>{out, base, (T)(s / theta), W.dinvA, r, (i64)nu}, grid_for(nu));
+      else hipLaunchKernelGGL((k_jacobi<T>), dim3(grid_for(nu)), dim3(VB), 0, stream, out, base, (T)(s / theta), W.dinvA, r, (i64)nu);
       check_launch();
       return;
     }
@@ -751,7 +772,10 @@ class EngineT : public EngineBase {
         eb = next_event();
         SMG_HIP(hipEventRecord(ea, stream));
       }
-      if (k == 1)
+      if (rec) {
+        if (k == 1) rec_add(LFused2<K, T, Op1, true>{g2, op1, o}, nb);
+        else rec_add(LFused2<K, T, Op1, false>{g2, op1, cast_op<OpChebA<T, true, false>>(o)}, nb);
+      } else if (k == 1)
         hipLaunchKernelGGL((wave2d_fused_kernel<K, T, Op1, true>), dim3(nb), dim3(64), 0, stream, g2, op1, o);
       else
         hipLaunchKernelGGL((wave2d_fused_kernel<K, T, Op1, false>), dim3(nb), dim3(64), 0, stream, g2, op1,
@@ -789,7 +813,11 @@ class EngineT : public EngineBase {
     const double beta = lv[l].beta_S, theta = 0.75 * beta, delta = 0.25 * beta, s1 = theta / delta;
     const int k = desc.cheb_deg_S;
     if (k == 0) {
-      if (p)
+      if (rec && p)
+        rec_add(LJacobiUpdate<T>{p, dp, (T)(tau / theta), W.dinvS, rp, (i64)np}, grid_for(np));
+      else if (rec)
+        rec_add(LJacobi<T>{dp, (const T *)nullptr, (T)(tau / theta), W.dinvS, rp, (i64)np}, grid_for(np));
+      else if (p)
         hipLaunchKernelGGL((k_jacobi_update<T>), dim3(grid_for(np)), dim3(VB), 0, stream, p, dp, (T)(tau / theta), W.dinvS, rp, (i64)np);
       else
         hipLaunchKernelGGL((k_jacobi<T>), dim3(grid_for(np)), dim3(VB), 0, stream, dp, (const T *)nullptr, (T)(tau / theta), W.dinvS, rp, (i64)np);
@@ -957,7 +985,12 @@ class EngineT : public EngineBase {
           eb = next_event();
           SMG_HIP(hipEventRecord(ea, stream));
         }
-        if (stage == 0) {
+        if (rec) {
+          if (stage == 0 && kA == 1) rec_add(LFused3<K, T, F3_DIVRES, true>{g2, P, o}, nb);
+          else if (stage == 0) rec_add(LFused3<K, T, F3_DIVRES, false>{g2, P, cast_op<OpChebA<T, true, false>>(o)}, nb);
+          else if (kA == 1) rec_add(LFused3<K, T, F3_CHEBS, true>{g2, P, o}, nb);
+          else rec_add(LFused3<K, T, F3_CHEBS, false>{g2, P, cast_op<OpChebA<T, true, false>>(o)}, nb);
+        } else if (stage == 0) {
           if (kA == 1)
             hipLaunchKernelGGL((wave2d_fused3_kernel<K, T, F3_DIVRES, true>), dim3(nb), dim3(64), 0, stream, g2, P, o);
           else
@@ -1019,7 +1052,8 @@ class EngineT : public EngineBase {
     const int nzv = (DIM == 3 ? gv.fdim[2] : 1) * DIM, nzp = DIM == 3 ? gp.fdim[2] : 1;
     const int64_t nxy = std::max((int64_t)gv.fdim[0] * gv.fdim[1], (int64_t)gp.fdim[0] * gp.fdim[1]);
     const dim3 grid((unsigned)((nxy + 255) / 256), (unsigned)(nzv + nzp));
-    hipLaunchKernelGGL((k_prolong<T, DIM, K>), grid, dim3(256), 0, stream, wc, xf, gv, gp, nzv);
+    if (rec) rec_add(LProlong<T, DIM, K>{wc, xf, gv, gp, nzv, (int)grid.x}, grid.x * grid.y);
+    else hipLaunchKernelGGL((k_prolong<T, DIM, K>), grid, dim3(256), 0, stream, wc, xf, gv, gp, nzv);
     check_launch();
   }
 
@@ -1031,7 +1065,8 @@ class EngineT : public EngineBase {
     const int nzv = (DIM == 3 ? gv.cdim[2] : 1) * DIM, nzp = DIM == 3 ? gp.cdim[2] : 1;
     const int nx = std::max(gv.cdim[0], gp.cdim[0]), ny = std::max(gv.cdim[1], gp.cdim[1]);
     const dim3 grid((unsigned)((nx + CX - 1) / CX), (unsigned)ny, (unsigned)(nzv + nzp));
-    hipLaunchKernelGGL((k_restrict<T, DIM, K, CX>), grid, dim3(256), 0, stream, rf, rc, zc, gv, gp, nzv);
+    if (rec) rec_add(LRestrict<T, DIM, K, CX>{rf, rc, zc, gv, gp, nzv, (int)grid.x, (int)grid.y}, grid.x * grid.y * grid.z);
+    else hipLaunchKernelGGL((k_restrict<T, DIM, K, CX>), grid, dim3(256), 0, stream, rf, rc, zc, gv, gp, nzv);
     check_launch();
   }
 
@@ -1039,7 +1074,8 @@ class EngineT : public EngineBase {
   template <typename T>
   void coarse_t(const T *b0, T *x0) {
     const unsigned nb = (unsigned)((n0 + (VB / 64) - 1) / (VB / 64));
-    hipLaunchKernelGGL((k_coarse_gemv<T>), dim3(nb), dim3(VB), 0, stream, Kinv, (i64)coarse_ld, n0, b0, x0);
+    if (rec) rec_add(LCoarseGemv<T>{Kinv, (i64)coarse_ld, n0, b0, x0}, nb);
+    else hipLaunchKernelGGL((k_coarse_gemv<T>), dim3(nb), dim3(VB), 0, stream, Kinv, (i64)coarse_ld, n0, b0, x0);
     check_launch();
   }
 
@@ -1047,18 +1083,94 @@ class EngineT : public EngineBase {
   // Algorithm 1 with cycle index desc.cycle_index; level 0 is the direct solve.
   template <typename T>
   void cycle_t(int l, T *x, const T *b, bool zero_init) {
+    // stage tags for batched execution (depth d below the finest level): on
+    // the way down 4d (pre-smoothing), 4d + 1 (residual), 4d + 2
+    // (restriction), 4d + 3 the coarse solve; on the way up ASCENT + 2(64 -
+    // d) (prolongation), + 1 (post-smoothing) -- increasing along the V-cycle
+    // of every hierarchy, whatever its depth
+    constexpr int ASCENT = 1000;
+    const int d = L - l;
     if (l == 0) {
+      set_tag(4 * d + 3);
       coarse_t<T>(b, x);
       return;
     }
     Work<T> &W = work<T>(l);
     Work<T> &C = work<T>(l - 1);
+    set_tag(4 * d);
     smooth_t<T>(l, x, b, desc.smooth_steps, zero_init);
+    set_tag(4 * d + 1);
     residual_t<T>(l, x, b, W.r);
+    set_tag(4 * d + 2);
     restrict_t<T>(l, W.r, C.b, C.x);   // also C.x = 0
     for (int j = 0; j < desc.cycle_index; ++j) cycle_t<T>(l - 1, C.x, C.b, j == 0);
+    set_tag(ASCENT + 2 * (64 - d));
     prolongate_t<T>(l, C.x, x);
+    set_tag(ASCENT + 2 * (64 - d) + 1);
     smooth_t<T>(l, x, b, desc.smooth_steps, false);
+  }
+
+  // ------------------------------------------------- batched execution
+  void record_cycle(int dt, Recorder &r) override {
+    if (desc.cycle_index != 1) throw Error{SMG_EUNSUPPORTED, "batched cycle: V-cycle only"};
+    if (profiling) throw Error{SMG_EINVAL, "batched cycle: kernel timing is on"};
+    rec = &r;
+    try {
+      r.tag = -1;
+      if (dt == SMG_F32) {
+        vset<float>(x32, 0.0f, lv[L].N);
+        cycle_t<float>(L, x32, b32, true);
+      } else {
+        vset<double>(x64, 0.0, lv[L].N);
+        cycle_t<double>(L, x64, b64, true);
+      }
+    } catch (...) {
+      rec = nullptr;
+      throw;
+    }
+    rec = nullptr;
+  }
+  void record_vmult(Recorder &r, const double *x, double *y) override {
+    rec = &r;
+    try {
+      vmult_t<double>(L, x, y);
+    } catch (...) {
+      rec = nullptr;
+      throw;
+    }
+    rec = nullptr;
+  }
+  void record_residual(Recorder &r, const double *x, const double *b, double *res) override {
+    rec = &r;
+    try {
+      residual_t<double>(L, x, b, res);
+    } catch (...) {
+      rec = nullptr;
+      throw;
+    }
+    rec = nullptr;
+  }
+  BatchView batch_view() override {
+    BatchView v;
+    v.N = lv[L].N;
+    v.restart = restart;
+    v.V = V;
+    v.Z = Z;
+    v.b64 = b64;
+    v.x64 = x64;
+    v.b32 = b32;
+    v.x32 = x32;
+    v.partial = partial;
+    v.precision = desc.precision;
+    v.c_zero = !has_c();
+    return v;
+  }
+  void normalize_solution(double *x) override { remove_pressure_mean(x); }
+  void set_variants(int split2d, int fuse2d, int fuse3_2d) override {
+    if (split2d >= 0) split2d_max_n = split2d;
+    if (fuse2d >= 0) fuse2d_max_n = fuse2d;
+    if (fuse3_2d >= 0) fuse3_2d_max_n = fuse3_2d;
+    invalidate_graphs();
   }
 
   // ---------------------------------------------------------- reductions

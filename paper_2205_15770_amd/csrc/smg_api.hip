@@ -7,9 +7,9 @@
 #include <chrono>
 #include <map>
 #include <mutex>
-#include <thread>
 #include <vector>
 
+#include "batch.hpp"
 #include "engine.hpp"
 
 std::string smg::EngineBase::profile_report() {
@@ -454,88 +454,161 @@ smg_status smg_node_coordinates(const smg_ctx *ctx, int level, double *xyz) {
   SMG_TRY(ctx->eng->node_coordinates(level, xyz));
 }
 
+struct smg_batch {
+  smg::BatchDriver drv;
+  std::vector<smg_ctx *> ctxs;
+  int device = 0;
+  int variant = 0;
+};
+
 namespace {
-// Instances -> host threads, longest-processing-time first by finest-level DoFs.
-std::vector<std::vector<int>> lpt_groups(smg_ctx *const *ctxs, int n, int nthreads) {
-  std::vector<int> order(n);
-  for (int i = 0; i < n; ++i) order[i] = i;
-  auto size = [&](int i) { return ctxs[i]->eng->lv.back().N; };
-  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return size(a) > size(b); });
-  std::vector<std::vector<int>> groups(nthreads);
-  std::vector<int64_t> load(nthreads, 0);
-  for (int i : order) {
-    const int t = (int)(std::min_element(load.begin(), load.end()) - load.begin());
-    groups[t].push_back(i);
-    load[t] += size(i);
-  }
-  return groups;
+// Kernel-variant choices the batch autotuner times: the largest 2D level
+// (cells per direction) that runs one wave per output field, the two-stage
+// fused launches (tiles owning 5 x 5 cells) and the three-stage launches
+// (3 x 3); the others run one wave per 8 x 8 tile owning 7 x 7 cells.
+constexpr int kBatchVariants[][3] = {
+    {256, 256, 128}, {0, 0, 0}, {256, 0, 0}, {256, 256, 0}, {512, 512, 128}, {256, 256, 256}, {512, 256, 64}};
+constexpr int kNumBatchVariants = (int)(sizeof(kBatchVariants) / sizeof(kBatchVariants[0]));
+
+smg_status check_batch(const smg_batch *b) {
+  if (!b) return fail(SMG_EINVAL, "null batch");
+  return SMG_OK;
 }
 }  // namespace
 
-smg_status smg_batch_solve(smg_ctx *const *ctxs, int n, double *const *x, const double *const *b, double rtol,
-                           int maxit, int nthreads, smg_solve_info *infos) {
-  if (!ctxs || !x || !b || n < 1) return fail(SMG_EINVAL, "need n >= 1 contexts and vectors");
+smg_status smg_batch_create(smg_ctx *const *ctxs, int n, void *stream, smg_batch **out) {
+  if (!out) return fail(SMG_EINVAL, "null output pointer");
+  *out = nullptr;
+  if (!ctxs || n < 1) return fail(SMG_EINVAL, "need n >= 1 contexts");
   for (int i = 0; i < n; ++i) {
     smg_status s = check_ctx(ctxs[i]);
-    if (s == SMG_OK) s = check_ptrs({x[i], b[i]});
     if (s != SMG_OK) return s;
     for (int j = 0; j < i; ++j)
       if (ctxs[j] == ctxs[i]) return fail(SMG_EINVAL, "a context appears twice in the batch");
+    const smg_desc &d = ctxs[i]->eng->desc;
+    if (d.dim != 2) return fail(SMG_EUNSUPPORTED, "batched solves: 2D problems only");
+    if (d.cycle_index != 1) return fail(SMG_EUNSUPPORTED, "batched solves: V-cycle only");
+    if (d.form != SMG_FORM_GRAD) return fail(SMG_EUNSUPPORTED, "batched solves: gradient form only");
+    if (ctxs[i]->device != ctxs[0]->device) return fail(SMG_EINVAL, "batched contexts must share one device");
   }
-  if (!(rtol > 0) || maxit < 0) return fail(SMG_EINVAL, "need rtol > 0 and maxit >= 0");
-  nthreads = std::max(1, std::min(nthreads, n));
-  const std::vector<std::vector<int>> groups = lpt_groups(ctxs, n, nthreads);
-  std::vector<smg_status> st(n, SMG_OK);
-  std::vector<std::string> err(n);
-  auto work = [&](int t) {
-    for (int i : groups[t]) {
-      try {
-        if (hipSetDevice(ctxs[i]->device) != hipSuccess) {
-          st[i] = SMG_EDEVICE;
-          err[i] = "hipSetDevice failed";
-          continue;
-        }
-        st[i] = smg_solve(ctxs[i], x[i], b[i], rtol, maxit, infos ? &infos[i] : nullptr);
-        if (st[i] != SMG_OK) err[i] = g_last_error;
-      } catch (const std::exception &e) {
-        st[i] = SMG_EDEVICE;
-        err[i] = std::string("exception: ") + e.what();
-      }
-    }
-  };
-  std::vector<std::thread> th;
-  for (int t = 1; t < nthreads; ++t) th.emplace_back(work, t);
-  work(0);
-  for (auto &h : th) h.join();
-  for (int i = 0; i < n; ++i)
-    if (st[i] != SMG_OK) return fail(st[i], "instance " + std::to_string(i) + ": " + err[i]);
+  smg_batch *b = new smg_batch();
+  try {
+    b->device = ctxs[0]->device;
+    b->ctxs.assign(ctxs, ctxs + n);
+    std::vector<smg::EngineBase *> e;
+    for (int i = 0; i < n; ++i) e.push_back(ctxs[i]->eng);
+    b->drv.stream = (hipStream_t)stream;
+    b->drv.init(e);
+    b->drv.build_cycle();
+  } catch (const smg::Error &e) {
+    delete b;
+    return fail(e.code, e.msg);
+  } catch (const std::exception &e) {
+    delete b;
+    return fail(SMG_EDEVICE, std::string("exception: ") + e.what());
+  }
+  *out = b;
   g_last_error.clear();
   return SMG_OK;
 }
 
-smg_status smg_batch_autotune(smg_ctx *const *ctxs, int n, double *const *x, const double *const *b,
-                              const int *candidates, int ncand, int probe_iterations, int *best, double *times_ms) {
-  if (!candidates || ncand < 1 || !best || probe_iterations < 1) return fail(SMG_EINVAL, "bad autotune arguments");
-  double tbest = 1e300;
-  for (int c = 0; c < ncand; ++c) {
-    if (candidates[c] < 1) return fail(SMG_EINVAL, "thread counts must be >= 1");
-    for (int i = 0; i < n; ++i) {
-      smg_status s = check_ctx(ctxs ? ctxs[i] : nullptr);
-      if (s != SMG_OK) return s;
-    }
-    const auto t0 = std::chrono::steady_clock::now();
-    // a fixed amount of work: probe_iterations FGMRES iterations per instance
-    smg_status s = smg_batch_solve(ctxs, n, x, b, 1e-300, probe_iterations, candidates[c], nullptr);
-    const double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
-    if (s != SMG_OK && s != SMG_ENOTCONV) return s;
-    if (times_ms) times_ms[c] = ms;
-    if (ms < 0.97 * tbest) {   // a clear gain only: near-equal timings keep the earlier count
-      tbest = ms;
-      *best = candidates[c];
-    }
-  }
-  g_last_error.clear();
+smg_status smg_batch_destroy(smg_batch *b) {
+  if (!b) return SMG_OK;
+  (void)hipStreamSynchronize(b->drv.stream);
+  delete b;
   return SMG_OK;
+}
+
+smg_status smg_batch_solve(smg_batch *b, double *const *x, const double *const *rhs, double rtol, int maxit,
+                           smg_solve_info *infos) {
+  smg_status s = check_batch(b);
+  if (s != SMG_OK) return s;
+  if (!x || !rhs) return fail(SMG_EINVAL, "null vector arrays");
+  for (size_t i = 0; i < b->ctxs.size(); ++i) {
+    s = check_ptrs({x[i], rhs[i]});
+    if (s != SMG_OK) return s;
+    if (x[i] == rhs[i]) return fail(SMG_EINVAL, "x and b must be distinct");
+  }
+  if (!(rtol > 0) || maxit < 0) return fail(SMG_EINVAL, "need rtol > 0 and maxit >= 0");
+  try {
+    smg_status r = b->drv.solve(x, rhs, rtol, maxit, infos);
+    if (r == SMG_ENOTCONV) g_last_error = "iteration limit reached before the tolerance (some problem)";
+    else if (r == SMG_EBREAKDOWN) g_last_error = "breakdown (NaN/Inf) in FGMRES (some problem)";
+    else g_last_error.clear();
+    return r;
+  } catch (const smg::Error &e) {
+    return fail(e.code, e.msg);
+  } catch (const std::exception &e) {
+    return fail(SMG_EDEVICE, std::string("exception: ") + e.what());
+  }
+}
+
+smg_status smg_batch_precondition(smg_batch *b, const double *const *v, double *const *z) {
+  smg_status s = check_batch(b);
+  if (s != SMG_OK) return s;
+  if (!v || !z) return fail(SMG_EINVAL, "null vector arrays");
+  for (size_t i = 0; i < b->ctxs.size(); ++i) {
+    s = check_ptrs({v[i], z[i]});
+    if (s != SMG_OK) return s;
+  }
+  SMG_TRY(b->drv.precondition(v, z));
+}
+
+smg_status smg_batch_info(const smg_batch *b, int *packed_launches_per_cycle, int *variant) {
+  smg_status s = check_batch(b);
+  if (s != SMG_OK) return s;
+  if (packed_launches_per_cycle)
+    *packed_launches_per_cycle = b->drv.cycle_plan ? (int)b->drv.cycle_plan->launches.size() : 0;
+  if (variant) *variant = b->variant;
+  return SMG_OK;
+}
+
+namespace {
+void batch_autotune_impl(smg_batch *b, int probe_cycles, int *best, double *times_ms) {
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  SMG_HIP(hipEventCreate(&e0));
+  SMG_HIP(hipEventCreate(&e1));
+  double tbest = 1e300;
+  int ibest = 0;
+  try {
+    for (int c = 0; c < kNumBatchVariants; ++c) {
+      for (smg::EngineBase *e : b->drv.eng)
+        e->set_variants(kBatchVariants[c][0], kBatchVariants[c][1], kBatchVariants[c][2]);
+      b->drv.build_cycle();
+      SMG_HIP(hipGraphLaunch(b->drv.gexec, b->drv.stream));   // warm-up
+      SMG_HIP(hipEventRecord(e0, b->drv.stream));
+      for (int k = 0; k < probe_cycles; ++k) SMG_HIP(hipGraphLaunch(b->drv.gexec, b->drv.stream));
+      SMG_HIP(hipEventRecord(e1, b->drv.stream));
+      SMG_HIP(hipEventSynchronize(e1));
+      float ms = 0.0f;
+      SMG_HIP(hipEventElapsedTime(&ms, e0, e1));
+      if (times_ms) times_ms[c] = ms / probe_cycles;
+      if (ms < 0.97 * tbest) {   // a clear gain only: near-equal timings keep the earlier choice
+        tbest = ms;
+        ibest = c;
+      }
+    }
+  } catch (...) {
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    throw;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  for (smg::EngineBase *e : b->drv.eng)
+    e->set_variants(kBatchVariants[ibest][0], kBatchVariants[ibest][1], kBatchVariants[ibest][2]);
+  b->drv.build_cycle();
+  b->variant = ibest;
+  if (best) *best = ibest;
+}
+}  // namespace
+
+smg_status smg_batch_autotune(smg_batch *b, int probe_cycles, int *best, double *times_ms, int *ncand) {
+  smg_status s = check_batch(b);
+  if (s != SMG_OK) return s;
+  if (probe_cycles < 1) return fail(SMG_EINVAL, "probe_cycles must be >= 1");
+  if (ncand) *ncand = kNumBatchVariants;
+  SMG_TRY(batch_autotune_impl(b, probe_cycles, best, times_ms));
 }
 
 smg_status smg_gradient(smg_ctx *ctx, const double *x, const double *lam, double *g_logmu, double *g_f) {

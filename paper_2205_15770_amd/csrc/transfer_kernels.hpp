@@ -246,4 +246,34 @@ __global__ void __launch_bounds__(256) k_restrict(const T *__restrict__ rf, T *_
   else restrict_block<T, DIM, K - 1, false, CX>(rf, rc, zc, gp, blockIdx.x, blockIdx.y, blockIdx.z - nv);
 }
 
+// The two launches above as functors over a flat block index (packed
+// launches, packed.hpp): gx (x gy) blocks per field plane as in their grids.
+template <typename T, int DIM, int K>
+struct LProlong {
+  static constexpr int THREADS = 256;
+  const T *wc;
+  T *xf;
+  XferGeo<T> gv, gp;
+  int nv, gx;
+  __device__ void run(int b, int) const {
+    const int bx = b % gx, by = b / gx;
+    if (by < nv) prolong_block<T, DIM, K, true>(wc, xf, gv, bx, by);
+    else prolong_block<T, DIM, K - 1, false>(wc, xf, gp, bx, by - nv);
+  }
+};
+
+template <typename T, int DIM, int K, int CX>
+struct LRestrict {
+  static constexpr int THREADS = 256;
+  const T *rf;
+  T *rc, *zc;
+  XferGeo<T> gv, gp;
+  int nv, gx, gy;
+  __device__ void run(int b, int) const {
+    const int bx = b % gx, r = b / gx, by = r % gy, bz = r / gy;
+    if (bz < nv) restrict_block<T, DIM, K, true, CX>(rf, rc, zc, gv, bx, by, bz);
+    else restrict_block<T, DIM, K - 1, false, CX>(rf, rc, zc, gp, bx, by, bz - nv);
+  }
+};
+
 }  // namespace smg

@@ -113,6 +113,97 @@ __global__ void k_multi_axpy(T *w, const T *V, i64 ldv, int nv, const double *h,
   }
 }
 
+// The same reductions and updates as launch functors (packed launches over
+// many problems, see packed.hpp); identical arithmetic and summation order.
+template <typename T>
+struct LMultidotPartial {
+  static constexpr int THREADS = VB;
+  const T *V;
+  i64 ldv;
+  int nv;
+  const T *w;
+  i64 n;
+  double *partial;
+  __device__ void run(int b, int nb) const {
+    const i64 chunk = (n + nb - 1) / nb;
+    const i64 lo = (i64)b * chunk;
+    const i64 hi = lo + chunk < n ? lo + chunk : n;
+    for (int j = 0; j < nv; ++j) {
+      const T *v = V + (i64)j * ldv;
+      double s = 0.0;
+      for (i64 i = lo + threadIdx.x; i < hi; i += VB) s += (double)v[i] * (double)w[i];
+      s = block_sum<T>(s);
+      if (threadIdx.x == 0) partial[(i64)b * nv + j] = s;
+    }
+  }
+};
+
+struct LPartialFinish {
+  static constexpr int THREADS = VB;
+  const double *partial;
+  int nblocks, nv;
+  double *out;
+  __device__ void run(int j, int) const {
+    double s = 0.0;
+    for (int b = threadIdx.x; b < nblocks; b += VB) s += partial[(i64)b * nv + j];
+    s = block_sum<double>(s);
+    if (threadIdx.x == 0) out[j] = s;
+  }
+};
+
+template <typename T>
+struct LMultiAxpy {
+  static constexpr int THREADS = VB;
+  T *w;
+  const T *V;
+  i64 ldv;
+  int nv;
+  const double *h;
+  double sign;
+  i64 n;
+  __device__ void run(int b, int nb) const {
+    for (i64 i = (i64)b * VB + threadIdx.x; i < n; i += (i64)nb * VB) {
+      double s = 0.0;
+      for (int j = 0; j < nv; ++j) s += h[j] * (double)V[(i64)j * ldv + i];
+      w[i] = (T)((double)w[i] + sign * s);
+    }
+  }
+};
+
+template <typename T>
+struct LScaleInvSqrt {
+  static constexpr int THREADS = VB;
+  T *w;
+  const double *s2;
+  i64 n;
+  __device__ void run(int b, int nb) const {
+    const double v = s2[0];
+    const double f = v > 0.0 ? 1.0 / sqrt(v) : 0.0;
+    for (i64 i = (i64)b * VB + threadIdx.x; i < n; i += (i64)nb * VB) w[i] = (T)((double)w[i] * f);
+  }
+};
+
+// x0 = Kinv[0:N0, 0:N0] b0 (coarse solve), one wave per row
+template <typename T>
+struct LCoarseGemv {
+  static constexpr int THREADS = VB;
+  const double *Kinv;
+  i64 ld;
+  int n0;
+  const T *b;
+  T *x;
+  __device__ void run(int blk, int) const {
+    const int row = blk * (VB / 64) + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (row >= n0) return;
+    double s = 0.0;
+    for (int c = lane; c < n0; c += 64) s += Kinv[(i64)row * ld + c] * (double)b[c];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
+    if (lane == 0) x[row] = (T)s;
+  }
+};
+
 // ---------------------------------------------------------------------------
 // transfers (Sec. 3.2): canonical injection P per field, R = P^T
 // ---------------------------------------------------------------------------
