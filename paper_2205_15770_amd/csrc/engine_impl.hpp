@@ -69,6 +69,13 @@ inline int sweep_waves_from_env() {
 // pressure output use one wave per (tile, output field) instead of one wave
 // per tile for all fields (launches with velocity outputs only always do);
 // SMG_SPLIT2D_MAX_N overrides it (0: one wave per tile everywhere).
+// 3D general cells: the line-layout cell kernel (1, default) or the one
+// with a lane per quadrature point (0); SMG_GEN3_LINES overrides it.
+inline int gen3_lines_from_env() {
+  const char *e = std::getenv("SMG_GEN3_LINES");
+  return e != nullptr ? std::atoi(e) : 1;
+}
+
 inline int split2d_max_n_from_env() {
   const char *e = std::getenv("SMG_SPLIT2D_MAX_N");
   return e != nullptr ? std::atoi(e) : 256;
@@ -118,6 +125,7 @@ class EngineT : public EngineBase {
   bool gen_op = false;                       // operator through the vertex-given cell kernel
   int block3d_max_n = block3d_max_n_from_env();
   int split2d_max_n = split2d_max_n_from_env();
+  int gen3_lines = gen3_lines_from_env();
   int sweep_waves = sweep_waves_from_env();
   int fuse2d_max_n = fuse2d_max_n_from_env();
   int fuse3_2d_max_n = fuse3_2d_max_n_from_env();
@@ -381,8 +389,28 @@ class EngineT : public EngineBase {
       gg.cbu = g.cbu;
       gg.cbp = g.cbp;
       const int64_t ncells = (int64_t)gg.n[0] * gg.n[1] * (DIM == 3 ? gg.n[2] : 1);
-      hipLaunchKernelGGL((gen_apply_kernel<DIM, K, T, BLK, Op>), dim3((unsigned)((ncells + CPB - 1) / CPB)), dim3(64), 0,
-                         stream, gg, op);
+      if constexpr (DIM == 3) {
+        if (gen3_lines && gg.Nv + gg.Np < ((int64_t)1 << 31)) {
+          // line layout (CPW cells per wave), then the gather with one
+          // thread per node (32-bit node indices)
+          hipLaunchKernelGGL((gen3_line_kernel<K, T, BLK, Op>), dim3((unsigned)gen3_blocks<K>(gg)), dim3(64), 0, stream,
+                             gg, op);
+          check_launch();
+          constexpr bool OU = (BLK & (BLK_A | BLK_MASS | BLK_BT)) != 0, OP = (BLK & (BLK_B | BLK_C)) != 0;
+          const int64_t items = (OU ? gg.Nv : 0) + (OP ? gg.Np : 0);
+          hipLaunchKernelGGL((gen3_gather_kernel<K, T, BLK, Op>), dim3((unsigned)((items + 255) / 256)), dim3(256), 0,
+                             stream, gg, op, make_fastdiv((uint32_t)gg.vd[0]), make_fastdiv((uint32_t)gg.vd[1]),
+                             make_fastdiv((uint32_t)gg.pd[0]), make_fastdiv((uint32_t)gg.pd[1]));
+          check_launch();
+          return;
+        } else {
+          hipLaunchKernelGGL((gen_apply_kernel<DIM, K, T, BLK, Op>), dim3((unsigned)((ncells + CPB - 1) / CPB)),
+                             dim3(64), 0, stream, gg, op);
+        }
+      } else {
+        hipLaunchKernelGGL((gen_apply_kernel<DIM, K, T, BLK, Op>), dim3((unsigned)((ncells + CPB - 1) / CPB)), dim3(64),
+                           0, stream, gg, op);
+      }
       check_launch();
       hipLaunchKernelGGL((gen_gather_epilogue_kernel<DIM, K, T, BLK, Op>), dim3(grid_for(n_all)), dim3(VB), 0, stream,
                          gg, op);

@@ -406,6 +406,348 @@ __global__ void __launch_bounds__(64) gen_apply_kernel(const GenGeo<T> g, const 
   }
 }
 
+// ---------------------------------------------------------------------------
+// 3D cells in line layout (every-cell mode, the production path in 3D).
+//
+// One wave64 per CPW = 64 / (k+1)^2 cells that are consecutive in x.  Lane l
+// belongs to cell slot s = l / (k+1)^2 and holds one line of k+1 entries of
+// its cell: with r = l % (k+1)^2 and (a, b) = (r % (k+1), r / (k+1)),
+//   an x line runs through (y, z) = (a, b), a y line through (x, z) = (a, b),
+//   a z line through (x, y) = (a, b).
+// A 1D pass along the line costs k+1 FMA per entry with wave-uniform
+// coefficients (compile-time constants); lines change direction through
+// LDS, each lane writing its line and reading another.  Forward: the nodal
+// values are loaded as x lines (contiguous in memory), interpolated to the
+// Gauss points along x, y and z; the reference gradients follow from the
+// collocation derivative at the Gauss points along each direction.  The
+// quadrature-point work runs on z lines: on a trilinear cell the column
+// d x / d zeta of J is constant along a z line and the other two columns
+// are linear in zeta.  Backward: the transposed passes in reverse order, the
+// velocity results leave as x lines (contiguous), into the per-cell results
+// the gather kernel sums (gen3_result_index).  Every index stays within
+// the cell of the lane's slot; lanes of a slot past the last cell of the
+// row (and the spare slot when (k+1)^2 does not divide 64) work on the
+// row's last cell and store nothing.
+// ---------------------------------------------------------------------------
+template <int NV>
+__device__ __forceinline__ int line_index(int dir, int a, int b, int i) {
+  return dir == 0 ? i + NV * (a + NV * b) : (dir == 1 ? a + NV * (i + NV * b) : a + NV * (b + NV * i));
+}
+
+// out[o] = sum_i m[o][i] in[i] (TR: sum_i m[i][o] in[i]); ACC adds to out.
+template <bool TR, bool ACC, int NO, int NI, typename T, int R, int C>
+__device__ __forceinline__ void line_pass(const T (&m)[R][C], const T (&in)[NI], T (&out)[NO]) {
+  static_assert(TR ? (R == NI && C == NO) : (R == NO && C == NI), "line_pass shape");
+#pragma unroll
+  for (int o = 0; o < NO; ++o) {
+    T acc = (TR ? m[0][o] : m[o][0]) * in[0];
+#pragma unroll
+    for (int i = 1; i < NI; ++i) acc += (TR ? m[i][o] : m[o][i]) * in[i];
+    out[o] = ACC ? out[o] + acc : acc;
+  }
+}
+
+// Cells a launch of gen3_line_kernel covers per block, and its block count.
+template <int K>
+constexpr int gen3_cells_per_wave() {
+  return 64 / ((K + 1) * (K + 1));
+}
+template <int K, typename T>
+inline i64 gen3_blocks(const GenGeo<T> &g) {
+  constexpr int CPW = gen3_cells_per_wave<K>();
+  return (i64)((g.n[0] + CPW - 1) / CPW) * g.n[1] * g.n[2];
+}
+
+// Per-cell results of the line-layout kernel, ordered so that the gather
+// reads them along x rows: velocity [comp][cz][cy][lz][ly][cx][lx] and
+// pressure [cz][cy][lz][ly][cx][lx] (cell (cx, cy, cz), local node
+// (lx, ly, lz) with NS nodes per direction); the x lines a wave writes and a
+// gather wave reads are contiguous.
+template <int NS>
+__host__ __device__ __forceinline__ i64 gen3_result_index(const int (&n)[3], int comp, int cx, int cy, int cz, int lx,
+                                                          int ly, int lz) {
+  return ((((i64)comp * n[2] + cz) * n[1] + cy) * NS * NS + (i64)lz * NS + ly) * ((i64)n[0] * NS) + (i64)cx * NS + lx;
+}
+
+// Block and lane -> cell slot s, line (a, b) and cell (cx, cy, cz) of the
+// line-layout kernel; live is false for lanes that store nothing (their cell
+// is the last of the row).
+struct Gen3Lane {
+  int s, a, b, cx, cy, cz;
+  bool live;
+};
+template <int K>
+__host__ __device__ __forceinline__ Gen3Lane gen3_lane(const int (&n)[3], int block, int nblocks, int lane) {
+  constexpr int NV = K + 1, NL = NV * NV, CPW = gen3_cells_per_wave<K>();
+  Gen3Lane l;
+  l.s = lane / NL;
+  const int r = lane - l.s * NL;
+  l.a = r % NV;
+  l.b = r / NV;
+  // the wave's cells: CPW consecutive cells of one x row; the rows of one
+  // XCD are contiguous in (y, z)
+  const int wrow = (n[0] + CPW - 1) / CPW;
+  const int w = xcd_contiguous_tile(block, nblocks);
+  const int wx = w % wrow;
+  const int rest = w / wrow;
+  l.cy = rest % n[1];
+  l.cz = rest / n[1];
+  l.live = l.s < CPW && wx * CPW + l.s < n[0];
+  l.cx = l.live ? wx * CPW + l.s : n[0] - 1;
+  return l;
+}
+
+template <int K, typename T, int BLK, class Op>
+__global__ void __launch_bounds__(64) gen3_line_kernel(const GenGeo<T> g, const Op op) {
+  constexpr int NV = K + 1, NP = K;
+  constexpr int NL = NV * NV;                 // lines per cell and direction
+  constexpr int SLOTS = (64 + NL - 1) / NL;   // a spare slot when NL does not divide 64
+  constexpr int NN = NV * NV * NV, NPN = NP * NP * NP;
+  constexpr cfe::QTab<K, T> Q = cfe::make_qtab<K, T>();
+  constexpr bool NEED_U = (BLK & (BLK_A | BLK_MASS | BLK_B)) != 0;
+  constexpr bool NEED_P = (BLK & (BLK_BT | BLK_C)) != 0;
+  constexpr bool OUT_U = (BLK & (BLK_A | BLK_MASS | BLK_BT)) != 0;
+  constexpr bool OUT_P = (BLK & (BLK_B | BLK_C)) != 0;
+  __shared__ T lds[3][SLOTS][NN];
+
+  const Gen3Lane ln = gen3_lane<K>(g.n, (int)blockIdx.x, (int)gridDim.x, (int)threadIdx.x);
+  const int s = ln.s, a = ln.a, b = ln.b, cx = ln.cx, cy = ln.cy, cz = ln.cz;
+  const bool live = ln.live;
+  const i64 cell = cx + (i64)g.n[0] * (cy + (i64)g.n[1] * cz);
+  T *const B0 = lds[0][s];
+  T *const B1 = lds[1][s];
+  T *const B2 = lds[2][s];
+  auto put = [&](T *B, int dir, const T(&v)[NV]) {
+#pragma unroll
+    for (int i = 0; i < NV; ++i) B[line_index<NV>(dir, a, b, i)] = v[i];
+  };
+  auto get = [&](const T *B, int dir, T(&v)[NV]) {
+#pragma unroll
+    for (int i = 0; i < NV; ++i) v[i] = B[line_index<NV>(dir, a, b, i)];
+  };
+
+  // ---- velocity: values and reference gradients at the points (a, b, k) of the z line
+  T uq[3][NV], gq[3][3][NV];
+#pragma unroll
+  for (int c = 0; c < 3; ++c)
+#pragma unroll
+    for (int k = 0; k < NV; ++k) {
+      uq[c][k] = 0;
+      gq[c][0][k] = gq[c][1][k] = gq[c][2][k] = 0;
+    }
+  if constexpr (NEED_U) {
+    const int gy = K * cy + a, gz = K * cz + b;
+    const bool bc_yz = on_box_boundary(gy, g.vd[1]) || on_box_boundary(gz, g.vd[2]);
+    const i64 row = (i64)g.vd[0] * (gy + (i64)g.vd[1] * gz) + K * cx;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      T u[NV], t[NV], t2[NV];
+#pragma unroll
+      for (int i = 0; i < NV; ++i) {
+        const bool bc = bc_yz || on_box_boundary(K * cx + i, g.vd[0]);
+        u[i] = (Op::ZERO_BC && bc) ? T(0) : op.load_u((i64)c * g.Nv + row + i);
+      }
+      line_pass<false, false, NV, NV>(Q.V, u, t);   // x: nodes -> points
+      put(B0, 0, t);
+      __syncthreads();
+      get(B0, 1, t2);
+      line_pass<false, false, NV, NV>(Q.V, t2, t);  // y
+      put(B1, 1, t);
+      __syncthreads();
+      get(B1, 2, t2);
+      line_pass<false, false, NV, NV>(Q.V, t2, uq[c]);       // z: values at the points
+      line_pass<false, false, NV, NV>(Q.D, uq[c], gq[c][2]);  // d / d zeta
+      put(B2, 2, uq[c]);
+      __syncthreads();
+      get(B2, 0, t2);
+      line_pass<false, false, NV, NV>(Q.D, t2, t);  // d / d xi on the x lines
+      put(B0, 0, t);
+      get(B2, 1, t2);
+      line_pass<false, false, NV, NV>(Q.D, t2, t);  // d / d eta on the y lines
+      put(B1, 1, t);
+      __syncthreads();
+      get(B0, 2, gq[c][0]);
+      get(B1, 2, gq[c][1]);
+      __syncthreads();
+    }
+  }
+
+  // ---- pressure at the points of the z line (pressure lines: K nodes)
+  T pq[NV];
+#pragma unroll
+  for (int k = 0; k < NV; ++k) pq[k] = 0;
+  if constexpr (NEED_P) {
+    T p[NP], t[NV], t2[NP];
+    const bool pl = a < NP && b < NP;
+    const i64 prow = (i64)g.pd[0] * ((K - 1) * cy + a + (i64)g.pd[1] * ((K - 1) * cz + b)) + (K - 1) * cx;
+#pragma unroll
+    for (int i = 0; i < NP; ++i) p[i] = pl ? op.load_p(prow + i) : T(0);
+    line_pass<false, false, NV, NP>(Q.Vp, p, t);   // x lines (y, z) = (a, b) < NP
+    put(B0, 0, t);
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < NP; ++j) t2[j] = B0[line_index<NV>(1, a, b, j)];
+    line_pass<false, false, NV, NP>(Q.Vp, t2, t);  // y lines (x, z) = (a, b), z < NP
+    put(B1, 1, t);
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < NP; ++k) t2[k] = B1[line_index<NV>(2, a, b, k)];
+    line_pass<false, false, NV, NP>(Q.Vp, t2, pq);  // z lines
+    __syncthreads();
+  }
+
+  // ---- geometry of the trilinear map on the z line (xi, eta) = (x_a, x_b)
+  T dE[3], E0[3], dF[3], F0[3], Zc[3];
+  {
+    const i64 vx = g.n[0] + 1, vxy = vx * (g.n[1] + 1);
+    const i64 v0 = cx + vx * cy + vxy * cz;
+    T X[8][3];
+#pragma unroll
+    for (int v = 0; v < 8; ++v) {
+      const i64 vid = v0 + (v & 1) + vx * ((v >> 1) & 1) + vxy * ((v >> 2) & 1);
+#pragma unroll
+      for (int d = 0; d < 3; ++d) X[v][d] = g.verts[vid * 3 + d];
+    }
+    const T xi = pick(Q.x, a), eta = pick(Q.x, b);
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      // vertex v = ox + 2 oy + 4 oz
+      const T e0 = (X[1][d] - X[0][d]) * (T(1) - eta) + (X[3][d] - X[2][d]) * eta;   // d/dxi, zeta = 0
+      const T e1 = (X[5][d] - X[4][d]) * (T(1) - eta) + (X[7][d] - X[6][d]) * eta;   // d/dxi, zeta = 1
+      const T f0 = (X[2][d] - X[0][d]) * (T(1) - xi) + (X[3][d] - X[1][d]) * xi;     // d/deta, zeta = 0
+      const T f1 = (X[6][d] - X[4][d]) * (T(1) - xi) + (X[7][d] - X[5][d]) * xi;     // d/deta, zeta = 1
+      E0[d] = e0;
+      dE[d] = e1 - e0;
+      F0[d] = f0;
+      dF[d] = f1 - f0;
+      Zc[d] = ((X[4][d] - X[0][d]) * (T(1) - xi) + (X[5][d] - X[1][d]) * xi) * (T(1) - eta) +
+              ((X[6][d] - X[2][d]) * (T(1) - xi) + (X[7][d] - X[3][d]) * xi) * eta;
+    }
+  }
+  const T wab = pick(Q.w, a) * pick(Q.w, b);
+  const T mu = g.mu_cell != nullptr ? g.mu_cell[cell] : g.mu;
+
+  // ---- integrands at the points of the z line (in place: gq -> test coefficients)
+  T vq[3][NV], pc[NV];
+#pragma unroll
+  for (int k = 0; k < NV; ++k) {
+    T J[3][3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      J[d][0] = E0[d] + Q.x[k] * dE[d];
+      J[d][1] = F0[d] + Q.x[k] * dF[d];
+      J[d][2] = Zc[d];
+    }
+    const T c00 = J[1][1] * J[2][2] - J[1][2] * J[2][1];
+    const T c01 = J[1][2] * J[2][0] - J[1][0] * J[2][2];
+    const T c02 = J[1][0] * J[2][1] - J[1][1] * J[2][0];
+    const T det = J[0][0] * c00 + J[0][1] * c01 + J[0][2] * c02;
+    const T id = T(1) / det;
+    T Ji[3][3];   // J^-1
+    Ji[0][0] = c00 * id;
+    Ji[1][0] = c01 * id;
+    Ji[2][0] = c02 * id;
+    Ji[0][1] = (J[0][2] * J[2][1] - J[0][1] * J[2][2]) * id;
+    Ji[1][1] = (J[0][0] * J[2][2] - J[0][2] * J[2][0]) * id;
+    Ji[2][1] = (J[0][1] * J[2][0] - J[0][0] * J[2][1]) * id;
+    Ji[0][2] = (J[0][1] * J[1][2] - J[0][2] * J[1][1]) * id;
+    Ji[1][2] = (J[0][2] * J[1][0] - J[0][0] * J[1][2]) * id;
+    Ji[2][2] = (J[0][0] * J[1][1] - J[0][1] * J[1][0]) * id;
+    const T JxW = det * wab * Q.w[k];
+    T gp[3][3];   // physical gradients grad u_c
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+#pragma unroll
+      for (int e = 0; e < 3; ++e) gp[c][e] = Ji[0][e] * gq[c][0][k] + Ji[1][e] * gq[c][1][k] + Ji[2][e] * gq[c][2][k];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      T val = 0;
+      if constexpr ((BLK & BLK_A) != 0) val += g.gr * uq[c][k];
+      if constexpr ((BLK & BLK_MASS) != 0) val += uq[c][k];
+      vq[c][k] = val * JxW;
+      T G[3] = {0, 0, 0};
+#pragma unroll
+      for (int e = 0; e < 3; ++e) {
+        if constexpr ((BLK & BLK_A) != 0) G[e] = mu * (g.sym ? T(0.5) * (gp[c][e] + gp[e][c]) : gp[c][e]);
+        if constexpr ((BLK & BLK_BT) != 0)
+          if (e == c) G[e] -= pq[k];
+      }
+#pragma unroll
+      for (int d = 0; d < 3; ++d) gq[c][d][k] = (Ji[d][0] * G[0] + Ji[d][1] * G[1] + Ji[d][2] * G[2]) * JxW;
+    }
+    T pv = 0;
+    if constexpr ((BLK & BLK_B) != 0) pv -= gp[0][0] + gp[1][1] + gp[2][2];
+    if constexpr ((BLK & BLK_C) != 0) pv += ((BLK & BLK_CPLUS) ? g.cp : -g.cp) * pq[k];
+    pc[k] = pv * JxW;
+  }
+
+  // ---- velocity test functions, per component; results as x lines
+  if constexpr (OUT_U) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      T wz[NV], t[NV], t2[NV];
+#pragma unroll
+      for (int k = 0; k < NV; ++k) wz[k] = vq[c][k];
+      line_pass<true, true, NV, NV>(Q.D, gq[c][2], wz);   // + D^T along z
+      put(B0, 2, gq[c][0]);
+      put(B1, 2, gq[c][1]);
+      __syncthreads();
+      get(B0, 0, t2);
+      line_pass<true, false, NV, NV>(Q.D, t2, t);   // D^T along x
+      __syncthreads();
+      put(B0, 0, t);
+      get(B1, 1, t2);
+      line_pass<true, false, NV, NV>(Q.D, t2, t);   // D^T along y
+      __syncthreads();
+      put(B1, 1, t);
+      __syncthreads();
+      get(B0, 2, t2);
+#pragma unroll
+      for (int k = 0; k < NV; ++k) wz[k] += t2[k];
+      get(B1, 2, t2);
+#pragma unroll
+      for (int k = 0; k < NV; ++k) wz[k] += t2[k];
+      line_pass<true, false, NV, NV>(Q.V, wz, t);   // z: points -> nodes
+      put(B2, 2, t);
+      __syncthreads();
+      get(B2, 1, t2);
+      line_pass<true, false, NV, NV>(Q.V, t2, t);   // y
+      __syncthreads();
+      put(B0, 1, t);
+      __syncthreads();
+      get(B0, 0, t2);
+      line_pass<true, false, NV, NV>(Q.V, t2, t);   // x
+      if (live) {
+        T *dst = g.cbu + gen3_result_index<NV>(g.n, c, cx, cy, cz, 0, a, b);
+#pragma unroll
+        for (int i = 0; i < NV; ++i) dst[i] = t[i];
+      }
+      __syncthreads();
+    }
+  }
+
+  // ---- pressure test functions; results as x lines of K nodes
+  if constexpr (OUT_P) {
+    T t[NP], t2[NV];
+    line_pass<true, false, NP, NV>(Q.Vp, pc, t);   // z: points -> pressure nodes
+#pragma unroll
+    for (int k = 0; k < NP; ++k) B0[line_index<NV>(2, a, b, k)] = t[k];
+    __syncthreads();
+    get(B0, 1, t2);                                // y lines (x, z) = (a, b), z < K
+    line_pass<true, false, NP, NV>(Q.Vp, t2, t);
+#pragma unroll
+    for (int j = 0; j < NP; ++j) B1[line_index<NV>(1, a, b, j)] = t[j];
+    __syncthreads();
+    get(B1, 0, t2);                                // x lines (y, z) = (a, b) < K
+    line_pass<true, false, NP, NV>(Q.Vp, t2, t);
+    if (live && a < NP && b < NP) {
+      T *dst = g.cbp + gen3_result_index<NP>(g.n, 0, cx, cy, cz, 0, a, b);
+#pragma unroll
+      for (int i = 0; i < NP; ++i) dst[i] = t[i];
+    }
+  }
+}
+
 // Dirichlet rows and the caller's epilogue on every node, from the
 // accumulated cell sums.
 template <int DIM, typename T, int BLK, class Op>
@@ -509,6 +851,114 @@ __global__ void gen_gather_epilogue_kernel(const GenGeo<T> g, const Op op) {
       const T t = gather_cells<DIM, K - 1, NPN>(g, g.cbp, 1, 0, x, y, z);
       op.store_p(j, t, NEED_P ? op.load_p(j) : T(0), op.fetch_p(j));
     }
+  }
+}
+
+// n / d for 0 <= n < 2^31 without a division: n m >> (31 + s) with
+// s = ceil(log2 d), m = ceil(2^(31+s) / d) < 2^32 (the rounding error of m
+// shifts n / d by less than n d / 2^(31+s) / d < 1 / d, which never crosses
+// an integer).
+struct FastDiv {
+  uint32_t d, m, s;
+};
+inline FastDiv make_fastdiv(uint32_t d) {
+  uint32_t s = 0;
+  while ((1ull << s) < d) ++s;
+  const uint64_t p = 1ull << (31 + s);
+  return FastDiv{d, (uint32_t)((p + d - 1) / d), s};
+}
+__host__ __device__ __forceinline__ uint32_t fast_div(uint32_t n, const FastDiv &f) {
+  return (uint32_t)(((uint64_t)n * f.m) >> (31 + f.s));
+}
+
+// The cells around lattice coordinate v (spacing deg per cell, n cells) along
+// one direction: first cell c0 and count (1 inside a cell, 2 on an interior
+// cell boundary, 1 on the domain boundary).
+__host__ __device__ __forceinline__ void cells_around(int v, int deg, int n, int &c0, int &nc) {
+  const int c = v / deg;
+  if (v - c * deg == 0) {
+    c0 = c > 0 ? c - 1 : 0;
+    nc = (c > 0 ? 1 : 0) + (c < n ? 1 : 0);
+  } else {
+    c0 = c;
+    nc = 1;
+  }
+}
+
+// Sum of the per-cell results at lattice node (x, y, z) over the cells
+// around it (c0, nc per direction), cells in increasing index order.  All
+// eight candidate reads are issued unconditionally (a missing second cell
+// reads the first one again) and the missing ones add zero, so the loads
+// overlap and the sum equals the one over the existing cells in that order.
+template <int NS, int DEG, typename T>
+__device__ __forceinline__ T sum_cells(const T *res, const int (&n)[3], int comp, int x, int y, int z,
+                                       const int (&c0)[3], const int (&nc)[3]) {
+  T v[8];
+#pragma unroll
+  for (int e = 0; e < 8; ++e) {
+    const int cx = c0[0] + ((e & 1) && nc[0] == 2 ? 1 : 0);
+    const int cy = c0[1] + ((e & 2) && nc[1] == 2 ? 1 : 0);
+    const int cz = c0[2] + ((e & 4) && nc[2] == 2 ? 1 : 0);
+    v[e] = res[gen3_result_index<NS>(n, comp, cx, cy, cz, x - DEG * cx, y - DEG * cy, z - DEG * cz)];
+  }
+  T acc = 0;
+#pragma unroll
+  for (int e = 0; e < 8; ++e) {
+    const bool ok = (!(e & 1) || nc[0] == 2) && (!(e & 2) || nc[1] == 2) && (!(e & 4) || nc[2] == 2);
+    acc += ok ? v[e] : T(0);
+  }
+  return acc;
+}
+
+// 3D every-cell mode epilogue: one thread per velocity node (its three
+// components) or pressure node, the sum over the cells around the node of
+// their results in increasing cell order, then the Dirichlet rows and the
+// caller's epilogue as in gen_gather_epilogue_kernel.  Threads of one XCD
+// take a contiguous range of nodes (z slabs, as the cell kernel's waves).
+// fv: divisions by the velocity lattice extents vd[0], vd[1]; fp: pressure.
+template <int K, typename T, int BLK, class Op>
+__global__ void __launch_bounds__(256)
+gen3_gather_kernel(const GenGeo<T> g, const Op op, const FastDiv fv0, const FastDiv fv1, const FastDiv fp0,
+                   const FastDiv fp1) {
+  constexpr int NV = K + 1, NP = K;
+  constexpr bool NEED_U = (BLK & (BLK_A | BLK_MASS | BLK_B)) != 0;
+  constexpr bool NEED_P = (BLK & (BLK_BT | BLK_C)) != 0;
+  constexpr bool OUT_U = (BLK & (BLK_A | BLK_MASS | BLK_BT)) != 0;
+  constexpr bool OUT_P = (BLK & (BLK_B | BLK_C)) != 0;
+  const uint32_t t = (uint32_t)xcd_contiguous_tile((int)blockIdx.x, (int)gridDim.x) * 256u + threadIdx.x;
+  const uint32_t nv = OUT_U ? (uint32_t)g.Nv : 0u;
+  if (t < nv) {
+    const uint32_t q = fast_div(t, fv0);
+    const int x = (int)(t - q * fv0.d);
+    const uint32_t zq = fast_div(q, fv1);
+    const int y = (int)(q - zq * fv1.d);
+    const int z = (int)zq;
+    const bool bc = on_box_boundary(x, g.vd[0]) || on_box_boundary(y, g.vd[1]) || on_box_boundary(z, g.vd[2]);
+    int c0[3], nc[3];
+    cells_around(x, K, g.n[0], c0[0], nc[0]);
+    cells_around(y, K, g.n[1], c0[1], nc[1]);
+    cells_around(z, K, g.n[2], c0[2], nc[2]);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const i64 i = (i64)c * g.Nv + t;
+      const T v = NEED_U ? op.load_u(i) : T(0);
+      const T acc = sum_cells<NV, K, T>(g.cbu, g.n, c, x, y, z, c0, nc);
+      const T r = bc ? ((BLK & BLK_A) != 0 ? v : T(0)) : acc;
+      op.store_u(i, r, bc ? r : v, bc, op.fetch_u(i));
+    }
+  } else if (OUT_P && t - nv < (uint32_t)g.Np) {
+    const uint32_t j = t - nv;
+    const uint32_t q = fast_div(j, fp0);
+    const int x = (int)(j - q * fp0.d);
+    const uint32_t zq = fast_div(q, fp1);
+    const int y = (int)(q - zq * fp1.d);
+    const int z = (int)zq;
+    int c0[3], nc[3];
+    cells_around(x, K - 1, g.n[0], c0[0], nc[0]);
+    cells_around(y, K - 1, g.n[1], c0[1], nc[1]);
+    cells_around(z, K - 1, g.n[2], c0[2], nc[2]);
+    const T acc = sum_cells<NP, K - 1, T>(g.cbp, g.n, 0, x, y, z, c0, nc);
+    op.store_p(j, acc, NEED_P ? op.load_p(j) : T(0), op.fetch_p(j));
   }
 }
 
