@@ -212,20 +212,58 @@ __device__ __forceinline__ void vel_cell(const Geo3<T> &g, T mu, const T (&u)[K 
   const T(&By)[K][K + 1] = COMP == 1 ? R.Gr : R.Nr;
   const T(&Bz)[K][K + 1] = COMP == 2 ? R.Gr : R.Nr;
   if constexpr ((BLK & BLK_A) != 0) {
+    // plane by plane in z (fewer live values than whole-cell passes):
+    //   y[oz] = sum_iz Mz[oz][iz] ((ax Kx + bx Mx) My + cy Mx Ky) u[iz]
+    //                + Kz[oz][iz] cz Mx My u[iz]
+    // with ax = mu sKx, bx = gamma rho sM, cy = mu sKy, cz = mu sKz
     T X[NV][NV];
-    const T ax = mu * g.sKx, bx = g.gr * g.sM;
+    const T ax = mu * g.sKx, bx = g.gr * g.sM, cy = mu * g.sKy, cz = cy * g.rz;
 #pragma unroll
     for (int i = 0; i < NV; ++i)
 #pragma unroll
       for (int j = 0; j < NV; ++j) X[i][j] = ax * R.Kr[i][j] + bx * R.Mr[i][j];
-    T a[NV][NV][NV], t[NV][NV][NV];
-    pass_z<false, false>(R.Mr, u, a, T(1));
-    pass_y<false, false>(R.Mr, a, t, T(1));
-    pass_x<false, false>(X, t, y, T(1));
-    pass_y<false, false>(R.Kr, a, t, T(1));
-    pass_z<false, false>(R.Kr, u, a, T(1));
-    pass_y<false, true>(R.Mr, a, t, g.rz);
-    pass_x<false, true>(R.Mr, t, y, mu * g.sKy);
+#pragma unroll
+    for (int iz = 0; iz < NV; ++iz) {
+      T t1[NV][NV], t2[NV][NV], v1[NV][NV], v2[NV][NV];
+      // t1 = My u, t2 = cy Ky u on the plane ([y][x])
+#pragma unroll
+      for (int x = 0; x < NV; ++x)
+#pragma unroll
+        for (int o = 0; o < NV; ++o) {
+          T s1 = 0, s2 = 0;
+#pragma unroll
+          for (int i = 0; i < NV; ++i) {
+            s1 += R.Mr[o][i] * u[iz][i][x];
+            s2 += R.Kr[o][i] * u[iz][i][x];
+          }
+          t1[o][x] = s1;
+          t2[o][x] = cy * s2;
+        }
+      // v1 = X t1 + Mx t2, v2 = cz Mx t1 along x
+#pragma unroll
+      for (int yy = 0; yy < NV; ++yy)
+#pragma unroll
+        for (int o = 0; o < NV; ++o) {
+          T s1 = 0, s2 = 0;
+#pragma unroll
+          for (int i = 0; i < NV; ++i) {
+            s1 += X[o][i] * t1[yy][i] + R.Mr[o][i] * t2[yy][i];
+            s2 += R.Mr[o][i] * t1[yy][i];
+          }
+          v1[yy][o] = s1;
+          v2[yy][o] = cz * s2;
+        }
+      // y[oz] (+)= Mz[oz][iz] v1 + Kz[oz][iz] v2
+#pragma unroll
+      for (int oz = 0; oz < NV; ++oz)
+#pragma unroll
+        for (int yy = 0; yy < NV; ++yy)
+#pragma unroll
+          for (int xx = 0; xx < NV; ++xx) {
+            const T c = R.Mr[oz][iz] * v1[yy][xx] + R.Kr[oz][iz] * v2[yy][xx];
+            y[oz][yy][xx] = iz == 0 ? c : y[oz][yy][xx] + c;
+          }
+    }
   } else if constexpr ((BLK & BLK_MASS) != 0) {
     T a[NV][NV][NV], t[NV][NV][NV];
     pass_z<false, false>(R.Mr, u, a, T(1));
@@ -288,19 +326,19 @@ __device__ __forceinline__ void vel_wave(const Geo3<T> &g, const Op &op, const C
     }
     const bool owner = s.col_owner && cl >= s.z_lo;
     const bool last_z = cl == g.n[2] - 1;
-    // epilogue inputs of the owned nodes [0,K)^3
+    T y[NV][NV][NV];
+    vel_cell<K, T, BLK, COMP>(g, mu, u, p, y);
+    // epilogue inputs of the owned nodes [0,K)^3, requested after the cell
+    // product (not live across it) and before the hand-over shuffles
     typename Op::Pre pre[K][K][K];
     if (owner) {
 #pragma unroll
       for (int z = 0; z < K; ++z)
 #pragma unroll
-        for (int y = 0; y < K; ++y)
+        for (int yy = 0; yy < K; ++yy)
 #pragma unroll
-          for (int x = 0; x < K; ++x) pre[z][y][x] = op.fetch_u(col.u_at(COMP, cl, x, y, z));
+          for (int x = 0; x < K; ++x) pre[z][yy][x] = op.fetch_u(col.u_at(COMP, cl, x, yy, z));
     }
-
-    T y[NV][NV][NV];
-    vel_cell<K, T, BLK, COMP>(g, mu, u, p, y);
     hand_over_xy<TX>(y, s.lcx, s.lcy, s.last_x, s.last_y);
 #pragma unroll
     for (int j = 0; j < NV; ++j)
