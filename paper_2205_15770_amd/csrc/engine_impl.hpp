@@ -30,11 +30,11 @@ inline int block3d_max_n_from_env() {
 // Largest 2D level (cells per direction) on which the smoother fuses the
 // operator application producing a Chebyshev right-hand side with the first
 // Chebyshev step (one launch instead of two; its 8 x 8 tile owns 5 x 5
-// cells, so it recomputes more, which pays where launches dominate: up to
-// 256^2 on the 512^2 solve).  SMG_FUSE2D_MAX_N overrides it (0: never).
+// cells, so it recomputes more; measured on the 512^2 solve it pays on
+// every level up to 512^2).  SMG_FUSE2D_MAX_N overrides it (0: never).
 inline int fuse2d_max_n_from_env() {
   const char *e = std::getenv("SMG_FUSE2D_MAX_N");
-  return e != nullptr ? std::atoi(e) : 256;
+  return e != nullptr ? std::atoi(e) : 512;
 }
 
 // Largest 2D level (cells per direction) on which an Uzawa step with k_S = 1
@@ -65,10 +65,6 @@ inline int sweep_waves_from_env() {
   return v > 0 ? v : 4096;
 }
 
-// Largest 2D level (cells per direction) whose operator launches with a
-// pressure output use one wave per (tile, output field) instead of one wave
-// per tile for all fields (launches with velocity outputs only always do);
-// SMG_SPLIT2D_MAX_N overrides it (0: one wave per tile everywhere).
 // 3D general cells: the line-layout cell kernel (1, default) or the one
 // with a lane per quadrature point (0); SMG_GEN3_LINES overrides it.
 inline int gen3_lines_from_env() {
@@ -76,9 +72,13 @@ inline int gen3_lines_from_env() {
   return e != nullptr ? std::atoi(e) : 1;
 }
 
+// Largest 2D level (cells per direction) whose operator launches with a
+// pressure output use one wave per (tile, output field) instead of one wave
+// per tile for all fields (launches with velocity outputs only always do);
+// SMG_SPLIT2D_MAX_N overrides it (0: one wave per tile everywhere).
 inline int split2d_max_n_from_env() {
   const char *e = std::getenv("SMG_SPLIT2D_MAX_N");
-  return e != nullptr ? std::atoi(e) : 256;
+  return e != nullptr ? std::atoi(e) : 512;
 }
 
 // Lanczos (Algorithm 2 asks for a close approximation of lambda_max): steps,

@@ -466,8 +466,9 @@ namespace {
 // (cells per direction) that runs one wave per output field, the two-stage
 // fused launches (tiles owning 5 x 5 cells) and the three-stage launches
 // (3 x 3); the others run one wave per 8 x 8 tile owning 7 x 7 cells.
+// Variant 0 is the solvers' default.
 constexpr int kBatchVariants[][3] = {
-    {256, 256, 128}, {0, 0, 0}, {256, 0, 0}, {256, 256, 0}, {512, 512, 128}, {256, 256, 256}, {512, 256, 64}};
+    {512, 512, 128}, {0, 0, 0}, {256, 0, 0}, {256, 256, 0}, {256, 256, 128}, {256, 256, 256}, {512, 256, 64}};
 constexpr int kNumBatchVariants = (int)(sizeof(kBatchVariants) / sizeof(kBatchVariants[0]));
 
 smg_status check_batch(const smg_batch *b) {
