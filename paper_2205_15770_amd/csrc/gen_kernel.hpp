@@ -18,6 +18,8 @@
 // a separate epilogue pass over all nodes then applies the Dirichlet rows and
 // the caller's fused vector algebra (the same functors as the box kernels).
 #pragma once
+#include <type_traits>
+
 #include "cell_kernel.hpp"
 #include "fe1d_const.hpp"
 
@@ -429,9 +431,21 @@ __global__ void __launch_bounds__(64) gen_apply_kernel(const GenGeo<T> g, const 
 // row (and the spare slot when (k+1)^2 does not divide 64) work on the
 // row's last cell and store nothing.
 // ---------------------------------------------------------------------------
+// LDS position of entry (x, y, z) of a cell slot: strides 1, PY, PZ, slots
+// LINE_SLOT apart.  For k+1 = 4 the strides are padded (5, 20, slot 80), which
+// takes the bank conflicts of the x and y line accesses of a wave from 4-way
+// to none and leaves the z line accesses at 2-way (the unpadded 4, 16, 64
+// layout: 4, 4 and 2-4 way).
+template <int NV>
+struct LineLayout {
+  static constexpr int PY = NV == 4 ? 5 : NV;
+  static constexpr int PZ = NV == 4 ? 20 : NV * NV;
+  static constexpr int SLOT = NV == 4 ? 80 : NV * NV * NV;
+};
 template <int NV>
 __device__ __forceinline__ int line_index(int dir, int a, int b, int i) {
-  return dir == 0 ? i + NV * (a + NV * b) : (dir == 1 ? a + NV * (i + NV * b) : a + NV * (b + NV * i));
+  constexpr int PY = LineLayout<NV>::PY, PZ = LineLayout<NV>::PZ;
+  return dir == 0 ? i + PY * a + PZ * b : (dir == 1 ? a + PY * i + PZ * b : a + PY * b + PZ * i);
 }
 
 // out[o] = sum_i m[o][i] in[i] (TR: sum_i m[i][o] in[i]); ACC adds to out.
@@ -502,21 +516,20 @@ __global__ void __launch_bounds__(64) gen3_line_kernel(const GenGeo<T> g, const 
   constexpr int NV = K + 1, NP = K;
   constexpr int NL = NV * NV;                 // lines per cell and direction
   constexpr int SLOTS = (64 + NL - 1) / NL;   // a spare slot when NL does not divide 64
-  constexpr int NN = NV * NV * NV, NPN = NP * NP * NP;
   constexpr cfe::QTab<K, T> Q = cfe::make_qtab<K, T>();
   constexpr bool NEED_U = (BLK & (BLK_A | BLK_MASS | BLK_B)) != 0;
   constexpr bool NEED_P = (BLK & (BLK_BT | BLK_C)) != 0;
   constexpr bool OUT_U = (BLK & (BLK_A | BLK_MASS | BLK_BT)) != 0;
   constexpr bool OUT_P = (BLK & (BLK_B | BLK_C)) != 0;
-  __shared__ T lds[3][SLOTS][NN];
+  __shared__ T lds[3][SLOTS * LineLayout<NV>::SLOT];
 
   const Gen3Lane ln = gen3_lane<K>(g.n, (int)blockIdx.x, (int)gridDim.x, (int)threadIdx.x);
   const int s = ln.s, a = ln.a, b = ln.b, cx = ln.cx, cy = ln.cy, cz = ln.cz;
   const bool live = ln.live;
   const i64 cell = cx + (i64)g.n[0] * (cy + (i64)g.n[1] * cz);
-  T *const B0 = lds[0][s];
-  T *const B1 = lds[1][s];
-  T *const B2 = lds[2][s];
+  T *const B0 = lds[0] + s * LineLayout<NV>::SLOT;
+  T *const B1 = lds[1] + s * LineLayout<NV>::SLOT;
+  T *const B2 = lds[2] + s * LineLayout<NV>::SLOT;
   auto put = [&](T *B, int dir, const T(&v)[NV]) {
 #pragma unroll
     for (int i = 0; i < NV; ++i) B[line_index<NV>(dir, a, b, i)] = v[i];
@@ -642,7 +655,9 @@ __global__ void __launch_bounds__(64) gen3_line_kernel(const GenGeo<T> g, const 
     const T c01 = J[1][2] * J[2][0] - J[1][0] * J[2][2];
     const T c02 = J[1][0] * J[2][1] - J[1][1] * J[2][0];
     const T det = J[0][0] * c00 + J[0][1] * c01 + J[0][2] * c02;
-    const T id = T(1) / det;
+    T id;
+    if constexpr (std::is_same<T, float>::value) id = __builtin_amdgcn_rcpf(det);   // 1 ulp (FP32 cycle)
+    else id = T(1) / det;
     T Ji[3][3];   // J^-1
     Ji[0][0] = c00 * id;
     Ji[1][0] = c01 * id;
