@@ -95,16 +95,27 @@ def rhs(mg, level, dim, seed=2, force="random"):
     return b
 
 
-def time_vmult(mg, level, dtype, reps=10):
+# Plain sum-factorisation flops per DoF of K x (velocity passes, pressure
+# passes, quadrature-point physics; counted per cell and divided by the DoFs
+# per cell) for the 3D workloads, against which the vmult is vector-ALU bound.
+FLOPS_PER_DOF = {"stokes3d_q2q1_64": 277.0, "stokes3d_q3q2_32_pert": 443.0}
+FP64_PEAK_TFLOPS = 78.6
+
+
+def time_vmult(mg, level, dtype, reps=10, max_pairs=None, flops_per_dof=None):
     """GDoF/s of y = K x, HIP events on the stream, rotating over as many
     (x, y) pairs as it takes to exceed twice the 256 MB Infinity Cache for the
-    vector type (so x comes from HBM and y goes to it); also the same
-    launches on one pair (cache-resident) for comparison."""
+    vector type (so x comes from HBM and y goes to it; max_pairs caps that for
+    small levels, which then stay cache-resident); also the same launches on
+    one pair (cache-resident) for comparison.  With flops_per_dof, also the
+    achieved vector rate against the FP64 / FP32 vector peak."""
     import torch
     import synth_inputs as si
     n = mg.n_total(level)
     esize = 8 if dtype == torch.float64 else 4
     pairs = max(4, -(-int(2 * MALL_BYTES) // (2 * esize * n)))
+    if max_pairs is not None:
+        pairs = min(pairs, max_pairs)
     x0 = torch.tensor(si.uniform(n, 200), dtype=dtype, device="cuda")
     xs = [x0 * (1.0 + 0.01 * i) for i in range(pairs)]
     ys = [torch.empty(n, dtype=dtype, device="cuda") for _ in range(pairs)]
@@ -126,12 +137,18 @@ def time_vmult(mg, level, dtype, reps=10):
     torch.cuda.synchronize()
     t_hot = e0.elapsed_time(e1) * 1e-3 / (reps * 4)
     del xs, ys
-    return {"gdofs": round(n / t / 1e9, 2), "us": round(t * 1e6, 2),
-            "hbm_gbs": round(2 * esize * n / t / 1e9, 1),
-            "frac_of_hbm_peak": round(2 * esize * n / t / 1e9 / HBM_PEAK_GBS, 3),
-            "pairs_rotated": pairs, "rotated_mb": round(2 * esize * n * pairs / 1e6, 1),
-            "us_one_pair_cache_resident": round(t_hot * 1e6, 2),
-            "gdofs_one_pair_cache_resident": round(n / t_hot / 1e9, 2)}
+    out = {"gdofs": round(n / t / 1e9, 2), "us": round(t * 1e6, 2),
+           "hbm_gbs": round(2 * esize * n / t / 1e9, 1),
+           "frac_of_hbm_peak": round(2 * esize * n / t / 1e9 / HBM_PEAK_GBS, 3),
+           "pairs_rotated": pairs, "rotated_mb": round(2 * esize * n * pairs / 1e6, 1),
+           "us_one_pair_cache_resident": round(t_hot * 1e6, 2),
+           "gdofs_one_pair_cache_resident": round(n / t_hot / 1e9, 2)}
+    if flops_per_dof is not None:
+        peak = FP64_PEAK_TFLOPS if esize == 8 else FP32_PEAK_TFLOPS
+        tfl = n * flops_per_dof / t / 1e12
+        out["alu"] = {"flops_per_dof": flops_per_dof, "achieved_tflops": round(tfl, 2), "peak_tflops": peak,
+                      "frac": round(tfl / peak, 3)}
+    return out
 
 
 def traffic_from_profiles(kernel_key):
@@ -406,8 +423,8 @@ def c3_block(steps):
                     "gdofs_solved": round(N / float(np.median(tt)) / 1e9, 4)}
         if prec == "f32":
             out["dofs"] = N
-            out["vmult_f64"] = time_vmult(mg, L, torch.float64)
-            out["vmult_f32"] = time_vmult(mg, L, torch.float32)
+            out["vmult_f64"] = time_vmult(mg, L, torch.float64, flops_per_dof=FLOPS_PER_DOF["stokes3d_q2q1_64"])
+            out["vmult_f32"] = time_vmult(mg, L, torch.float32, flops_per_dof=FLOPS_PER_DOF["stokes3d_q2q1_64"])
         mg.close()
         torch.cuda.synchronize()
     out["speedup_mixed_vs_f64"] = round(out["f64"]["solve_ms_median"] / out["f32_mixed"]["solve_ms_median"], 3)
@@ -581,7 +598,14 @@ def main():
                 "largest_kernel_in_solve": dom, "alu": alu}
     extra = {}
     if not args.quick:
-        extra["vmult"] = {"f64": time_vmult(mg, L, torch.float64), "f32": time_vmult(mg, L, torch.float32)}
+        fpd = FLOPS_PER_DOF.get(args.workload)
+        extra["vmult"] = {"f64": time_vmult(mg, L, torch.float64, flops_per_dof=fpd),
+                          "f32": time_vmult(mg, L, torch.float32, flops_per_dof=fpd)}
+        # FP64 vmult on every level (levels below the finest rotate over at
+        # most 64 vector pairs: from 128^2 down they stay in the Infinity Cache)
+        extra["vmult_f64_levels_gdofs"] = {
+            "x".join(str(v >> (L - l)) for v in cells(wl)[:wl["dim"]]): time_vmult(
+                mg, l, torch.float64, reps=5, max_pairs=64)["gdofs"] for l in range(L + 1)}
         x_mixed = x.clone()
         mg64 = StokesMG(precision="f64", **common)
         x64 = torch.zeros_like(x)
