@@ -10,10 +10,11 @@ FGMRES(30) preconditioned with one FP32 V-cycle per iteration: every part of
 the method (operator applications, Chebyshev-Jacobi Uzawa smoothing, residuals,
 transfers, coarse solve, cycle, outer loop) runs in each step; the diagonals
 and Chebyshev bounds are set up once before the timed region.  Each step ends
-with sixteen finest-level applications of A_hat^-1 = sigma Cheb(A, D_A, 1) in
-FP32 (the operator kernel that dominates the cycle) back to back between one
-pair of HIP events on the solver's stream, on vector pairs rotating through
-more memory than the Infinity Cache holds: the roofline entry's duration.
+with sixteen finest-level velocity updates u_hat = u + A_hat^-1 (f - A u -
+B^T p), A_hat^-1 = sigma Cheb(A, D_A, 1), in FP32 (one fused launch each: the
+operator kernel that dominates the cycle) back to back between one pair of HIP
+events on the solver's stream, on vector sets rotating through more memory
+than the Infinity Cache holds: the roofline entry's duration.
 
 value = DoFs solved per second: N * steps / (sum of the solve times of the
 timed steps; each solve call returns synchronised), GDoF/s; the roofline
@@ -496,24 +497,51 @@ def main():
     b = rhs(mg, L, wl["dim"], force=wl.get("force", "random"))
     x = torch.zeros(N, dtype=torch.float64, device="cuda")
     print(f"# setup {t_setup:.2f} s, N = {N}", file=sys.stderr, flush=True)
-    # the dominant operator kernel of the cycle: the finest-level Chebyshev
-    # application of A (k_A = 1, FP32), one launch per smg_chebyshev call.
-    # Its inputs and outputs rotate over ROT (r, out) pairs, more than the
-    # Infinity Cache holds, so every launch reads r and writes out in HBM.
+    # the dominant operator kernel of the cycle.  On 2D box levels that is the
+    # fused velocity update of the Uzawa step (the residual f - A u - B^T p and
+    # the first Chebyshev step of A_hat^-1 = sigma Cheb(A, D_A, 1) in one
+    # launch, FP32), one launch per smg_velocity_update call; where that update
+    # is more than one launch, the finest-level Chebyshev application of A,
+    # one launch per smg_chebyshev call.  Inputs and outputs rotate over ROT
+    # sets, more than the Infinity Cache holds, so every launch reads its
+    # inputs from HBM and writes its output to it.
     nu, _ = mg.sizes(L)
-    r32 = torch.tensor(synth_uniform(nu, 31), dtype=torch.float32, device="cuda")
-    rot = max(8, -(-int(2 * MALL_BYTES) // (2 * 4 * nu)))
-    rs = [r32 * (1.0 + 0.01 * i) for i in range(rot)]
-    outs = [torch.empty_like(r32) for _ in range(rot)]
+    x1 = torch.tensor(synth_uniform(N, 31), dtype=torch.float32, device="cuda")
+    b1 = torch.tensor(synth_uniform(N, 32), dtype=torch.float32, device="cuda")
+    mg.profile(True)
+    mg.velocity_update(L, x1, b1)
+    probe = mg.profile_report()
+    mg.profile(False)
+    fused = len(probe) == 1
+    if fused:
+        key = next(iter(probe))
+        set_bytes = 4 * (2 * N + nu)
+    else:
+        key = f"cheb_A/v3/blk1/f32/{'x'.join(str(v) for v in cells(wl))}"
+        set_bytes = 2 * 4 * nu
+    rot = max(8, -(-int(2 * MALL_BYTES) // set_bytes))
+    if fused:
+        ins = [(x1 * (1.0 + 0.01 * i), b1 * (1.0 - 0.01 * i)) for i in range(rot)]
+        outs = [torch.empty(nu, dtype=torch.float32, device="cuda") for _ in range(rot)]
+
+        def launch(i):
+            mg.velocity_update(L, ins[i][0], ins[i][1], outs[i])
+    else:
+        ins = [x1[:nu] * (1.0 + 0.01 * i) for i in range(rot)]
+        outs = [torch.empty(nu, dtype=torch.float32, device="cuda") for _ in range(rot)]
+
+        def launch(i):
+            mg.chebyshev(L, 0, ins[i], outs[i])
+    del x1, b1
     per_step = 16
     for _ in range(args.warmup):
         x.zero_()
         mg.solve(x, b, rtol=1e-8, maxit=300)
         for i in range(rot):
-            mg.chebyshev(L, 0, rs[i], outs[i])
+            launch(i)
     print("# warmup done", file=sys.stderr, flush=True)
     # per step: the solve (host clock; it returns synchronised), then per_step
-    # launches of the kernel back to back on per_step different vector pairs,
+    # launches of the kernel back to back on per_step different vector sets,
     # between one pair of HIP events on the solver's stream (the stream the
     # library launches on): issue-to-issue time per launch, the inter-dispatch
     # gap included
@@ -530,33 +558,54 @@ def main():
         solve_s += time.perf_counter() - s0
         ev[s][0].record(stream)
         for j in range(per_step):
-            i = (s * per_step + j) % rot
-            mg.chebyshev(L, 0, rs[i], outs[i])
+            launch((s * per_step + j) % rot)
         ev[s][1].record(stream)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     print("# timed steps done", file=sys.stderr, flush=True)
     elapsed = t1 - t0
     value = N * args.steps / solve_s / 1e9
-    cheb_ms = sum(e0.elapsed_time(e1) for e0, e1 in ev) / (args.steps * per_step)
-    # the same launch back to back on one (r, out) pair (cache-resident), for comparison
+    kern_ms_rot = sum(e0.elapsed_time(e1) for e0, e1 in ev) / (args.steps * per_step)
+    # the same launch back to back on one set (cache-resident), for comparison
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    mg.chebyshev(L, 0, rs[0], outs[0])
+    launch(0)
     e0.record(stream)
     for _ in range(16):
-        mg.chebyshev(L, 0, rs[0], outs[0])
+        launch(0)
     e1.record(stream)
     torch.cuda.synchronize()
-    cheb_hot_ms = e0.elapsed_time(e1) / 16
-    # algorithmic bytes of exactly that launch (r, D_A^-1 read, out written:
-    # the library's own accounting of the call)
-    key = f"cheb_A/v3/blk1/f32/{'x'.join(str(v) for v in cells(wl))}"
+    kern_hot_ms = e0.elapsed_time(e1) / 16
+    # algorithmic bytes of exactly that launch (the library's own accounting
+    # of the call: every vector the kernel reads or writes, once)
     mg.profile(True)
-    mg.chebyshev(L, 0, rs[0], outs[0])
+    launch(0)
     cnt1, _, nbytes1 = mg.profile_report()[key]
     mg.profile(False)
     bytes_per_launch = nbytes1 / cnt1
-    del rs, outs
+    # the plain Chebyshev application of A (the roofline kernel when the
+    # update is not fused), rotated the same way, for comparison
+    plain = None
+    if fused:
+        rs = [outs[i] for i in range(min(rot, 2 * per_step))]
+        r_outs = [ins[i][0][:nu] for i in range(len(rs))]
+        for i in range(len(rs)):
+            mg.chebyshev(L, 0, rs[i], r_outs[i])
+        e0.record(stream)
+        for i in range(len(rs)):
+            mg.chebyshev(L, 0, rs[i], r_outs[i])
+        e1.record(stream)
+        torch.cuda.synchronize()
+        pk = f"cheb_A/v3/blk1/f32/{'x'.join(str(v) for v in cells(wl))}"
+        mg.profile(True)
+        mg.chebyshev(L, 0, rs[0], r_outs[0])
+        pc, _, pb = mg.profile_report()[pk]
+        mg.profile(False)
+        p_ms = e0.elapsed_time(e1) / len(rs)
+        plain = {"kernel": pk, "avg_us": round(p_ms * 1e3, 2),
+                 "frac": round(pb / pc / (p_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                 "traffic": traffic_from_profiles(pk)}
+        del rs, r_outs
+    del ins, outs
     # per-kernel shares of one eager solve (kernel timing on), for the record
     mg.profile(True)
     x.zero_()
@@ -566,10 +615,11 @@ def main():
     kern_ms = sum(v[1] for v in rep.values())
     dom = max(rep, key=lambda k: rep[k][1])
     cnt, ms, nbytes = rep[key]
-    achieved = bytes_per_launch / (cheb_ms * 1e-3) / 1e9
+    achieved = bytes_per_launch / (kern_ms_rot * 1e-3) / 1e9
     traffic = traffic_from_profiles(key)
     # the same launch as vector-ALU work: the sum-factorised A of every cell
-    # (2D: 4 passes of (k+1)^3 FMA per component, 3D: 7 passes of (k+1)^4),
+    # (2D: 4 passes of (k+1)^3 FMA per component, 3D: 7 passes of (k+1)^4;
+    # the B^T p part of the fused residual is left out, so a lower bound),
     # against the FP32 vector peak (box cells only)
     alu = None
     if "perturb" not in wl:
@@ -579,23 +629,26 @@ def main():
             ncell *= v
         fma = d * (4 * (k + 1) ** 3 if d == 2 else 7 * (k + 1) ** 4)
         flops = 2.0 * fma * ncell
-        tfl = flops / (cheb_ms * 1e-3) / 1e12
+        tfl = flops / (kern_ms_rot * 1e-3) / 1e12
         alu = {"achieved": round(tfl, 2), "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
                "frac": round(tfl / FP32_PEAK_TFLOPS, 4), "flops_per_launch": flops}
+    set_desc = "x (u, p), b (f, g) and u_hat" if fused else "r and out"
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                "kernel": key, "avg_us": round(cheb_ms * 1e3, 2),
+                "kernel": key, "avg_us": round(kern_ms_rot * 1e3, 2),
                 "avg_us_definition": f"{args.steps} x {per_step} launches in the timed steps, {per_step} back to back "
                                      f"per step between one HIP event pair (issue-to-issue time, inter-dispatch gap "
-                                     f"included), r and out rotating over {rot} vector pairs "
-                                     f"({2 * 4 * nu * rot / 1e6:.0f} MB, more than the 256 MB Infinity Cache)",
+                                     f"included), {set_desc} rotating over {rot} vector sets "
+                                     f"({set_bytes * rot / 1e6:.0f} MB, more than the 256 MB Infinity Cache)",
                 "algorithmic_bytes_per_launch": bytes_per_launch,
-                "algorithmic_bytes_definition": "r and D_A^-1 read, out written, each once (3 x 4 B x N_u)",
-                "avg_us_one_pair_cache_resident": round(cheb_hot_ms * 1e3, 2),
-                "frac_one_pair_cache_resident": round(bytes_per_launch / (cheb_hot_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                "algorithmic_bytes_definition":
+                    "u, p, f and D_A^-1 read, u_hat written, each once ((4 N_u + N_p) x 4 B)" if fused else
+                    "r and D_A^-1 read, out written, each once (3 x 4 B x N_u)",
+                "avg_us_one_pair_cache_resident": round(kern_hot_ms * 1e3, 2),
+                "frac_one_pair_cache_resident": round(bytes_per_launch / (kern_hot_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
                 "launches_in_solve": cnt, "algorithmic_bytes_per_launch_in_solve": nbytes / cnt,
                 "share_of_solve_kernel_time": round(ms / kern_ms, 3),
-                "largest_kernel_in_solve": dom, "alu": alu}
+                "largest_kernel_in_solve": dom, "alu": alu, "plain_cheb_A_rotated": plain}
     extra = {}
     if not args.quick:
         fpd = FLOPS_PER_DOF.get(args.workload)

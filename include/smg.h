@@ -229,6 +229,17 @@ smg_status smg_set_eigs(smg_ctx *ctx, int level, double beta_A, double beta_S);
  * Sec. 3.3.1, by the three-term Chebyshev recurrence from a zero start. */
 smg_status smg_chebyshev(smg_ctx *ctx, int level, int dtype, int which, const void *r, void *out);
 
+/* uhat = u + sigma Cheb(A, D_A, k_A) (f - A u - B^T p): the velocity update
+ * that opens an inexact symmetric Uzawa step (Sec. 1, Sec. 3.3.1), on level
+ * l >= 1.  x = (u, p) and b = (f, g) are level vectors (length N, layout of
+ * smg_vmult); uhat (caller-owned device memory) has the velocity length d*Nv.
+ * Constrained velocity rows are treated as in smg_smooth.  On 2D box levels
+ * up to the two-stage fusion threshold this is the one launch the smoother
+ * uses (residual and first Chebyshev step fused), elsewhere the residual and
+ * the Chebyshev steps run as separate launches.  SMG_EINVAL for uhat
+ * aliasing x or b. */
+smg_status smg_velocity_update(smg_ctx *ctx, int level, int dtype, const void *x, const void *b, void *uhat);
+
 /* `steps` inexact symmetric Uzawa steps (Sec. 1; compact form of Sec. 3.3.1)
  * on level l >= 1, in place on x (length N) for right-hand side b. */
 smg_status smg_smooth(smg_ctx *ctx, int level, int dtype, void *x, const void *b, int steps);

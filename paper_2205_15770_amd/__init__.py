@@ -183,6 +183,18 @@ class StokesMG:
         _lib.check(self.lib.smg_chebyshev(self._h, level, _dtype_code(r), which, _ptr(r), _ptr(out)))
         return out
 
+    def velocity_update(self, level, x, b, uhat=None):
+        """uhat = u + sigma Cheb(A, D_A, k_A)(f - A u - B^T p) (the first line
+        of an inexact symmetric Uzawa step) for x = (u, p), b = (f, g)."""
+        nu, _ = self.sizes(level)
+        n = self.n_total(level)
+        self._check(x, n, "x")
+        self._check(b, n, "b")
+        uhat = self._like(x, nu) if uhat is None else uhat
+        self._check(uhat, nu, "uhat")
+        _lib.check(self.lib.smg_velocity_update(self._h, level, _dtype_code(x), _ptr(x), _ptr(b), _ptr(uhat)))
+        return uhat
+
     def smooth(self, level, x, b, steps=1):
         n = self.n_total(level)
         self._check(x, n, "x")

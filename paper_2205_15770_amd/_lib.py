@@ -21,7 +21,7 @@ STATUS_NAMES = {0: "SMG_OK", -1: "SMG_EINVAL", -2: "SMG_ENOMEM", -3: "SMG_EDEVIC
 
 EXPORTS = ["smg_desc_default", "smg_create", "smg_destroy", "smg_sizes", "smg_set_stream",
            "smg_vmult", "smg_vmult_noalloc", "smg_residual", "smg_apply_block", "smg_lift_dirichlet", "smg_insert_dirichlet", "smg_get_diagonal", "smg_get_eigs",
-           "smg_set_eigs", "smg_chebyshev", "smg_smooth", "smg_restrict", "smg_prolongate_add",
+           "smg_set_eigs", "smg_chebyshev", "smg_velocity_update", "smg_smooth", "smg_restrict", "smg_prolongate_add",
            "smg_coarse_solve", "smg_vcycle", "smg_solve", "smg_solve_stationary", "smg_batch_create",
            "smg_batch_destroy", "smg_batch_solve", "smg_batch_precondition", "smg_batch_info", "smg_batch_autotune",
            "smg_node_coordinates", "smg_gradient", "smg_pressure_mean_adjoint", "smg_profile", "smg_profile_report",
@@ -84,6 +84,7 @@ def load(path=LIB_PATH):
         "smg_get_eigs": (I, [P, I, dp, dp]),
         "smg_set_eigs": (I, [P, I, D, D]),
         "smg_chebyshev": (I, [P, I, I, I, P, P]),
+        "smg_velocity_update": (I, [P, I, I, P, P, P]),
         "smg_smooth": (I, [P, I, I, P, P, I]),
         "smg_restrict": (I, [P, I, I, P, P]),
         "smg_prolongate_add": (I, [P, I, I, P, P]),

@@ -96,6 +96,7 @@ class EngineBase {
   virtual void lift_dirichlet(int l, int dt, const void *ud, void *b) = 0;
   virtual void insert_dirichlet(int l, int dt, const void *ud, void *x) = 0;
   virtual void chebyshev(int l, int dt, int which, const void *r, void *out) = 0;
+  virtual void velocity_update(int l, int dt, const void *x, const void *b, void *uhat) = 0;
   virtual void smooth(int l, int dt, void *x, const void *b, int steps) = 0;
   virtual void restrict_(int lf, int dt, const void *rf, void *rc) = 0;
   virtual void prolongate_add(int lf, int dt, const void *wc, void *xf) = 0;

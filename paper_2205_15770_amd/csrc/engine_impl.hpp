@@ -814,9 +814,16 @@ class EngineT : public EngineBase {
         char key[160];
         std::snprintf(key, sizeof(key), "%s+cheb_A/v%d/fused/%s/%dx%dx%d", Op1::NAME, k == 1 ? 3 : 1,
                       std::is_same<T, double>::value ? "f64" : "f32", g.n[0], g.n[1], g.n[2]);
+        // algorithmic bytes, every vector read or written once: the producer's
+        // inputs (residual: u, p, f; B^T d: d), then D_A^-1, the base unless
+        // it is the residual's u, and the output (k = 1), or the recurrence's
+        // r, x, d and D_A^-1 (k > 1)
         const double nu = (double)(DIM * g.Nv), np = (double)g.Np;
-        const double bytes = sizeof(T) * ((std::is_same<Op1, OpResidual<T>>::value ? 3 * nu + np : np) +
-                                          nu * (k == 1 ? (base ? 3 : 2) : 4));
+        constexpr bool RES = std::is_same<Op1, OpResidual<T>>::value;
+        bool base_read = base != nullptr;
+        if constexpr (RES) base_read = base_read && (const void *)base != (const void *)op1.xu;
+        const double bytes =
+            sizeof(T) * ((RES ? 2 * nu + np : np) + nu * (k == 1 ? (base_read ? 3 : 2) : 4));
         prof.push_back(ProfRec{key, ea, eb, bytes});
       }
       if (k > 1) cheb_A<T>(l, nullptr, base, out, s, 1);
@@ -920,22 +927,32 @@ class EngineT : public EngineBase {
   //   u_hat = u + A_hat^-1 (f - A u - B^T p)
   //   dp    = S_hat^-1 (B u_hat - C p - g),   p <- p + dp
   //   u     = u_hat - A_hat^-1 B^T dp
+  // velocity_update_t forms the first line (zero_init: u = 0, p = 0, the
+  // residual is f), uzawa_step the whole step.
+  template <typename T>
+  void velocity_update_t(int l, const T *x, const T *b, T *uhat, bool zero_init = false) {
+    Work<T> &W = work<T>(l);
+    const int64_t nu = lv[l].Nu;
+    const T *u = x, *p = x + nu, *f = b;
+    if (zero_init) {
+      cheb_A<T>(l, f, nullptr, uhat, sigma);
+    } else {
+      const OpResidual<T> op{u, p, f, nullptr, W.ru, nullptr};
+      if (!cheb_A_fused<T>(l, op, u, uhat, sigma)) {
+        tile<T, BLK_A | BLK_BT>(geom<T>(l), op);
+        cheb_A<T>(l, W.ru, u, uhat, sigma);
+      }
+    }
+  }
+
   template <typename T>
   void uzawa_step(int l, T *x, const T *b, bool zero_init) {
     Work<T> &W = work<T>(l);
     const int64_t nu = lv[l].Nu;
     T *u = x, *p = x + nu;
-    const T *f = b, *gp = b + nu;
+    const T *gp = b + nu;
     auto g = geom<T>(l);
-    if (zero_init) {
-      cheb_A<T>(l, f, nullptr, W.uhat, sigma);
-    } else {
-      const OpResidual<T> op{u, p, f, nullptr, W.ru, nullptr};
-      if (!cheb_A_fused<T>(l, op, u, W.uhat, sigma)) {
-        tile<T, BLK_A | BLK_BT>(g, op);
-        cheb_A<T>(l, W.ru, u, W.uhat, sigma);
-      }
-    }
+    velocity_update_t<T>(l, x, b, W.uhat, zero_init);
     if (uzawa_tail_fused3<T>(l, u, p, gp)) return;
     OpDivResidual<T> od{W.uhat, p, gp, W.rp};
     if (has_c()) tile<T, BLK_B | BLK_C>(g, od);
@@ -1672,6 +1689,10 @@ class EngineT : public EngineBase {
     else
       SMG_DISPATCH(dt, cheb_S<double>(l, (const double *)r, (double *)out, nullptr),
                    cheb_S<float>(l, (const float *)r, (float *)out, nullptr));
+  }
+  void velocity_update(int l, int dt, const void *x, const void *b, void *uhat) override {
+    SMG_DISPATCH(dt, velocity_update_t<double>(l, (const double *)x, (const double *)b, (double *)uhat),
+                 velocity_update_t<float>(l, (const float *)x, (const float *)b, (float *)uhat));
   }
   void smooth(int l, int dt, void *x, const void *b, int steps) override {
     SMG_DISPATCH(dt, smooth_t<double>(l, (double *)x, (const double *)b, steps, false),

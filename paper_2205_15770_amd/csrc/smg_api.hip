@@ -369,6 +369,15 @@ smg_status smg_chebyshev(smg_ctx *ctx, int level, int dtype, int which, const vo
   SMG_TRY(ctx->eng->chebyshev(level, dtype, which, r, out));
 }
 
+smg_status smg_velocity_update(smg_ctx *ctx, int level, int dtype, const void *x, const void *b, void *uhat) {
+  smg_status s = check_level(ctx, level, 1);
+  if (s == SMG_OK) s = check_dtype(dtype);
+  if (s == SMG_OK) s = check_ptrs({x, b, uhat});
+  if (s != SMG_OK) return s;
+  if (uhat == x || uhat == b) return fail(SMG_EINVAL, "uhat must not alias x or b");
+  SMG_TRY(ctx->eng->velocity_update(level, dtype, x, b, uhat));
+}
+
 smg_status smg_smooth(smg_ctx *ctx, int level, int dtype, void *x, const void *b, int steps) {
   smg_status s = check_level(ctx, level, 1);
   if (s == SMG_OK) s = check_dtype(dtype);

@@ -230,6 +230,37 @@ def test_chebyshev_and_smoother(name, kA, kS):
 
 
 @pytest.mark.parametrize("name", list(CONFIGS))
+@pytest.mark.parametrize("kA", [0, 1, 3])
+def test_velocity_update(name, kA):
+    """u_hat = u + A_hat^-1 (f - A u - B^T p), the first line of the Uzawa
+    step (Sec. 1), against the oracle's assembled blocks; the 2D configs
+    without the _plain suffix take the fused residual + Chebyshev launch."""
+    ora, gpu = _setup(name, kA=kA)
+    _inject_betas(ora, gpu)
+    for l in (ora.L, 1):
+        S = ora.smoothers[l]
+        nu = S.nu
+        n = ora.levels[l].K.shape[0]
+        x = si.uniform(n, 25 + l)
+        b = si.uniform(n, 26 + l)
+        ref = x[:nu] + S.Ainv(b[:nu] - S.A @ x[:nu] - S.B.T @ x[nu:])
+        assert _rel(gpu.velocity_update(l, _dev(x), _dev(b)), ref) < 1e-10
+        out32 = gpu.velocity_update(l, _dev(x, torch.float32), _dev(b, torch.float32))
+        assert out32.dtype == torch.float32
+        assert _rel(out32, ref) < 1e-4
+
+
+def test_velocity_update_rejects_aliasing():
+    from paper_2205_15770_amd import _lib
+    ora, gpu = _setup("2d_k2")
+    n = ora.levels[ora.L].K.shape[0]
+    nu = ora.smoothers[ora.L].nu
+    x = _dev(si.uniform(n, 27))
+    with pytest.raises(_lib.SmgError):
+        gpu.velocity_update(ora.L, x, _dev(si.uniform(n, 28)), x[:nu])
+
+
+@pytest.mark.parametrize("name", list(CONFIGS))
 def test_transfers(name):
     ora, gpu = _setup(name)
     for l in range(1, ora.L + 1):
