@@ -39,6 +39,84 @@ struct Geo2 {
   T sB[2];
 };
 
+// The cell products of one cell (lane): yu_c = (A u_c | M u_c) + B_c^T p for
+// the velocity fields selected by FIELD, yp = B u (+/- C p) for the pressure
+// (FIELD -1: every output field of the block, 0 / 1: velocity component
+// 0 / 1 only, 2: pressure only).  Inputs are masked already.
+template <int K, typename T, int BLK, int FIELD>
+__device__ __forceinline__ void cell2d_products(const Geo2<T> &g, const T mu, const T (&u)[2][1][K + 1][K + 1],
+                                                const T (&p)[1][K][K], T (&yu)[2][1][K + 1][K + 1],
+                                                T (&yp)[1][K][K]) {
+  constexpr int NV = K + 1, NP = K;
+  constexpr cfe::TabT<K, T> R = cfe::make_tab_t<K, T>();
+  constexpr bool ALL_U = (BLK & (BLK_A | BLK_MASS | BLK_BT)) != 0;
+  constexpr bool OUT_P = (BLK & (BLK_B | BLK_C)) != 0 && (FIELD == -1 || FIELD == 2);
+  constexpr bool DU[2] = {ALL_U && (FIELD == -1 || FIELD == 0), ALL_U && (FIELD == -1 || FIELD == 1)};
+  if constexpr ((BLK & BLK_A) != 0) {
+    T X[NV][NV];
+    const T axk = mu * g.sKx, bxm = g.gr * g.sM;
+#pragma unroll
+    for (int i = 0; i < NV; ++i)
+#pragma unroll
+      for (int j = 0; j < NV; ++j) X[i][j] = axk * R.Kr[i][j] + bxm * R.Mr[i][j];
+    const T sy = mu * g.sKy;
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+      if (!DU[c]) continue;
+      T t[1][NV][NV];
+      pass_y<false, false>(R.Mr, u[c], t, T(1));
+      pass_x<false, false>(X, t, yu[c], T(1));
+      pass_y<false, false>(R.Kr, u[c], t, T(1));
+      pass_x<false, true>(R.Mr, t, yu[c], sy);
+    }
+  } else if constexpr ((BLK & BLK_MASS) != 0) {
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+      if (!DU[c]) continue;
+      T t[1][NV][NV];
+      pass_y<false, false>(R.Mr, u[c], t, T(1));
+      pass_x<false, false>(R.Mr, t, yu[c], g.sM);
+    }
+  }
+  if constexpr ((BLK & BLK_BT) != 0) {
+    constexpr bool ACC = (BLK & (BLK_A | BLK_MASS)) != 0;
+    if constexpr (DU[0]) {
+      T s[1][NV][NP];
+      pass_y<true, false>(R.Nr, p, s, T(1));
+      pass_x<true, ACC>(R.Gr, s, yu[0], -g.sB[0]);
+    }
+    if constexpr (DU[1]) {
+      T s2[1][NP][NV];
+      pass_x<true, false>(R.Nr, p, s2, T(1));
+      pass_y<true, ACC>(R.Gr, s2, yu[1], -g.sB[1]);
+    }
+  } else if constexpr (!ALL_U) {
+#pragma unroll
+    for (int c = 0; c < 2; ++c)
+#pragma unroll
+      for (int y = 0; y < NV; ++y)
+#pragma unroll
+        for (int x = 0; x < NV; ++x) yu[c][0][y][x] = 0;
+  }
+  if constexpr (OUT_P) {
+    if constexpr ((BLK & BLK_B) != 0) {
+      T w[1][NV][NP];
+      pass_x<false, false>(R.Gr, u[0], w, T(1));
+      pass_y<false, false>(R.Nr, w, yp, -g.sB[0]);
+      pass_x<false, false>(R.Nr, u[1], w, T(1));
+      pass_y<false, true>(R.Gr, w, yp, -g.sB[1]);
+    }
+    if constexpr ((BLK & BLK_C) != 0) {
+      constexpr bool ACC = (BLK & BLK_B) != 0;
+      const T sc = ((BLK & BLK_CPLUS) ? g.cp : -g.cp) * g.sM;
+      T q[1][NP][NP];
+      pass_x<false, false>(R.Mpr, p, q, T(1));
+      pass_y<false, ACC>(R.Mpr, q, yp, sc);
+    }
+  }
+
+}
+
 // One tile; FIELD = -1: every output field of the block, 0 / 1: velocity
 // component 0 / 1 only, 2: pressure only (the split form for small levels,
 // where a wave's instruction count is its latency).
@@ -138,68 +216,7 @@ __device__ __forceinline__ void wave2d_tile(const Geo2<T> &g, const Op &op, int 
 
   // 3. cell matrices
   T yu[2][1][NV][NV], yp[1][NP][NP];
-  if constexpr ((BLK & BLK_A) != 0) {
-    T X[NV][NV];
-    const T axk = mu * g.sKx, bxm = g.gr * g.sM;
-#pragma unroll
-    for (int i = 0; i < NV; ++i)
-#pragma unroll
-      for (int j = 0; j < NV; ++j) X[i][j] = axk * R.Kr[i][j] + bxm * R.Mr[i][j];
-    const T sy = mu * g.sKy;
-#pragma unroll
-    for (int c = 0; c < 2; ++c) {
-      if (!DU[c]) continue;
-      T t[1][NV][NV];
-      pass_y<false, false>(R.Mr, u[c], t, T(1));
-      pass_x<false, false>(X, t, yu[c], T(1));
-      pass_y<false, false>(R.Kr, u[c], t, T(1));
-      pass_x<false, true>(R.Mr, t, yu[c], sy);
-    }
-  } else if constexpr ((BLK & BLK_MASS) != 0) {
-#pragma unroll
-    for (int c = 0; c < 2; ++c) {
-      if (!DU[c]) continue;
-      T t[1][NV][NV];
-      pass_y<false, false>(R.Mr, u[c], t, T(1));
-      pass_x<false, false>(R.Mr, t, yu[c], g.sM);
-    }
-  }
-  if constexpr ((BLK & BLK_BT) != 0) {
-    constexpr bool ACC = (BLK & (BLK_A | BLK_MASS)) != 0;
-    if constexpr (DU[0]) {
-      T s[1][NV][NP];
-      pass_y<true, false>(R.Nr, p, s, T(1));
-      pass_x<true, ACC>(R.Gr, s, yu[0], -g.sB[0]);
-    }
-    if constexpr (DU[1]) {
-      T s2[1][NP][NV];
-      pass_x<true, false>(R.Nr, p, s2, T(1));
-      pass_y<true, ACC>(R.Gr, s2, yu[1], -g.sB[1]);
-    }
-  } else if constexpr (!ALL_U) {
-#pragma unroll
-    for (int c = 0; c < 2; ++c)
-#pragma unroll
-      for (int y = 0; y < NV; ++y)
-#pragma unroll
-        for (int x = 0; x < NV; ++x) yu[c][0][y][x] = 0;
-  }
-  if constexpr (OUT_P) {
-    if constexpr ((BLK & BLK_B) != 0) {
-      T w[1][NV][NP];
-      pass_x<false, false>(R.Gr, u[0], w, T(1));
-      pass_y<false, false>(R.Nr, w, yp, -g.sB[0]);
-      pass_x<false, false>(R.Nr, u[1], w, T(1));
-      pass_y<false, true>(R.Gr, w, yp, -g.sB[1]);
-    }
-    if constexpr ((BLK & BLK_C) != 0) {
-      constexpr bool ACC = (BLK & BLK_B) != 0;
-      const T sc = ((BLK & BLK_CPLUS) ? g.cp : -g.cp) * g.sM;
-      T q[1][NP][NP];
-      pass_x<false, false>(R.Mpr, p, q, T(1));
-      pass_y<false, ACC>(R.Mpr, q, yp, sc);
-    }
-  }
+  cell2d_products<K, T, BLK, FIELD>(g, mu, u, p, yu, yp);
 
   // 4. hand-over to the right (lane + 1) and upper (lane + 8) neighbours
 #pragma unroll
@@ -340,26 +357,141 @@ __device__ __forceinline__ void gather_high_faces(T (&v)[N][N], bool bxh, bool b
 // rows of v take the values the separate launches would store (r = f - u for
 // the residual, 0 for q), so the result equals the two-launch sequence.
 // One wave per (tile, velocity component).
+// ---------------------------------------------------------------------------
+// Workgroups of WX x WY waves, each an 8 x 8 block of cells (one per lane),
+// the blocks side by side without overlap.  The two helpers below do what
+// hand_over_xy and gather_high_faces do inside a wave, across the whole
+// workgroup: values that cross a wave boundary go through LDS.  Every wave of
+// the workgroup calls them (they hold barriers).
+template <int WX, int WY, int N, typename T>
+struct WgFaces {
+  T x[WX * WY * 8 * N];    // x step of a hand-over
+  T y[WX * WY * 8 * N];    // y step of a hand-over
+  T gx[WX * WY * 8 * N];   // published left columns (gather)
+  T gy[WX * WY * 8 * N];   // published bottom rows (gather)
+};
+
+template <int WX, int WY, typename T, int N>
+__device__ __forceinline__ void wg_hand_over(T (&y)[1][N][N], int lcx, int lcy, int wx, int wy, bool last_x,
+                                             bool last_y, WgFaces<WX, WY, N, T> &sh) {
+  constexpr int TX = 8;
+  const int w = wx + WX * wy;
+  T r[N];
+#pragma unroll
+  for (int j = 0; j < N; ++j) r[j] = __shfl_up(y[0][j][N - 1], 1, TX);
+  if (lcx == TX - 1 && wx < WX - 1) {
+#pragma unroll
+    for (int j = 0; j < N; ++j) sh.x[(w * TX + lcy) * N + j] = y[0][j][N - 1];
+  }
+  __syncthreads();
+  if (lcx == 0 && wx > 0) {
+#pragma unroll
+    for (int j = 0; j < N; ++j) r[j] = sh.x[((w - 1) * TX + lcy) * N + j];
+  }
+  const bool from_left = lcx > 0 || wx > 0;
+#pragma unroll
+  for (int j = 0; j < N; ++j) {
+    if (from_left) y[0][j][0] += r[j];
+    if (!last_x) y[0][j][N - 1] = 0;
+  }
+#pragma unroll
+  for (int i = 0; i < N; ++i) r[i] = __shfl_up(y[0][N - 1][i], TX, 64);
+  if (lcy == TX - 1 && wy < WY - 1) {
+#pragma unroll
+    for (int i = 0; i < N; ++i) sh.y[(w * TX + lcx) * N + i] = y[0][N - 1][i];
+  }
+  __syncthreads();
+  if (lcy == 0 && wy > 0) {
+#pragma unroll
+    for (int i = 0; i < N; ++i) r[i] = sh.y[((w - WX) * TX + lcx) * N + i];
+  }
+  const bool from_below = lcy > 0 || wy > 0;
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+    if (from_below) y[0][0][i] += r[i];
+    if (!last_y) y[0][N - 1][i] = 0;
+  }
+}
+
+template <int WX, int WY, typename T, int N>
+__device__ __forceinline__ void wg_gather_high_faces(T (&v)[N][N], int lcx, int lcy, int wx, int wy, bool bxh,
+                                                     bool byh, WgFaces<WX, WY, N, T> &sh) {
+  constexpr int E = N - 1, TX = 8;
+  const int w = wx + WX * wy;
+  // publish the left column of the lanes at lcx = 0 and the bottom row of the
+  // lanes at lcy = 0
+  if (lcx == 0) {
+#pragma unroll
+    for (int j = 0; j < N; ++j) sh.gx[(w * TX + lcy) * N + j] = v[j][0];
+  }
+  if (lcy == 0) {
+#pragma unroll
+    for (int i = 0; i < N; ++i) sh.gy[(w * TX + lcx) * N + i] = v[0][i];
+  }
+  T colE[E], rowE[E];
+#pragma unroll
+  for (int j = 0; j < E; ++j) colE[j] = __shfl_down(v[j][0], 1, 64);
+#pragma unroll
+  for (int i = 0; i < E; ++i) rowE[i] = __shfl_down(v[0][i], TX, 64);
+  T c9 = __shfl_down(v[0][0], TX + 1, 64);   // (0, 0) of the upper-right cell
+  T c8 = __shfl_down(v[0][E], TX, 64);       // (E, 0) of the upper cell
+  T c1 = __shfl_down(v[E][0], 1, 64);        // (0, E) of the right cell
+  __syncthreads();
+  const bool rx = lcx == TX - 1 && wx < WX - 1, ry = lcy == TX - 1 && wy < WY - 1;
+  const int wr = w + 1, wu = w + WX;
+  if (rx) {
+#pragma unroll
+    for (int j = 0; j < E; ++j) colE[j] = sh.gx[(wr * TX + lcy) * N + j];
+    c1 = sh.gx[(wr * TX + lcy) * N + E];
+  }
+  if (ry) {
+#pragma unroll
+    for (int i = 0; i < E; ++i) rowE[i] = sh.gy[(wu * TX + lcx) * N + i];
+    c8 = sh.gy[(wu * TX + lcx) * N + E];
+  }
+  if (lcx == TX - 1 && lcy < TX - 1 && rx) c9 = sh.gx[(wr * TX + lcy + 1) * N];
+  else if (lcy == TX - 1 && lcx < TX - 1 && ry) c9 = sh.gy[(wu * TX + lcx + 1) * N];
+  else if (lcx == TX - 1 && lcy == TX - 1 && rx && ry) c9 = sh.gx[((wu + 1) * TX) * N];
+  if (!bxh) {
+#pragma unroll
+    for (int j = 0; j < E; ++j) v[j][E] = colE[j];
+  }
+  if (!byh) {
+#pragma unroll
+    for (int i = 0; i < E; ++i) v[E][i] = rowE[i];
+  }
+  if (!bxh && !byh) v[E][E] = c9;
+  else if (bxh && !byh) v[E][E] = c8;
+  else if (!bxh && byh) v[E][E] = c1;
+}
+
 template <class Op>
 struct is_residual_op : std::false_type {};
 template <typename T>
 struct is_residual_op<OpResidual<T>> : std::true_type {};
 
-template <int K, typename T, class Op1, bool LAST>
+template <int K, typename T, class Op1, bool LAST, int WX = 1, int WY = 1>
 __device__ __forceinline__ void wave2d_fused_body(const Geo2<T> &g, const Op1 &op1, const OpChebA<T, true, LAST> &op2,
-                                                  const int bb) {
-  constexpr int NV = K + 1, NP = K, TX = 8, OWN = TX - 3;
+                                                  const int bb, WgFaces<WX, WY, K + 1, T> *sh = nullptr) {
+  constexpr int NV = K + 1, NP = K, TX = 8;
+  constexpr int CXW = TX * WX, CYW = TX * WY;       // cells of the tile
+  constexpr int OWNX = CXW - 3, OWNY = CYW - 3;     // owned cells
+  constexpr bool WG = WX * WY > 1;
   constexpr uint32_t ST = sizeof(T);
   constexpr cfe::TabT<K, T> R = cfe::make_tab_t<K, T>();
   constexpr bool RESID = is_residual_op<Op1>::value;
 
   const int c = bb % 2, b = bb / 2;
   const int tx = b % g.tiles[0], ty = b / g.tiles[0];
-  const int lcx = threadIdx.x % TX, lcy = threadIdx.x / TX;
-  const int gcx = tx * OWN - 2 + lcx, gcy = ty * OWN - 2 + lcy;
+  const int lane = threadIdx.x % 64;
+  const int wv = WG ? __builtin_amdgcn_readfirstlane((int)threadIdx.x / 64) : 0;
+  const int wx = wv % WX, wy = wv / WX;
+  const int lcx = lane % TX, lcy = lane / TX;
+  const int lx = TX * wx + lcx, ly = TX * wy + lcy;   // cell of the tile
+  const int gcx = tx * OWNX - 2 + lx, gcy = ty * OWNY - 2 + ly;
   const bool active = gcx >= 0 && gcx < g.n[0] && gcy >= 0 && gcy < g.n[1];
-  const bool valid2 = active && lcx >= 1 && lcx <= TX - 2 && lcy >= 1 && lcy <= TX - 2;
-  const bool owner = active && lcx >= 2 && lcx <= TX - 2 && lcy >= 2 && lcy <= TX - 2;
+  const bool valid2 = active && lx >= 1 && lx <= CXW - 2 && ly >= 1 && ly <= CYW - 2;
+  const bool owner = active && lx >= 2 && lx <= CXW - 2 && ly >= 2 && ly <= CYW - 2;
   const bool bxl = gcx == 0, bxh = gcx == g.n[0] - 1, byl = gcy == 0, byh = gcy == g.n[1] - 1;
   const int ax = gcx < 0 ? 0 : (gcx >= g.n[0] ? g.n[0] - 1 : gcx);
   const int ay = gcy < 0 ? 0 : (gcy >= g.n[1] ? g.n[1] - 1 : gcy);
@@ -443,7 +575,8 @@ __device__ __forceinline__ void wave2d_fused_body(const Geo2<T> &g, const Op1 &o
       pass_y<true, ACC>(R.Gr, s2, t1, -g.sB[1]);
     }
   }
-  hand_over_xy<TX>(t1, lcx, lcy, bxh, byh);
+  if constexpr (WG) wg_hand_over<WX, WY>(t1, lcx, lcy, wx, wy, bxh, byh, *sh);
+  else hand_over_xy<TX>(t1, lcx, lcy, bxh, byh);
   // v on the nodes this lane holds completely
   T v[NV][NV];
 #pragma unroll
@@ -455,7 +588,8 @@ __device__ __forceinline__ void wave2d_fused_body(const Geo2<T> &g, const Op1 &o
       v[y][x] = vbc(x, y) ? bc_v : free_v;
     }
   // 3. right / upper faces and corner from the owners (lane + 1, + 8, + 9)
-  gather_high_faces<TX>(v, bxh, byh);
+  if constexpr (WG) wg_gather_high_faces<WX, WY>(v, lcx, lcy, wx, wy, bxh, byh, *sh);
+  else gather_high_faces<TX>(v, bxh, byh);
   // 4. second stage: t2 = A d0, d0 = D^-1 v / theta (inputs of the valid lanes only)
   T d0[1][NV][NV], t2[1][NV][NV];
 #pragma unroll
@@ -466,7 +600,8 @@ __device__ __forceinline__ void wave2d_fused_body(const Geo2<T> &g, const Op1 &o
       d0[0][y][x] = (valid2 && !vbc(x, y)) ? d : T(0);
     }
   apply_A(d0, t2);
-  hand_over_xy<TX>(t2, lcx, lcy, bxh, byh);
+  if constexpr (WG) wg_hand_over<WX, WY>(t2, lcx, lcy, wx, wy, bxh, byh, *sh);
+  else hand_over_xy<TX>(t2, lcx, lcy, bxh, byh);
 
   // 5. owned nodes through the Chebyshev epilogue
   if (!owner) return;
@@ -761,6 +896,16 @@ wave2d_fused_kernel(const Geo2<T> g, const Op1 op1, const OpChebA<T, true, LAST>
   wave2d_fused_body<K, T, Op1, LAST>(g, op1, op2, xcd_contiguous_tile(blockIdx.x, gridDim.x));
 }
 
+// The same two stages on a workgroup of WX x WY waves: one tile of 8 WX x
+// 8 WY cells per (workgroup, velocity component) owns (8 WX - 3) x (8 WY - 3)
+// cells; faces between the waves go through LDS instead of halo cells.
+template <int K, typename T, class Op1, bool LAST, int WX, int WY>
+__global__ void __launch_bounds__(64 * WX * WY)
+wg2d_fused_kernel(const Geo2<T> g, const Op1 op1, const OpChebA<T, true, LAST> op2) {
+  __shared__ WgFaces<WX, WY, K + 1, T> sh;
+  wave2d_fused_body<K, T, Op1, LAST, WX, WY>(g, op1, op2, xcd_contiguous_tile(blockIdx.x, gridDim.x), &sh);
+}
+
 template <int K, typename T, int MODE, bool LAST>
 __global__ void __launch_bounds__(64)
 wave2d_fused3_kernel(const Geo2<T> g, const Fuse3P<T> P, const OpChebA<T, true, LAST> op2) {
@@ -806,6 +951,18 @@ struct LFused2 {
   Op1 op1;
   OpChebA<T, true, LAST> op2;
   __device__ void run(int b, int nb) const { wave2d_fused_body<K, T, Op1, LAST>(g, op1, op2, xcd_contiguous_tile(b, nb)); }
+};
+
+template <int K, typename T, class Op1, bool LAST, int WX, int WY>
+struct LFused2Wg {
+  static constexpr int THREADS = 64 * WX * WY;
+  Geo2<T> g;
+  Op1 op1;
+  OpChebA<T, true, LAST> op2;
+  __device__ void run(int b, int nb) const {
+    __shared__ WgFaces<WX, WY, K + 1, T> sh;
+    wave2d_fused_body<K, T, Op1, LAST, WX, WY>(g, op1, op2, xcd_contiguous_tile(b, nb), &sh);
+  }
 };
 
 template <int K, typename T, int MODE, bool LAST>

@@ -81,6 +81,21 @@ inline int split2d_max_n_from_env() {
   return e != nullptr ? std::atoi(e) : 512;
 }
 
+// Smallest 2D level (cells per direction) whose fused two-stage launches run
+// on workgroups of several waves that exchange faces through LDS instead of
+// one wave per tile (the tile's halo shrinks from 39 of 64 cells to 87 of
+// 256); SMG_WGF2D_MIN_N overrides it (0: never) and SMG_WGF2D_SHAPE picks the
+// waves per workgroup (22: 2 x 2, 42: 4 x 2, 44: 4 x 4).
+inline int wgf2d_min_n_from_env() {
+  const char *e = std::getenv("SMG_WGF2D_MIN_N");
+  return e != nullptr ? std::atoi(e) : 512;
+}
+inline int wgf2d_shape_from_env() {
+  const char *e = std::getenv("SMG_WGF2D_SHAPE");
+  const int v = e != nullptr ? std::atoi(e) : 22;
+  return (v == 42 || v == 22 || v == 44) ? v : 22;
+}
+
 // Lanczos (Algorithm 2 asks for a close approximation of lambda_max): steps,
 // safety factor and SplitMix64 seeds of the start vectors.
 constexpr int LANCZOS_STEPS = 30;
@@ -125,6 +140,8 @@ class EngineT : public EngineBase {
   bool gen_op = false;                       // operator through the vertex-given cell kernel
   int block3d_max_n = block3d_max_n_from_env();
   int split2d_max_n = split2d_max_n_from_env();
+  int wgf2d_min_n = wgf2d_min_n_from_env();
+  int wgf2d_shape = wgf2d_shape_from_env();
   int gen3_lines = gen3_lines_from_env();
   int sweep_waves = sweep_waves_from_env();
   int fuse2d_max_n = fuse2d_max_n_from_env();
@@ -800,7 +817,12 @@ class EngineT : public EngineBase {
         eb = next_event();
         SMG_HIP(hipEventRecord(ea, stream));
       }
-      if (rec) {
+      const bool wg = wgf2d_min_n > 0 && std::max(lv[l].n[0], lv[l].n[1]) >= wgf2d_min_n;
+      if (wg) {
+        if (wgf2d_shape == 22) fused_wg_launch<T, Op1, 2, 2>(g, op1, o, k);
+        else if (wgf2d_shape == 44) fused_wg_launch<T, Op1, 4, 4>(g, op1, o, k);
+        else fused_wg_launch<T, Op1, 4, 2>(g, op1, o, k);
+      } else if (rec) {
         if (k == 1) rec_add(LFused2<K, T, Op1, true>{g2, op1, o}, nb);
         else rec_add(LFused2<K, T, Op1, false>{g2, op1, cast_op<OpChebA<T, true, false>>(o)}, nb);
       } else if (k == 1)
@@ -812,7 +834,7 @@ class EngineT : public EngineBase {
       if (profiling) {
         SMG_HIP(hipEventRecord(eb, stream));
         char key[160];
-        std::snprintf(key, sizeof(key), "%s+cheb_A/v%d/fused/%s/%dx%dx%d", Op1::NAME, k == 1 ? 3 : 1,
+        std::snprintf(key, sizeof(key), "%s+cheb_A/v%d/%s/%s/%dx%dx%d", Op1::NAME, k == 1 ? 3 : 1, wg ? "fusedwg" : "fused",
                       std::is_same<T, double>::value ? "f64" : "f32", g.n[0], g.n[1], g.n[2]);
         // algorithmic bytes, every vector read or written once: the producer's
         // inputs (residual: u, p, f; B^T d: d), then D_A^-1, the base unless
@@ -828,6 +850,25 @@ class EngineT : public EngineBase {
       }
       if (k > 1) cheb_A<T>(l, nullptr, base, out, s, 1);
       return true;
+    }
+  }
+
+  // The fused pair on workgroups of WX x WY waves (2D box levels).
+  template <typename T, class Op1, int WX, int WY>
+  void fused_wg_launch(const LevelGeom<T, DIM, K> &g, const Op1 &op1, const OpChebA<T, true, true> &o, int k) {
+    Geo2<T> g2 = geo2<T>(g, 5);
+    g2.tiles[0] = (g.n[0] + 8 * WX - 4) / (8 * WX - 3);
+    g2.tiles[1] = (g.n[1] + 8 * WY - 4) / (8 * WY - 3);
+    const unsigned nb = (unsigned)(g2.tiles[0] * g2.tiles[1] * 2);
+    if (rec) {
+      if (k == 1) rec_add(LFused2Wg<K, T, Op1, true, WX, WY>{g2, op1, o}, nb);
+      else rec_add(LFused2Wg<K, T, Op1, false, WX, WY>{g2, op1, cast_op<OpChebA<T, true, false>>(o)}, nb);
+    } else if (k == 1) {
+      hipLaunchKernelGGL((wg2d_fused_kernel<K, T, Op1, true, WX, WY>), dim3(nb), dim3(64 * WX * WY), 0, stream, g2,
+                         op1, o);
+    } else {
+      hipLaunchKernelGGL((wg2d_fused_kernel<K, T, Op1, false, WX, WY>), dim3(nb), dim3(64 * WX * WY), 0, stream,
+                         g2, op1, cast_op<OpChebA<T, true, false>>(o));
     }
   }
 

@@ -48,6 +48,18 @@ CONFIGS = {
                         env={"SMG_SPLIT2D_MAX_N": "0", "SMG_FUSE2D_MAX_N": "0", "SMG_FUSE3_2D_MAX_N": "0"}),
     "2d_k3_plain": dict(dim=2, k=3, n_coarse=(3, 2), levels=4,
                         env={"SMG_SPLIT2D_MAX_N": "0", "SMG_FUSE2D_MAX_N": "0", "SMG_FUSE3_2D_MAX_N": "0"}),
+    # large 2D levels run the fused producer + Chebyshev launches on
+    # workgroups of several waves that exchange faces through LDS; the same
+    # small meshes with that on every level (three-stage launches off, so that
+    # every fused pair takes it), in its three shapes:
+    "2d_k2_wgf": dict(dim=2, k=2, n_coarse=(5, 3), levels=4,
+                      env={"SMG_WGF2D_MIN_N": "1", "SMG_FUSE3_2D_MAX_N": "0"}),
+    "2d_k3_wgf": dict(dim=2, k=3, n_coarse=(3, 2), levels=4,
+                      env={"SMG_WGF2D_MIN_N": "1", "SMG_FUSE3_2D_MAX_N": "0"}),
+    "2d_k2_wgf22": dict(dim=2, k=2, n_coarse=(5, 3), levels=4,
+                        env={"SMG_WGF2D_MIN_N": "1", "SMG_WGF2D_SHAPE": "22", "SMG_FUSE3_2D_MAX_N": "0"}),
+    "2d_k3_wgf44": dict(dim=2, k=3, n_coarse=(3, 2), levels=4,
+                        env={"SMG_WGF2D_MIN_N": "1", "SMG_WGF2D_SHAPE": "44", "SMG_FUSE3_2D_MAX_N": "0"}),
     "3d_k3": dict(dim=3, k=3, n_coarse=(2, 2, 3), levels=2),
     # vertex-given (multilinear) cells: interior vertices of the finest mesh
     # moved by up to 0.2 h, coarse levels take the finest vertices
