@@ -104,3 +104,37 @@ def test_dirichlet_entry_points_reject_null_arguments():
     assert lib.smg_lift_dirichlet(None, 0, 0, None, None) == -1
     assert lib.smg_insert_dirichlet(None, 0, 0, None, None) == -1
 
+
+
+def _c_layout(struct, fields, tmp_path):
+    """sizeof and offsetof of a header struct, from a C program built with
+    the host compiler against include/smg.h."""
+    import shutil
+    import subprocess
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no host C compiler")
+    src = tmp_path / "layout.c"
+    lines = ["#include <stddef.h>", "#include <stdio.h>", '#include "smg.h"', "int main(void) {",
+             f'  printf("%zu\\n", sizeof({struct}));']
+    lines += [f'  printf("%zu\\n", offsetof({struct}, {f}));' for f in fields]
+    lines += ["  return 0;", "}"]
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    r = subprocess.run([cc, "-std=c11", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)],
+                       stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True)
+    assert r.returncode == 0, r.stdout
+    out = subprocess.run([str(exe)], stdout=subprocess.PIPE, text=True, check=True).stdout.split()
+    return int(out[0]), [int(v) for v in out[1:]]
+
+
+@pytest.mark.parametrize("struct,cls", [("smg_desc", "SmgDesc"), ("smg_solve_info", "SmgSolveInfo")])
+def test_binding_structs_match_the_header(struct, cls, tmp_path):
+    """The ctypes mirrors of the header's structs (t_setup_ms among the solve
+    fields) have the C layout: size and every field's offset."""
+    from paper_2205_15770_amd import _lib
+    c = getattr(_lib, cls)
+    fields = [f for f, _ in c._fields_]
+    size, offs = _c_layout(struct, fields, tmp_path)
+    assert ctypes.sizeof(c) == size
+    assert [getattr(c, f).offset for f in fields] == offs

@@ -372,6 +372,7 @@ def test_fgmres_solve(name, precision):
     xs = x.cpu().numpy()
     assert np.linalg.norm(b - asm.K @ xs) <= 1.05e-8 * np.linalg.norm(b)
     assert info["iterations"] < 40
+    assert info["t_setup_ms"] > 0.0 and info["t_solve_ms"] > 0.0
     # against the oracle's direct solve (bordered, zero-mean pressure)
     nu = asm.A.shape[0]
     m = np.zeros(len(b))
