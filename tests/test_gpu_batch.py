@@ -33,8 +33,14 @@ def _rhs(mg, seed):
 
 
 @pytest.mark.parametrize("prec", ["f32", "f64"])
-def test_batch_solve_equals_individual_solves(prec):
+@pytest.mark.parametrize("wgf", [False, True])
+def test_batch_solve_equals_individual_solves(prec, wgf, monkeypatch):
+    """wgf: the fused launches of every level on workgroups of 2 x 2 waves
+    (by default only levels of 512 cells per direction), packed through
+    their own launch functor in the batch."""
     from paper_2205_15770_amd import StokesMG, StokesBatch
+    if wgf:
+        monkeypatch.setenv("SMG_WGF2D_MIN_N", "1")
     probs = _problems(prec)
     batch = StokesBatch(probs)
     nl, var = batch.info()
