@@ -10,6 +10,7 @@
 #include "packed.hpp"
 #include "gen_kernel.hpp"
 #include "cell_kernel3d.hpp"
+#include "cell_kernel3d_mfma.hpp"
 #include "engine.hpp"
 #include "ops.hpp"
 #include "setup_kernels.hpp"
@@ -64,6 +65,25 @@ inline int sweep_waves_from_env() {
   const int v = e != nullptr ? std::atoi(e) : 4096;
   return v > 0 ? v : 4096;
 }
+
+// Smallest 3D Q2 level (cells per direction, any direction) whose FP32
+// Chebyshev steps for A run on the matrix-core cell kernel instead of the
+// column sweep: by default none (measured slower than the sweep at 64^3:
+// 78 against 56 us); SMG_MFMA3D_MIN_N sets it.  SMG_MFMA3D_WAVES sets the
+// waves that launch aims at (z chunks).
+inline int mfma3d_min_n_from_env() {
+  const char *e = std::getenv("SMG_MFMA3D_MIN_N");
+  return e != nullptr ? std::atoi(e) : 0;
+}
+inline int mfma3d_waves_from_env() {
+  const char *e = std::getenv("SMG_MFMA3D_WAVES");
+  const int v = e != nullptr ? std::atoi(e) : 2048;
+  return v > 0 ? v : 2048;
+}
+template <class Op>
+struct is_cheb_a_op : std::false_type {};
+template <typename T, bool F, bool L>
+struct is_cheb_a_op<OpChebA<T, F, L>> : std::true_type {};
 
 // 3D general cells: the line-layout cell kernel (1, default) or the one
 // with a lane per quadrature point (0); SMG_GEN3_LINES overrides it.
@@ -144,6 +164,8 @@ class EngineT : public EngineBase {
   int wgf2d_shape = wgf2d_shape_from_env();
   int gen3_lines = gen3_lines_from_env();
   int sweep_waves = sweep_waves_from_env();
+  int mfma3d_min_n = mfma3d_min_n_from_env();
+  int mfma3d_waves = mfma3d_waves_from_env();
   int fuse2d_max_n = fuse2d_max_n_from_env();
   int fuse3_2d_max_n = fuse3_2d_max_n_from_env();
   int plane3d_max_n = plane3d_max_n_from_env();
@@ -353,8 +375,24 @@ class EngineT : public EngineBase {
         else
           hipLaunchKernelGGL((block3d_kernel<K, T, BLK, Op>), dim3(nbb), dim3(64), 0, stream, g3, op);
       } else {
-        const unsigned nb3 = (unsigned)sweep3d_chunks(g3, NF, sweep_waves);
-        hipLaunchKernelGGL((tile3d_kernel<K, T, BLK, Op, 8, 8>), dim3(nb3), dim3(64), 0, stream, g3, op);
+        bool done = false;
+        if constexpr (std::is_same<T, float>::value && BLK == BLK_A && is_cheb_a_op<Op>::value) {
+          // uniform box cells: the cell matrix is shared, 32 cells per
+          // matrix-core product (per-cell viscosity only with gamma rho = 0)
+          if (mfma3d_min_n > 0 && std::max(g.n[0], std::max(g.n[1], g.n[2])) >= mfma3d_min_n &&
+              (g.mu_cell == nullptr || g.gr == 0)) {
+            const unsigned nbm = (unsigned)mfma3d_chunks(g3, mfma3d_waves);
+            if (g.mu_cell != nullptr)
+              hipLaunchKernelGGL((mfma3d_kernel<Op, true>), dim3(nbm), dim3(64), 0, stream, g3, op);
+            else
+              hipLaunchKernelGGL((mfma3d_kernel<Op, false>), dim3(nbm), dim3(64), 0, stream, g3, op);
+            done = true;
+          }
+        }
+        if (!done) {
+          const unsigned nb3 = (unsigned)sweep3d_chunks(g3, NF, sweep_waves);
+          hipLaunchKernelGGL((tile3d_kernel<K, T, BLK, Op, 8, 8>), dim3(nb3), dim3(64), 0, stream, g3, op);
+        }
       }
     }
     check_launch();

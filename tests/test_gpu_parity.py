@@ -60,6 +60,15 @@ CONFIGS = {
                         env={"SMG_WGF2D_MIN_N": "1", "SMG_WGF2D_SHAPE": "22", "SMG_FUSE3_2D_MAX_N": "0"}),
     "2d_k3_wgf44": dict(dim=2, k=3, n_coarse=(3, 2), levels=4,
                         env={"SMG_WGF2D_MIN_N": "1", "SMG_WGF2D_SHAPE": "44", "SMG_FUSE3_2D_MAX_N": "0"}),
+    # FP32 Chebyshev steps for A on the matrix-core cell kernel (by default
+    # levels of at least 64 cells per direction) on every level: uniform
+    # viscosity with gamma rho != 0 (one cell matrix), and per-cell viscosity
+    # with gamma = 0 (the viscosity scales the cell input); ragged 17 x 9
+    # column tiles in x and y
+    "3d_k2_mfma": dict(dim=3, k=2, n_coarse=(5, 3, 2), levels=3, percell=False,
+                       env={"SMG_MFMA3D_MIN_N": "1", "SMG_BLOCK3D_MAX_N": "0"}),
+    "3d_k2_mfma_mucell": dict(dim=3, k=2, n_coarse=(2, 3, 2), levels=3, gamma=0.0,
+                              env={"SMG_MFMA3D_MIN_N": "1", "SMG_BLOCK3D_MAX_N": "0"}),
     "3d_k3": dict(dim=3, k=3, n_coarse=(2, 2, 3), levels=2),
     # vertex-given (multilinear) cells: interior vertices of the finest mesh
     # moved by up to 0.2 h, coarse levels take the finest vertices
@@ -84,14 +93,16 @@ def _setup(name, c_p=0.0, kA=1, kS=1, schur="d", m=2, cycle=1, percell=True):
     cfg = CONFIGS[name]
     dim, k, L = cfg["dim"], cfg["k"], cfg["levels"]
     n_f = [c * 2 ** (L - 1) for c in cfg["n_coarse"]]
+    percell = percell and cfg.get("percell", True)
+    gamma = cfg.get("gamma", PHYS["gamma"])
     mu_cell = si.uniform(int(np.prod(n_f)), 17, 0.5, 3.0) if percell else None
     verts = _vertices(name)
     meshes = make_hierarchy(dim, cfg["n_coarse"], L, k, fine_mu=mu_cell, fine_vertices=verts)
-    ora = Multigrid(meshes, mu=1.0, gamma=PHYS["gamma"], rho=PHYS["rho"], c_p=c_p, k_A=kA, k_S=kS,
+    ora = Multigrid(meshes, mu=1.0, gamma=gamma, rho=PHYS["rho"], c_p=c_p, k_A=kA, k_S=kS,
                     schur=schur, smooth_steps=m, cycle_index=cycle)
     with _env(cfg):
         gpu = StokesMG(dim=dim, fe_degree=k, n_coarse=cfg["n_coarse"], n_levels=L, mu=1.0, mu_cell=mu_cell,
-                       gamma=PHYS["gamma"], rho=PHYS["rho"], c_pressure=c_p, cheb_deg_A=kA, cheb_deg_S=kS,
+                       gamma=gamma, rho=PHYS["rho"], c_pressure=c_p, cheb_deg_A=kA, cheb_deg_S=kS,
                        smooth_steps=m, cycle_index=cycle, schur_diag=schur, fine_vertices=verts)
     _cache[key] = (ora, gpu)
     return ora, gpu
