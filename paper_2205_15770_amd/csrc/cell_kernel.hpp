@@ -29,7 +29,9 @@ __device__ __forceinline__ void hand_over_xy(T (&y)[NZ][N][N], int lcx, int lcy,
   for (int z = 0; z < NZ; ++z)
 #pragma unroll
     for (int j = 0; j < N; ++j) {
-      const T r = __shfl_up(y[z][j][N - 1], 1, TX);
+      // x neighbour: lane - 1 (its value is used only where lcx > 0, i.e. by
+      // lanes whose lane - 1 is in the same row of TX lanes)
+      const T r = __shfl_up(y[z][j][N - 1], 1, (TX & (TX - 1)) == 0 ? TX : 64);
       if (lcx > 0) y[z][j][0] += r;
       if (!last_x) y[z][j][N - 1] = 0;
     }

@@ -2,12 +2,13 @@
 // K = [A B^T; B -C] on axis-aligned box cells in 3D (Sec. 3.1: K x =
 // sum_tau P_tau K_tau P_tau^T x, cell matrices by sum factorisation).
 //
-// Work decomposition (gfx950): one wave64 per (tile of 8 x 8 cell columns,
-// z chunk, output field).  Lane l holds the cell column (l % 8, l / 8) of the
-// tile and sweeps the cells of its column through the chunk in z.  A tile
-// owns 7 x 7 columns; lane column 0 and lane row 0 are halo columns, and the
-// cell layer below a chunk is a halo layer: their cell results are computed
-// only to hand them over.  No LDS, no barriers, no atomics; every output
+// Work decomposition (gfx950): one wave64 per (tile of TX x TY cell columns,
+// z chunk, output field); the library uses 9 x 7 (lane 63 idle).  Lane l
+// holds the cell column (l % TX, l / TX) of the tile and sweeps the cells of
+// its column through the chunk in z.  A tile owns (TX - 1) x (TY - 1)
+// columns; lane column 0 and lane row 0 are halo columns, and the cell layer
+// below a chunk is a halo layer: their cell results are computed only to
+// hand them over.  No LDS, no barriers, no atomics; every output
 // entry is written once, from complete cell sums.
 //
 //   velocity wave (field c < 3):  y_c = (A u)_c + (B^T p)_c
@@ -155,14 +156,22 @@ struct Sweep {
   bool last_x, last_y;
 };
 
-// Launch shape of the column sweep (host): 8 x 8 column tiles owning 7 x 7
-// columns, NF output fields, the z extent cut into chunks of >= 2 cells so
-// that the launch has about `waves` waves when the level is large enough.
-// Sets g.tiles and returns the number of blocks (one wave each).
-template <typename T>
+// Column-sweep tile used by the library: 9 x 7 lanes (63 of the 64) owning
+// 8 x 6 cell columns.  On the power-of-two levels of a box hierarchy 8 owned
+// columns divide the level in x; 8 x 8 lanes owning 7 x 7 divide nothing
+// (64^2: 10 x 10 tiles, 6400 computed columns for 4096, against 8 x 11
+// tiles, 5632).
+constexpr int SW_TX = 9, SW_TY = 7;
+
+// Launch shape of the column sweep (host): TX x TY column tiles owning
+// (TX - 1) x (TY - 1) columns, NF output fields, the z extent cut into
+// chunks of >= 2 cells so that the launch has about `waves` waves when the
+// level is large enough.  Sets g.tiles and returns the number of blocks (one
+// wave each).
+template <int TX, int TY, typename T>
 inline int sweep3d_chunks(Geo3<T> &g, int NF, int waves) {
-  g.tiles[0] = (g.n[0] + 6) / 7;
-  g.tiles[1] = (g.n[1] + 6) / 7;
+  g.tiles[0] = (g.n[0] + TX - 2) / (TX - 1);
+  g.tiles[1] = (g.n[1] + TY - 2) / (TY - 1);
   const int cols = g.tiles[0] * g.tiles[1] * NF;
   int nzc = (waves + cols - 1) / cols;
   const int zmax = (g.n[2] + 1) / 2;
@@ -194,7 +203,9 @@ __host__ __device__ inline bool sweep3d_decode(const Geo3<T> &g, int NF, int b, 
   s.lcy = lane / TX;
   cx = tx * (TX - 1) - 1 + s.lcx;
   cy = ty * (TY - 1) - 1 + s.lcy;
-  s.col_owner = cx >= 0 && cx < g.n[0] && cy >= 0 && cy < g.n[1] && s.lcx > 0 && s.lcy > 0;
+  // (lanes past TX * TY, if any, compute a column outside the tile and own
+  // nothing)
+  s.col_owner = cx >= 0 && cx < g.n[0] && cy >= 0 && cy < g.n[1] && s.lcx > 0 && s.lcy > 0 && s.lcy < TY;
   s.last_x = cx == g.n[0] - 1;
   s.last_y = cy == g.n[1] - 1;
   return true;
@@ -1097,7 +1108,7 @@ constexpr int tile3d_waves_per_eu() {
 template <int K, typename T, int BLK, class Op, int TX, int TY>
 __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(tile3d_waves_per_eu<Op, T>())))
 tile3d_kernel(const Geo3<T> g, const Op op) {
-  static_assert(TX * TY == 64, "one wave per tile");
+  static_assert(TX * TY <= 64, "one wave per tile");
   constexpr bool OUT_U = (BLK & (BLK_A | BLK_MASS | BLK_BT)) != 0;
   constexpr bool OUT_P = (BLK & (BLK_B | BLK_C)) != 0;
   constexpr int NFIELD = (OUT_U ? 3 : 0) + (OUT_P ? 1 : 0);

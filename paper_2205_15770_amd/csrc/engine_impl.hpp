@@ -341,7 +341,7 @@ class EngineT : public EngineBase {
       // Q3-Q2 in 3D always runs on the vertex-given cell kernel (gen_op)
       throw Error{SMG_EUNSUPPORTED, "3D Q3-Q2 box kernel"};
     } else {
-      // 8 x 8 cell columns per wave, one wave per output field; the z extent
+      // SW_TX x SW_TY cell columns per wave, one wave per output field; the z extent
       // is cut into chunks so that the launch has about sweep_waves waves
       // (4096: four per SIMD) when the level is large enough, chunks of >= 2
       // cells.
@@ -390,8 +390,8 @@ class EngineT : public EngineBase {
           }
         }
         if (!done) {
-          const unsigned nb3 = (unsigned)sweep3d_chunks(g3, NF, sweep_waves);
-          hipLaunchKernelGGL((tile3d_kernel<K, T, BLK, Op, 8, 8>), dim3(nb3), dim3(64), 0, stream, g3, op);
+          const unsigned nb3 = (unsigned)sweep3d_chunks<SW_TX, SW_TY>(g3, NF, sweep_waves);
+          hipLaunchKernelGGL((tile3d_kernel<K, T, BLK, Op, SW_TX, SW_TY>), dim3(nb3), dim3(64), 0, stream, g3, op);
         }
       }
     }

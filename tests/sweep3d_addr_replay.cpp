@@ -18,6 +18,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <string>
+#include <vector>
 
 #include "cell_kernel3d.hpp"
 
@@ -87,14 +88,16 @@ int main(int argc, char **argv) {
       // ---------------- column sweep (tile3d_kernel)
       {
         Geo3<double> gs = g;
-        const int nb = sweep3d_chunks(gs, NF, sweep_waves);
+        const int nb = sweep3d_chunks<SW_TX, SW_TY>(gs, NF, sweep_waves);
+        // owner stores per node: every node of an output field exactly once
+        std::vector<uint8_t> ucount(OUT_U ? 3 * Nv : 0), pcount(OUT_P ? Np : 0);
         for (int blk = 0; blk < nb; ++blk) {
           const int b = xcd_contiguous_tile(blk, nb);
           for (int lane = 0; lane < 64; ++lane) {
             int field;
             Sweep s;
             int cx, cy;
-            if (!sweep3d_decode<8, 8>(gs, NF, b, lane, field, s, cx, cy)) continue;
+            if (!sweep3d_decode<SW_TX, SW_TY>(gs, NF, b, lane, field, s, cx, cy)) continue;
             const Column3D<KK, double> col(gs, cx, cy);
             const bool vel = OUT_U && field < 3;
             const int comp = vel ? field : 0;
@@ -136,7 +139,12 @@ int main(int argc, char **argv) {
                         const bool own = x < KK && y < KK && z < KK;
                         const bool high = !own && !((x == KK && !s.last_x) || (y == KK && !s.last_y) ||
                                                     (z == KK && !last_z));
-                        if (own || high) B.u(col.u_at(comp, cl, x, y, z), "sweep fetch/store u");
+                        if (own || high) {
+                          const BOff o = col.u_at(comp, cl, x, y, z);
+                          B.u(o, "sweep fetch/store u");
+                          const uint64_t idx = ((uint64_t)o.v + o.c) / 8;
+                          if (idx < ucount.size() && ucount[idx] < 255) ++ucount[idx];
+                        }
                       }
                 }
               } else {
@@ -170,12 +178,25 @@ int main(int argc, char **argv) {
                       for (int x = 0; x < NP; ++x) {
                         const bool main = x < KK - 1 && y < KK - 1 && z < KK - 1;
                         const bool edge = ((x < KK - 1) | s.last_x) & ((y < KK - 1) | s.last_y) & ((z < KK - 1) | last_z);
-                        if (main || edge) B.p(col.p_at(cl, x, y, z), "sweep fetch/store p");
+                        if (main || edge) {
+                          const BOff o = col.p_at(cl, x, y, z);
+                          B.p(o, "sweep fetch/store p");
+                          const uint64_t idx = ((uint64_t)o.v + o.c) / 8;
+                          if (idx < pcount.size() && pcount[idx] < 255) ++pcount[idx];
+                        }
                       }
                 }
               }
             }
           }
+        }
+        long miss = 0, twice = 0;
+        for (const uint8_t c : ucount) miss += c == 0, twice += c > 1;
+        for (const uint8_t c : pcount) miss += c == 0, twice += c > 1;
+        if (miss || twice) {
+          std::fprintf(stderr, "sweep ownership (NF %d): %ld nodes never stored, %ld stored more than once\n", NF,
+                       miss, twice);
+          B.errors += miss + twice;
         }
       }
       // ---------------- cell block and cell planes (block3d_kernel, block3d_plane_kernel)

@@ -4,7 +4,8 @@ the FP64 CPU oracle on the same seeded inputs.
 Sizes: meshes the oracle assembles in seconds that still span several tiles
 with ragged last tiles in every direction (2D wave tiles own 7 x 7 cells, or
 5 x 5 / 3 x 3 in the two- and three-stage fused launches; 3D column sweeps
-own 7 x 7 cell columns, cell blocks 3 x 3 x 3 cells).  Tolerances:
+own 8 x 6 cell columns, cell blocks 3 x 3 x 3 cells, the matrix-core cell
+kernel 16 x 8 columns).  Tolerances:
   * FP64 operator applications: relative 2-norm error <= 1e-12 (a few hundred
     roundings of O(1) terms per entry on random inputs), and componentwise
     max_i |y - y_o|_i / (|K| |x|)_i <= 1e-12 (1e-4 in FP32), which is not
