@@ -37,6 +37,9 @@ CONFIGS = {
     # the same levels through the column-sweep kernel (by default levels of at
     # most 32 cells per direction take the one-cell-per-lane block kernel)
     "3d_k2_sweep": dict(dim=3, k=2, n_coarse=(2, 3, 2), levels=3, env={"SMG_BLOCK3D_MAX_N": "0"}),
+    # the column sweep's tiles own 8 x 6 columns: a level of 10 x 14 x 6 cells
+    # leaves ragged last tiles in x and y (and two z chunks)
+    "3d_k2_sweep_ragged": dict(dim=3, k=2, n_coarse=(5, 7, 3), levels=2, env={"SMG_BLOCK3D_MAX_N": "0"}),
     # levels of at most 16 cells per direction use one wave per output plane
     # of the cell block by default; the same levels with one wave per block:
     "3d_k2_cellblock": dict(dim=3, k=2, n_coarse=(2, 3, 2), levels=3, env={"SMG_PLANE3D_MAX_N": "0"}),
