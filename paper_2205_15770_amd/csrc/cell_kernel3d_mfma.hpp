@@ -2,7 +2,7 @@
 // operator on axis-aligned box cells in 3D, Q2 (Sec. 3.1: A u =
 // sum_tau P_tau A_tau P_tau^T u, evaluated cell by cell).  A variant of the
 // FP32 Chebyshev steps for A, selected by level size (off by default: at
-// 64^3 it takes 78 us against 56 us for the column sweep).
+// 64^3 it takes 68 us against 54 us for the column sweep).
 //
 // On a box level all cells have the widths (h_x, h_y, h_z), so every cell has
 // the same 27 x 27 matrix per velocity component,
@@ -104,6 +104,120 @@ __host__ __device__ inline bool mfma3d_decode(const Geo3<T> &g, int b, Mfma3DTil
   return t.z_lo < t.z_hi;
 }
 
+// Per-lane addressing of mfma3d_kernel: the patch-plane loads, the LDS
+// indices of the matrix-core operands, the staging slots and the node
+// gathers, and the owned output nodes.  Host and device: the kernel and the
+// host replay of its accesses use this same arithmetic.
+struct Mfma3DLane {
+  int lane, hi, n;
+  int gx0, gy0;          // global node of patch node (0, 0)
+  int vd0, vd1, vd2;     // velocity lattice extents
+  int ox_hi, oy_hi;      // owned nodes: x < ox_hi, y < oy_hi (from patch node (2, 2))
+  uint32_t plane_bytes;  // bytes of one lattice plane (one component)
+  uint32_t comp_base;    // byte offset of the tile's velocity component
+  // gather, x part: node x = 2 + n is node kx0 (1 or 2) of cell i0 and, for
+  // even x inside the computed cells (xe), node 0 of cell i0 + 1
+  int xp, xph;
+  bool xe;
+  bool xok, xdir;        // x = gx0 + 2 + n owned / on the boundary
+  uint32_t lane_off;     // byte offset of the lane's (clamped) lattice column x
+  __host__ __device__ Mfma3DLane(const Geo3<float> &g, const Mfma3DTile &t, int lane_) {
+    using namespace mf3;
+    lane = lane_;
+    hi = lane >> 5;
+    n = lane & 31;
+    vd0 = g.vd[0];
+    vd1 = g.vd[1];
+    vd2 = g.vd[2];
+    plane_bytes = 4u * (uint32_t)vd0 * (uint32_t)vd1;
+    comp_base = (uint32_t)t.comp * g.nv_bytes;
+    gx0 = 2 * (OX * t.tx - 1);
+    gy0 = 2 * (OY * t.ty - 1);
+    ox_hi = t.tx == g.tiles[0] - 1 ? vd0 : gx0 + 2 + 2 * OX;
+    oy_hi = t.ty == g.tiles[1] - 1 ? vd1 : gy0 + 2 + 2 * OY;
+    const int i0 = (1 + n) >> 1, kx0 = 2 + n - 2 * i0;
+    xe = kx0 == 2 && i0 + 1 < CX;
+    const int xgl = gx0 + 2 + n;
+    xok = xgl < ox_hi;
+    xdir = xgl == 0 || xgl == vd0 - 1;
+    lane_off = comp_base + 4u * (uint32_t)(xgl < vd0 ? xgl : vd0 - 1);
+    // staging offset of (cell i0 + 17 j0, node kx0 + 3 ky0): rows y = 2 + 2 j
+    // (hi = 0: j0 = j, ky0 = 2) and y = 3 + 2 j (hi = 1: j0 = j + 1, ky0 = 1)
+    // differ by 17 SST - 3
+    xp = i0 * SST + kx0;
+    xph = xp + hi * (CX * SST - 3);
+  }
+  // patch-plane node q = lane + 64 j (x fastest over 35): byte offset of its
+  // lattice column (clamped into the lattice), inside / on the x-y boundary
+  __host__ __device__ uint32_t plane_node(int j, bool &inside, bool &bnd) const {
+    using namespace mf3;
+    const int q = lane + 64 * j;
+    const int x = q % PX, y = q / PX;
+    const int gx = gx0 + x, gy = gy0 + y;
+    inside = q < PL && gx >= 0 && gx < vd0 && gy >= 0 && gy < vd1;
+    bnd = gx == 0 || gx == vd0 - 1 || gy == 0 || gy == vd1 - 1;
+    const int cgx = gx < 0 ? 0 : (gx >= vd0 ? vd0 - 1 : gx);
+    const int cgy = gy < 0 ? 0 : (gy >= vd1 ? vd1 - 1 : gy);
+    return 4u * ((uint32_t)cgx + (uint32_t)vd0 * (uint32_t)cgy);
+  }
+  // LDS index (input planes) of the A operand of batch b, step s: input node
+  // 2 s + hi of cell n of the batch (padding rows read cell 0)
+  __host__ __device__ int a_index(int b, int s) const {
+    using namespace mf3;
+    const int c = 32 * b + n;
+    return cell_base(c < NCELL ? c : 0) + node_off(2 * s) + hi * (node_off(2 * s + 1) - node_off(2 * s));
+  }
+  // LDS staging index of result register r of batch b: node n of the cell
+  // in row 8 (r / 4) + 4 hi + r % 4 of the batch (padding rows and columns
+  // land in unused slots)
+  __host__ __device__ int stg_index(int b, int r) const {
+    using namespace mf3;
+    return n + 4 * SST * hi + SST * (32 * b + 8 * (r / 4) + (r % 4));
+  }
+  // owned-node slot j < 9 of a plane: node x = 2 + n, y = 2 + 2 j + hi of
+  // the patch (the last row pair has no hi = 1 node: those lanes own
+  // nothing there and read the hi = 0 node's staging and input).  The four
+  // staging indices of its (up to) four cells in z plane kz and which of
+  // them contribute, in summation order.
+  __host__ __device__ void gather_index(int j, int kz, int (&a)[4], bool (&use)[4]) const {
+    using namespace mf3;
+    const int a00 = (j < NE - 1 ? xph : xp) + CX * j * SST + 6 + 9 * kz;
+    const bool ye = hi == 0 && j + 1 < CY;
+    a[0] = a00;
+    a[1] = a00 + SST - 2;
+    a[2] = a00 + CX * SST - 6;
+    a[3] = a00 + (CX + 1) * SST - 8;
+    use[0] = true;
+    use[1] = xe;
+    use[2] = ye;
+    use[3] = xe && ye;
+  }
+  // LDS index (input planes) of slot j's node in z plane zp
+  __host__ __device__ int vin_index(int zp, int j) const {
+    using namespace mf3;
+    return zp * PL + (2 + 2 * j + (j < NE - 1 ? hi : 0)) * PX + 2 + n;
+  }
+  // slot j < 9: global address in plane byte offset zoff (clamped into the
+  // lattice), owned, on the x-y boundary
+  __host__ __device__ void slot(int j, uint32_t zoff, BOff &gi, bool &ok, bool &dir) const {
+    using namespace mf3;
+    const int gy = gy0 + 2 + 2 * j + hi;
+    ok = xok && gy < oy_hi && !(j == NE - 1 && hi);
+    dir = xdir || gy == 0 || gy == vd1 - 1;
+    gi = BOff{lane_off + zoff + 4u * (uint32_t)vd0 * (uint32_t)(gy < vd1 ? gy : vd1 - 1), 0};
+  }
+  // slot 9: the patch column x = 34 (the domain's high x face, last tile
+  // only), y = 2 + lane: always a Dirichlet row
+  __host__ __device__ void slot9(uint32_t zoff, BOff &gi, bool &ok) const {
+    using namespace mf3;
+    const int gx = gx0 + PX - 1, gy = gy0 + 2 + lane;
+    ok = lane < PY - 2 && gx < ox_hi && gy < oy_hi;
+    gi = BOff{comp_base + zoff + 4u * ((uint32_t)(gx < vd0 ? gx : vd0 - 1) +
+                                       (uint32_t)vd0 * (uint32_t)(gy < vd1 ? gy : vd1 - 1)),
+              0};
+  }
+};
+
 typedef float mf3_v16 __attribute__((ext_vector_type(16)));
 
 // Entry (n, k) of the cell matrix, n = output node (its 1D rows of Kr and Mr
@@ -147,26 +261,19 @@ __global__ void __launch_bounds__(64) mfma3d_kernel(const Geo3<float> g, const O
   Mfma3DTile t;
   if (!mfma3d_decode(g, xcd_contiguous_tile(blockIdx.x, gridDim.x), t)) return;  // whole wave
   const int lane = threadIdx.x;
-  const int hi = lane >> 5, n = lane & 31;
-  const int vd0 = g.vd[0], vd1 = g.vd[1], vd2 = g.vd[2];
-  const uint32_t plane_bytes = 4u * (uint32_t)vd0 * (uint32_t)vd1;
-  const uint32_t comp_base = (uint32_t)t.comp * g.nv_bytes;
+  const Mfma3DLane L(g, t, lane);
+  const int hi = L.hi, n = L.n;
+  const int vd2 = L.vd2;
+  const uint32_t plane_bytes = L.plane_bytes, comp_base = L.comp_base;
   const int cx0 = OX * t.tx - 1, cy0 = OY * t.ty - 1;  // first computed cell column
-  const int gx0 = 2 * cx0, gy0 = 2 * cy0;              // global node of patch node (0, 0)
 
   // ---- per-lane node addressing of the plane loads: node q = lane + 64 j
   uint32_t off_xy[LPP];
   uint32_t in_bits = 0, bnd_bits = 0;
 #pragma unroll
   for (int j = 0; j < LPP; ++j) {
-    const int q = lane + 64 * j;
-    const int x = q % PX, y = q / PX;
-    const int gx = gx0 + x, gy = gy0 + y;
-    const bool inside = q < PL && gx >= 0 && gx < vd0 && gy >= 0 && gy < vd1;
-    const bool bnd = gx == 0 || gx == vd0 - 1 || gy == 0 || gy == vd1 - 1;
-    const int cgx = gx < 0 ? 0 : (gx >= vd0 ? vd0 - 1 : gx);
-    const int cgy = gy < 0 ? 0 : (gy >= vd1 ? vd1 - 1 : gy);
-    off_xy[j] = 4u * ((uint32_t)cgx + (uint32_t)vd0 * (uint32_t)cgy);
+    bool inside, bnd;
+    off_xy[j] = L.plane_node(j, inside, bnd);
     in_bits |= (inside ? 1u : 0u) << j;
     bnd_bits |= (bnd ? 1u : 0u) << j;
   }
@@ -219,73 +326,30 @@ __global__ void __launch_bounds__(64) mfma3d_kernel(const Geo3<float> g, const O
   }
   __syncthreads();
 
-  // A operand: lane (n, hi) reads input node 2 s + hi of cell n of the
-  // batch (padding rows read cell 0 and are scaled by 0).  Results: lane
-  // (n, hi) of register r of batch b holds node n of the cell in row
-  // 8 (r / 4) + 4 hi + r % 4 of the batch; it goes to staging row (cell) c,
-  // slot n (padding rows and columns land in unused slots).
-  int cbA[NBLK];
-#pragma unroll
-  for (int b = 0; b < NBLK; ++b) cbA[b] = cell_base(32 * b + n < NCELL ? 32 * b + n : 0);
-  const int stg_lane = n + 4 * SST * hi;
-
-  // Owned nodes of a plane, lane (n, hi): slots j < 9 are the nodes
-  // x = 2 + n, y = 2 + 2 j + hi of the patch (x = 2 .. 33, y = 2 .. 18);
-  // slot 9 is the column x = 34 (the domain's high x face, last tile only),
-  // y = 2 + lane.  A node's sum is formed from the staged results of the
-  // (up to) four cells around it in a fixed order; the z = 2 plane's partial
-  // sums are carried in registers to the next layer's z = 0 plane (the same
-  // nodes, the same lanes).
-  const int ox_hi = t.tx == g.tiles[0] - 1 ? vd0 : gx0 + 2 + 2 * OX;
-  const int oy_hi = t.ty == g.tiles[1] - 1 ? vd1 : gy0 + 2 + 2 * OY;
-  // x part (per lane): node x = 2 i0 + kx0 of cell i0 (kx0 = 1 or 2) and,
-  // for even x inside the computed cells, node 0 of cell i0 + 1
-  const int i0 = (1 + n) >> 1, kx0 = 2 + n - 2 * i0;
-  const bool xe = kx0 == 2 && i0 + 1 < CX;
-  const int xgl = gx0 + 2 + n;
-  const bool xok = xgl < ox_hi, xdir = xgl == 0 || xgl == vd0 - 1;
-  const uint32_t lane_off = comp_base + 4u * (uint32_t)(xgl < vd0 ? xgl : vd0 - 1);
-  // staging offset of (cell i0 + 17 j0, node kx0 + 3 ky0): rows y = 2 + 2 j
-  // (hi = 0: j0 = j, ky0 = 2) and y = 3 + 2 j (hi = 1: j0 = j + 1, ky0 = 1)
-  // differ by 17 SST - 3; the last row pair has no hi = 1 node (y = 19), and
-  // its lanes read the hi = 0 node instead (result unused)
-  const int xp = i0 * SST + kx0;
-  const int xph = xp + hi * (CX * SST - 3);
+  // A node's sum is formed from the staged results of the (up to) four
+  // cells around it in a fixed order; the z = 2 plane's partial sums are
+  // carried in registers to the next layer's z = 0 plane (the same nodes,
+  // the same lanes).
   auto gather = [&](int j, int kz) {
-    const int a00 = (j < NE - 1 ? xph : xp) + CX * j * SST + 6 + 9 * kz;
-    const bool ye = hi == 0 && j + 1 < CY;
-    const float v00 = s_stg[a00], v10 = s_stg[a00 + SST - 2];
-    const float v01 = s_stg[a00 + CX * SST - 6], v11 = s_stg[a00 + (CX + 1) * SST - 8];
+    int a[4];
+    bool use[4];
+    L.gather_index(j, kz, a, use);
+    const float v00 = s_stg[a[0]], v10 = s_stg[a[1]], v01 = s_stg[a[2]], v11 = s_stg[a[3]];
     float sum = v00;
-    sum += xe ? v10 : 0.f;
-    sum += ye ? v01 : 0.f;
-    sum += (xe && ye) ? v11 : 0.f;
+    sum += use[1] ? v10 : 0.f;
+    sum += use[2] ? v01 : 0.f;
+    sum += use[3] ? v11 : 0.f;
     return sum;
   };
-  // global node of slot j (j < 9) of a plane: address (clamped into the
-  // lattice), owned, Dirichlet
-  auto slot = [&](int j, uint32_t zoff, BOff &gi, bool &ok, bool &dir) {
-    const int gy = gy0 + 2 + 2 * j + hi;
-    ok = xok && gy < oy_hi && !(j == NE - 1 && hi);
-    dir = xdir || gy == 0 || gy == vd1 - 1;
-    gi = BOff{lane_off + zoff + 4u * (uint32_t)vd0 * (uint32_t)(gy < vd1 ? gy : vd1 - 1), 0};
-  };
-  auto slot9 = [&](uint32_t zoff, BOff &gi, bool &ok) {
-    const int gx = gx0 + PX - 1, gy = gy0 + 2 + lane;
-    ok = lane < PY - 2 && gx < ox_hi && gy < oy_hi;
-    gi = BOff{comp_base + zoff + 4u * ((uint32_t)(gx < vd0 ? gx : vd0 - 1) +
-                                       (uint32_t)vd0 * (uint32_t)(gy < vd1 ? gy : vd1 - 1)),
-              0};
-  };
   // the functor's inputs and the unmasked value (the Dirichlet rows' result)
-  // of the ten slots of a plane
+  // of the ten owned-node slots of a plane
   auto fetch_plane = [&](uint32_t zoff, typename Op::Pre (&pre)[NE + 1], float (&rw)[NE + 1]) {
 #pragma unroll
     for (int j = 0; j <= NE; ++j) {
       BOff gi;
       bool ok, dir;
-      if (j < NE) slot(j, zoff, gi, ok, dir);
-      else slot9(zoff, gi, ok);
+      if (j < NE) L.slot(j, zoff, gi, ok, dir);
+      else L.slot9(zoff, gi, ok);
       pre[j] = op.fetch_u(gi);
       rw[j] = op.load_u(gi);
     }
@@ -296,17 +360,16 @@ __global__ void __launch_bounds__(64) mfma3d_kernel(const Geo3<float> g, const O
     for (int j = 0; j < NE; ++j) {
       BOff gi;
       bool ok, dir;
-      slot(j, zoff, gi, ok, dir);
+      L.slot(j, zoff, gi, ok, dir);
       dir |= zb;
-      // (the last row pair has no hi = 1 node: its lanes read row 18, unused)
-      const float vin = s_in[zp * PL + (2 + 2 * j + (j < NE - 1 ? hi : 0)) * PX + 2 + n];
+      const float vin = s_in[L.vin_index(zp, j)];
       // Dirichlet rows: the functor gets the unmasked input as both the
       // operator result and the input (identity row of A)
       if (ok) op.store_u(gi, dir ? rw[j] : sum[j], dir ? rw[j] : vin, dir, pre[j]);
     }
     BOff gi;
     bool ok;
-    slot9(zoff, gi, ok);
+    L.slot9(zoff, gi, ok);
     if (ok) op.store_u(gi, rw[NE], rw[NE], true, pre[NE]);
   };
 
@@ -343,15 +406,14 @@ __global__ void __launch_bounds__(64) mfma3d_kernel(const Geo3<float> g, const O
       float a[14];
 #pragma unroll
       for (int s = 0; s < 14; ++s) {
-        const int k0 = node_off(2 * s), d = node_off(2 * s + 1) - node_off(2 * s);
-        a[s] = s_in[cbA[b] + k0 + hi * d];
+        a[s] = s_in[L.a_index(b, s)];
         if (MUC || 32 * b + 31 >= NCELL) a[s] *= sc[b];
       }
       mf3_v16 acc = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
 #pragma unroll
       for (int s = 0; s < 14; ++s) acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a[s], Bop[s], acc, 0, 0, 0);
 #pragma unroll
-      for (int r = 0; r < 16; ++r) s_stg[stg_lane + SST * (32 * b + 8 * (r / 4) + (r % 4))] = acc[r];
+      for (int r = 0; r < 16; ++r) s_stg[L.stg_index(b, r)] = acc[r];
     }
     __syncthreads();
 

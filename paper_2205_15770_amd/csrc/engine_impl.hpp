@@ -69,16 +69,17 @@ inline int sweep_waves_from_env() {
 // Smallest 3D Q2 level (cells per direction, any direction) whose FP32
 // Chebyshev steps for A run on the matrix-core cell kernel instead of the
 // column sweep: by default none (measured slower than the sweep at 64^3:
-// 78 against 56 us); SMG_MFMA3D_MIN_N sets it.  SMG_MFMA3D_WAVES sets the
-// waves that launch aims at (z chunks).
+// 68 against 54 us); SMG_MFMA3D_MIN_N sets it.  SMG_MFMA3D_WAVES sets the
+// waves that launch aims at (z chunks; default 960: at one wave per SIMD
+// the 64^3 launch then runs in one round on the 1024 SIMDs).
 inline int mfma3d_min_n_from_env() {
   const char *e = std::getenv("SMG_MFMA3D_MIN_N");
   return e != nullptr ? std::atoi(e) : 0;
 }
 inline int mfma3d_waves_from_env() {
   const char *e = std::getenv("SMG_MFMA3D_WAVES");
-  const int v = e != nullptr ? std::atoi(e) : 2048;
-  return v > 0 ? v : 2048;
+  const int v = e != nullptr ? std::atoi(e) : 960;
+  return v > 0 ? v : 960;
 }
 template <class Op>
 struct is_cheb_a_op : std::false_type {};
