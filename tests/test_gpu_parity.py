@@ -631,6 +631,67 @@ def test_full_size_2d_512_chebyshev_sampled_rows(dtype, tol):
     gpu.close()
 
 
+_CHEB3D_REF = {}
+
+
+def _cheb3d_64_reference(beta):
+    """Sampled rows of sigma Cheb(A, D_A, 1) r on the 64^3 level from the
+    oracle (rows, their stencils' diagonal, the recurrence), computed once for
+    both kernel variants."""
+    if beta in _CHEB3D_REF:
+        return _CHEB3D_REF[beta]
+    from oracle.mesh import BoxMesh
+    from oracle.rows import velocity_stencil, sample_diag_A
+    from oracle.smoother import chebyshev_apply, scaling_constant
+    mesh = BoxMesh(3, (64, 64, 64), 2)
+    vd = 129
+    Nv = vd ** 3
+    nu = 3 * Nv
+    r = si.uniform(nu, 124)
+    rng = np.random.default_rng(9)
+    pts = [(x_, y_, z) for x_ in (1, 15, 16, 17, 31, 32, 33, 64, 127) for y_ in (1, 11, 12, 13, 15, 16, 17, 127)
+           for z in (1, 13, 14, 15, 63, 127)]
+    extra = [c * Nv + vd * vd * z + vd * y_ + x_ for c in range(3) for (x_, y_, z) in pts[::7]]
+    dofs = np.unique(np.concatenate([rng.integers(0, nu, 100), np.arange(0, 10), np.arange(nu - 10, nu), extra]))
+    need = velocity_stencil(mesh, dofs)
+    dinv = np.ones(nu)
+    dinv[need] = 1.0 / sample_diag_A(mesh, need)
+    rin = r.astype(np.float32).astype(np.float64)
+
+    def rows_of_A(v):   # A v on the sampled rows (the only rows the result is read at)
+        out = np.zeros(nu)
+        out[dofs] = sample_Kx(mesh, np.concatenate([v, np.zeros(mesh.n_pnode)]), dofs)
+        return out
+
+    ref = scaling_constant(1) * chebyshev_apply(rows_of_A, dinv, rin, 1, beta)
+    _CHEB3D_REF[beta] = (r, dofs, ref[dofs])
+    return _CHEB3D_REF[beta]
+
+
+@pytest.mark.parametrize("variant", ["column_sweep", "matrix_cores"])
+def test_full_size_3d_64_chebyshev_sampled_rows(variant):
+    """The FP32 Chebyshev application for A (k_A = 1) on the 64^3 level of the
+    3D workload at full size through smg_chebyshev -- on the column sweep (the
+    default) and on the matrix-core cell kernel -- on sampled rows against the
+    oracle's recurrence (with k_A = 1 a row needs only its own row of A d_0).
+    The rows include nodes on the tile and z-chunk boundaries of both kernels
+    and on the domain faces, in all three components.  The eigenvalue bound
+    is set by the test so that both sides use the same one."""
+    from paper_2205_15770_amd import StokesMG
+    beta = 2.6
+    r, dofs, ref = _cheb3d_64_reference(beta)
+    env = {"SMG_MFMA3D_MIN_N": "64" if variant == "matrix_cores" else "0"}
+    with _env({"env": env}):
+        gpu = StokesMG(dim=3, fe_degree=2, n_coarse=(2, 2, 2), n_levels=6, mu=1.0, gamma=0.0)
+    L = 5
+    gpu.set_eigs(L, beta, 1.5)
+    nu, _ = gpu.sizes(L)
+    assert nu == len(r)
+    y = gpu.chebyshev(L, 0, _dev(r, torch.float32)).cpu().numpy().astype(np.float64)
+    assert np.linalg.norm(y[dofs] - ref) / np.linalg.norm(ref) < 2e-5
+    gpu.close()
+
+
 def _sampled_dofs(n, nu, lat_v, extra, seed):
     rng = np.random.default_rng(seed)
     return np.unique(np.concatenate([rng.integers(0, n, 400), np.arange(0, 40), np.arange(n - 40, n),
