@@ -477,7 +477,7 @@ namespace {
 // (3 x 3); the others run one wave per 8 x 8 tile owning 7 x 7 cells.
 // Variant 0 is the solvers' default.
 constexpr int kBatchVariants[][3] = {
-    {512, 512, 128}, {0, 0, 0}, {256, 0, 0}, {256, 256, 0}, {256, 256, 128}, {256, 256, 256}, {512, 256, 64}};
+    {256, 512, 128}, {0, 0, 0}, {256, 0, 0}, {256, 256, 0}, {256, 256, 128}, {256, 256, 256}, {512, 512, 128}};
 constexpr int kNumBatchVariants = (int)(sizeof(kBatchVariants) / sizeof(kBatchVariants[0]));
 
 smg_status check_batch(const smg_batch *b) {
