@@ -73,7 +73,10 @@ typedef enum { SMG_F64 = 0, SMG_F32 = 1 } smg_dtype;
 
 /* Approximations of the Schur-complement diagonal, Sec. 3.3.1:
  *   SMG_SCHUR_D   diag(B diag(A)^-1 B^T)                     (assembled B entries)
- *   SMG_SCHUR_LOC sum_tau diag(B_tau diag(A_tau)^-1 B_tau^T) (cell-local)
+ *   SMG_SCHUR_LOC sum_tau diag(B_tau diag(A_tau)^-1 B_tau^T) (cell-local;
+ *                 Dirichlet columns left out; box cells from the 1D cell
+ *                 matrices, vertex-given cells by quadrature; gradient form
+ *                 only: SMG_EUNSUPPORTED with SMG_FORM_EPS)
  *   SMG_SCHUR_P   diag(M_p)                                  (pressure mass)
  *   SMG_SCHUR_EXACT diag(B A_hat^-1 B^T), A_hat^-1 = sigma Cheb(A, D_A, k_A):
  *                 the diagonal the three choices above approximate; built

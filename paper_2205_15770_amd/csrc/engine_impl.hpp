@@ -11,6 +11,7 @@
 #include "gen_kernel.hpp"
 #include "cell_kernel3d.hpp"
 #include "cell_kernel3d_mfma.hpp"
+#include "gen_setup.hpp"
 #include "engine.hpp"
 #include "ops.hpp"
 #include "setup_kernels.hpp"
@@ -615,6 +616,38 @@ class EngineT : public EngineBase {
       }
       check_launch();
     }
+  }
+
+  // D~_S_loc on vertex-given cells (Sec. 3.3.1): cell contributions by
+  // quadrature, then one fixed-order sum per pressure node (replaces the D~_S
+  // the probing left).
+  void local_schur_diagonal_general(int l) {
+    LevelInfo &I = lv[l];
+    auto g = geom<double>(l);
+    GenGeo<double> gg;
+    std::memset(&gg, 0, sizeof(gg));
+    for (int a = 0; a < 3; ++a) {
+      gg.n[a] = g.n[a];
+      gg.vd[a] = g.vd[a];
+      gg.pd[a] = g.pd[a];
+    }
+    gg.Nv = g.Nv;
+    gg.Np = g.Np;
+    gg.mu = g.mu;
+    gg.gr = g.gr;
+    gg.cp = g.cp;
+    gg.mu_cell = g.mu_cell;
+    gg.verts = g.verts;
+    constexpr int NPN = DIM == 3 ? K * K * K : K * K;
+    const int64_t nt = (int64_t)g.n[0] * g.n[1] * (DIM == 3 ? g.n[2] : 1) * NPN;
+    if (nt > I.N) throw Error{SMG_EINVAL, "local Schur diagonal: cell contributions exceed the work vector"};
+    double *contrib = lz[2];
+    hipLaunchKernelGGL((k_schur_loc_cells<DIM, K>), dim3(grid_for(nt)), dim3(VB), 0, stream, gg, desc.c_pressure,
+                       contrib);
+    check_launch();
+    hipLaunchKernelGGL((k_schur_loc_gather<DIM, K>), dim3(grid_for(I.Np)), dim3(VB), 0, stream, gg,
+                       (const double *)contrib, I.DS);
+    check_launch();
   }
 
   // D_S~ = diag(B A_hat^-1 B^T) (+ c_p diag(M_p)), A_hat^-1 = sigma Cheb(A, D_A, k_A)
@@ -1703,6 +1736,7 @@ class EngineT : public EngineBase {
       auto g = geom<double>(l);
       if (general) {
         probe_diagonals(l);
+        if (desc.schur_diag == SMG_SCHUR_LOC) local_schur_diagonal_general(l);
       } else {
         hipLaunchKernelGGL((k_diag_A<DIM, K>), dim3(grid_for(I.Nv)), dim3(VB), 0, stream, g, I.DA);
         check_launch();

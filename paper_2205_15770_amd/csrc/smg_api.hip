@@ -149,8 +149,8 @@ smg_status validate(const smg_desc *d) {
   if (d->precision != SMG_PRECOND_F64 && d->precision != SMG_PRECOND_F32) return fail(SMG_EINVAL, "precision must be 0 or 1");
   if (d->fgmres_restart < 1 || d->fgmres_restart > 200) return fail(SMG_EINVAL, "fgmres_restart must be in [1, 200]");
   if (d->form != SMG_FORM_GRAD && d->form != SMG_FORM_EPS) return fail(SMG_EINVAL, "form must be 0 (grad) or 1 (eps)");
-  if ((d->fine_vertices || d->form == SMG_FORM_EPS) && d->schur_diag == SMG_SCHUR_LOC)
-    return fail(SMG_EUNSUPPORTED, "the local Schur diagonal is built for box cells and the gradient form only");
+  if (d->form == SMG_FORM_EPS && d->schur_diag == SMG_SCHUR_LOC)
+    return fail(SMG_EUNSUPPORTED, "the local Schur diagonal is built for the gradient form only");
   if (d->mu_cell) {
     double nf = 1.0;
     for (int a = 0; a < d->dim; ++a) nf *= (double)d->n_coarse[a] * std::ldexp(1.0, d->n_levels - 1);

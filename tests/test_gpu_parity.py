@@ -211,8 +211,6 @@ def test_residual_and_blocks(name):
 @pytest.mark.parametrize("name", list(CONFIGS))
 @pytest.mark.parametrize("schur", ["d", "loc", "p", "exact"])
 def test_diagonals(name, schur):
-    if CONFIGS[name].get("pert") and schur == "loc":
-        pytest.skip("the local Schur diagonal is built for box cells only (SMG_EUNSUPPORTED)")
     ora, gpu = _setup(name, schur=schur, c_p=0.2)
     # the exact diagonal goes through A_hat^-1, whose Chebyshev coefficients
     # depend on each side's own Lanczos estimate of beta_A
