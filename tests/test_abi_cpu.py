@@ -92,7 +92,7 @@ def test_unsupported_combinations_rejected_without_device():
     d = _lib.SmgDesc()
     lib.smg_desc_default(ctypes.byref(d))
     d.form = _lib.SMG_FORM_EPS
-    d.schur_diag = _lib.SMG_SCHUR_LOC        # needs box cells and the gradient form
+    d.schur_diag = _lib.SMG_SCHUR_LOC        # built for the gradient form only
     h = ctypes.c_void_p()
     assert lib.smg_create(ctypes.byref(d), ctypes.byref(h)) == -6
     assert h.value is None
