@@ -208,6 +208,35 @@ def test_local_schur_diagonal_matches_hand_derivation():
         assert np.abs(schur_diagonal(asm, "d") - ref).max() > 0.1 * np.abs(ref).max()
 
 
+def test_local_schur_diagonal_rotation_and_scaling_invariance():
+    """D~_S_loc (Sec. 3.3.1) on cells given by their vertices: rotating and
+    translating a mesh leaves every entry unchanged (sum_c (psi_i, d_c phi_j)^2
+    and |grad phi_j|^2 are rotation invariant), and scaling it by s with no
+    mass term multiplies every entry by s^d.  A Jacobian used untransposed
+    or its determinant dropped breaks one of the two."""
+    rng = np.random.default_rng(5)
+    for d, n, ang in ((2, (3, 2), 0.7), (3, (2, 2, 1), 0.4)):
+        if d == 2:
+            R = np.array([[np.cos(ang), -np.sin(ang)], [np.sin(ang), np.cos(ang)]])
+        else:
+            ax = np.array([1.0, 2.0, 2.0]) / 3.0
+            Kx = np.array([[0, -ax[2], ax[1]], [ax[2], 0, -ax[0]], [-ax[1], ax[0], 0]])
+            R = np.eye(3) + np.sin(ang) * Kx + (1 - np.cos(ang)) * Kx @ Kx
+        mu = rng.uniform(0.5, 3.0, int(np.prod(n)))
+        hi = [1.5, 1.0, 0.75][:d]
+        base = BoxMesh(d, n, 2, lo=[0.0] * d, hi=hi, mu_cell=mu)
+        ref = schur_diagonal(Assembled(base, gamma=2.0, rho=1.0), "loc")
+        V = base.vertices @ R.T + 0.3
+        rot = BoxMesh(d, n, 2, vertices=V, mu_cell=mu)
+        D = schur_diagonal(Assembled(rot, gamma=2.0, rho=1.0), "loc")
+        assert np.abs(D - ref).max() <= 1e-13 * np.abs(ref).max()
+        s = 1.7
+        ref0 = schur_diagonal(Assembled(base), "loc")
+        big = BoxMesh(d, n, 2, vertices=s * V, mu_cell=mu)
+        D0 = schur_diagonal(Assembled(big), "loc")
+        assert np.abs(D0 - s ** d * ref0).max() <= 1e-13 * np.abs(s ** d * ref0).max()
+
+
 def test_schur_diagonal_choices_are_spectrally_equivalent():
     # the three choices of Sec. 3.3.1 are all ~ diag(M_p) (their analysis)
     for n in (4, 8, 16):
